@@ -1,0 +1,267 @@
+/*
+ * ph.h -- C ABI of the MI355X parametric H^2-matrix library (online stage).
+ *
+ * Method: arxiv 2511.03109, "Parametric Hierarchical Matrix Approximations to
+ * Kernel Matrices".  Problem statement (Sec. 1): points X = (x_i) in a box
+ * B = [alpha, beta]^d, a parametric kernel kappa(x, y; theta), theta in a
+ * parameter box Theta.  Offline, a parametric H^2-matrix K~(theta) is built over
+ * Theta; online, for one theta, it is instantiated with no kernel evaluations and
+ * applied in an H^2 matrix-vector product.
+ *
+ * Conventions
+ *  - Every function returns an int status: PH_OK (0) or a negative PH_E* code.
+ *    The message of the last failure on the calling thread is ph_last_error().
+ *    No C++ exception crosses this interface.
+ *  - Handles (ph_tree, ph_model, ph_inst) are opaque.  A model keeps what it needs
+ *    of its tree and an instance keeps its model alive (reference counting), so
+ *    the *_free functions may be called in any order; they accept NULL.
+ *  - "Host" pointers are ordinary CPU memory, "device" pointers are HIP device
+ *    memory of the current device.  Streams are hipStream_t passed as void*
+ *    (NULL = the null stream).  Device work is stream-ordered and asynchronous;
+ *    a kernel fault surfaces at the caller's next synchronisation.
+ *  - Matrices are column-major (MATLAB order, Sec. 2.1 "Reshape Command"); multi-
+ *    indices are flattened little-endian (first index fastest).
+ *  - Tree order: the order of points after the cluster-tree partition (leaves in
+ *    breadth-first order, each leaf keeping the original order of its points).
+ */
+#ifndef PH_H
+#define PH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------------- */
+enum {
+  PH_OK = 0,
+  PH_EINVAL = -1,        /* bad argument (NULL pointer, size, NaN, point outside the box) */
+  PH_EDOMAIN = -2,       /* theta outside the parameter box Theta */
+  PH_ENOMEM = -3,        /* host or device allocation failed */
+  PH_EHIP = -4,          /* a HIP runtime call failed */
+  PH_ESTATE = -5,        /* handle used in a state that does not allow the call */
+  PH_EUNSUPPORTED = -6   /* valid but not supported combination (kernel, d, d_theta, dtype) */
+};
+
+/* ---- kernels ---------------------------------------------------------------------
+ * Closed-form stationary, symmetric kernels; r = |x - y|_2.
+ *   GAUSSIAN        exp(-r^2 / (2 l^2))                          d_theta = 1, theta = (l)
+ *   MATERN32        (1 + sqrt(3) r / l) exp(-sqrt(3) r / l)       d_theta = 1
+ *   MATERN12        exp(-r / l)  (the paper's exponential E)     d_theta = 1
+ *   ANISO_GAUSSIAN  exp(-sum_k (x_k - y_k)^2 / (2 l_k^2))         d_theta = d (d <= 2)
+ *   POLY_TEST       theta^2 r^2 + theta (test kernel; reproduced exactly by p >= 3)
+ *   POLY2_TEST      theta_1 r^2 + theta_2^2 (test kernel, d_theta = 2)
+ */
+typedef enum {
+  PH_KERNEL_GAUSSIAN = 0,
+  PH_KERNEL_MATERN32 = 1,
+  PH_KERNEL_MATERN12 = 2,
+  PH_KERNEL_ANISO_GAUSSIAN = 3,
+  PH_KERNEL_POLY_TEST = 4,
+  PH_KERNEL_POLY2_TEST = 5
+} ph_kernel;
+
+/* Arithmetic of an instance.  PH_F64: FP64 storage and arithmetic, I/O in double.
+ * PH_F32: FP32 storage of the instantiated blocks, FP32 arithmetic, I/O in float. */
+typedef enum { PH_F64 = 0, PH_F32 = 1 } ph_dtype;
+
+typedef struct ph_tree ph_tree;
+typedef struct ph_model ph_model;
+typedef struct ph_inst ph_inst;
+
+/* ---- cluster tree and block cluster tree ------------------------------------------
+ * Sec. 3.2 and Alg. ConstructClusterTree: uniform 2^d-ary subdivision of the box
+ * [lo, hi]^d down to level l_max.  A point with x_k <= midpoint goes to the lower
+ * half of axis k; children are numbered by the little-endian child id
+ * sum_k b_k 2^(k-1) (b_k = 1 for the upper half); children holding no point are
+ * not created.  Node ids are breadth-first (level, parent id, child id).
+ * Sec. 3.3 and Alg. ConstructBlockClusterTree: starting from root x root, an
+ * inadmissible pair whose nodes both have children is split into all child pairs;
+ * leaf pairs are far (admissible) or near.  Admissibility (eq. "admissible"),
+ * max(diam B_s, diam B_t) <= eta dist(B_s, B_t), is evaluated exactly in integer
+ * arithmetic on the box indices, with equality admissible; eta^2 is given as the
+ * rational eta2_num / eta2_den.  Far blocks are grouped into translation classes
+ * keyed by (level, box offset) (Sec. 5.2).
+ */
+typedef struct {
+  int d;            /* spatial dimension, 1..3 */
+  double lo, hi;    /* the root box [lo, hi]^d; every point must lie inside */
+  int leaf_size;    /* used when l_max < 0: l_max = smallest l with n <= leaf_size 2^(d l) */
+  int l_max;        /* maximum (and leaf) level, >= 0, or -1 to derive it from leaf_size */
+  int eta2_num;     /* eta^2 = eta2_num / eta2_den, both > 0 */
+  int eta2_den;
+} ph_tree_opts;
+
+typedef struct {
+  int64_t n;
+  int d;
+  int l_max;
+  int64_t n_nodes, n_leaves, n_near, n_far, n_classes;
+  int64_t near_entries;      /* N_nf = sum over near blocks of n_s n_t */
+  int min_far_level;         /* smallest level holding a far block, or -1 */
+} ph_tree_info;
+
+/* Build the trees.  pts: host, row-major n x d, copied.  Errors: PH_EINVAL for a NULL
+ * pointer, n < 1, d outside 1..3, lo >= hi, a NaN or a point outside [lo, hi]^d,
+ * l_max > 20 or a non-positive eta2.  *out is owned by the caller (ph_tree_free). */
+int ph_build_tree(const double* pts, int64_t n, const ph_tree_opts* opts, ph_tree** out);
+
+int ph_tree_info_get(const ph_tree* t, ph_tree_info* info);
+
+/* perm[t] = original index of the point at tree position t (host, n entries). */
+int ph_tree_perm(const ph_tree* t, int64_t* perm);
+
+/* Per node (host arrays of n_nodes entries; coords has n_nodes * d, node-major):
+ * level, integer box index at its level, [begin, end) range in tree order, parent
+ * (-1 for the root).  Any pointer may be NULL to skip that array. */
+int ph_tree_nodes(const ph_tree* t, int32_t* level, int32_t* coords, int64_t* begin,
+                  int64_t* end, int32_t* parent);
+
+/* Block lists sorted by (level, sigma, tau): near[2b], near[2b+1] = (sigma, tau) node ids;
+ * far likewise, far_class[b] = its translation class.  Any pointer may be NULL. */
+int ph_tree_blocks(const ph_tree* t, int32_t* near, int32_t* far, int32_t* far_class);
+
+/* Translation classes sorted by (level, offset lexicographic, axis 1 first):
+ * level[c], offset[c * d + k] = k_tau - k_sigma along axis k. */
+int ph_tree_classes(const ph_tree* t, int32_t* level, int32_t* offset);
+
+void ph_tree_free(ph_tree* t);
+
+/* ---- offline stage -------------------------------------------------------------------
+ * Alg. "Offline Stage: Parametric H^2-matrix": leaf cluster-basis factors
+ * [U_{s,k}]_{ij} = l_j^{(B_{s,k})}(x_{s,i,k}) (Sec. 3.2), transfer factors
+ * [E_{s',k}]_{j,i} = l_i^{(B_s,k)}(eta_j^{(B_s',k)}) (Sec. 3.4.1, lemma orientation),
+ * one far tensor M[i, k_1.., j] = kappa(eta_i^{B_s}, eta_j^{B_t}; eta_k) per
+ * translation class (App. PTTK review, Sec. 5.2) and one near tensor
+ * A_b[e, k_1..] = kappa(x_{s,i}, x_{t,j}; eta_k), e = i + j n_s, per near block
+ * (Sec. 4.3), each compressed by a truncated HOSVD whose mode ranks keep
+ * sum_{j>r} s_j^2 <= (tol^2 / N) ||M||_F^2 (N modes), in FP64 on the host, then
+ * uploaded.  Symmetry: A_{ts} = A_{st}^T and M_{(l,-o)} = M_{(l,o)}^T exactly, so only
+ * near blocks with sigma <= tau and classes with offset >= 0 (lexicographic) are
+ * compressed; the others are their transposes.
+ */
+typedef struct {
+  ph_kernel kernel;
+  int d_theta;              /* 1 or 2; must match the kernel */
+  double theta_lo[2];       /* parameter box Theta = prod_k [theta_lo[k], theta_hi[k]] */
+  double theta_hi[2];
+  int p_s;                  /* spatial Chebyshev nodes per axis, 1..16; P = p_s^d <= 128 */
+  int p_theta;              /* parameter Chebyshev nodes per axis, 1..16 */
+  double tol;               /* relative Frobenius tolerance of each compressed tensor, >= 0 */
+  int num_threads;          /* host threads for the offline work, 0 = all */
+} ph_offline_opts;
+
+typedef struct {
+  int64_t n, n_near_stored, n_classes_stored;
+  int64_t near_entries;       /* N_nf */
+  int64_t near_factor_entries;/* sum over stored near blocks of N_e * r_e */
+  double near_rank_mean;      /* entry-weighted mean near rank r_bar */
+  int near_rank_max;
+  double far_rank_mean;       /* mean of (r_L + r_R)/2 over stored classes */
+  int far_rank_max;
+  int64_t device_bytes;       /* bytes the model holds on the device */
+  int64_t kernel_evals;       /* kernel evaluations done by the offline stage */
+  int P, p_theta, d_theta;
+} ph_model_info;
+
+/* Offline stage.  stream: the upload stream.  Errors: PH_EINVAL (NULL, bad sizes,
+ * theta_lo >= theta_hi), PH_EUNSUPPORTED (kernel / d / d_theta combination),
+ * PH_ENOMEM, PH_EHIP.  *out is owned by the caller (ph_model_free); the tree may be
+ * freed right after this call. */
+int ph_offline_compress(const ph_tree* t, const ph_offline_opts* opts, void* stream,
+                        ph_model** out);
+
+int ph_model_info_get(const ph_model* m, ph_model_info* info);
+
+/* Ranks of the stored near blocks in canonical near order (e-mode rank; -1 for blocks
+ * stored as the transpose of another), host array of n_near entries. */
+int ph_model_near_ranks(const ph_model* m, int32_t* ranks);
+
+/* Ranks (r_L, r_theta_1, [r_theta_2], r_R) of every class as stored (mirrored classes
+ * report their source's ranks swapped), host array of n_classes * (2 + d_theta). */
+int ph_model_class_ranks(const ph_model* m, int32_t* ranks);
+
+void ph_model_free(ph_model* m);
+
+/* ---- online stage --------------------------------------------------------------------
+ * Alg. "Online Stage" and Alg. PTTK online.  For each theta: parametric vectors
+ * v_k(theta_k) = [l_1 .. l_p](theta_k) on [theta_lo[k], theta_hi[k]] (App. PTTK
+ * review), far couplings C(theta) = L H(theta) R^T per class with
+ * H = core x_theta (Theta_k^T v_k) (Sec. 4.2), near blocks
+ * D_b(theta) = reshape(P_b c_b(theta), [n_s, n_t]) with c_b = core x_theta (Theta_k^T v_k)
+ * (Sec. 4.3).  No kernel evaluation happens here.
+ *
+ * theta: host, T x d_theta row-major.  T >= 1 instantiates T independent parameter
+ * values into one instance (slot t holds theta[t]).  dt selects the storage and
+ * arithmetic (PH_F64 or PH_F32).
+ * *inout: NULL -> a new instance is allocated and returned (owned by the caller,
+ * ph_inst_free).  Non-NULL -> that instance is re-instantiated in place; it must come
+ * from the same model with the same T and dt (else PH_EINVAL), and no allocation
+ * happens.  Any theta outside Theta -> PH_EDOMAIN before anything is enqueued. */
+int ph_instantiate(const ph_model* m, const double* theta, int T, ph_dtype dt, void* stream,
+                   ph_inst** inout);
+
+/* As ph_instantiate, but the instance holds dK~/dtheta_dim at each theta: the
+ * parametric vector of dimension dim is replaced by its derivative v_dim'(theta_dim)
+ * (the approximation is linear in each v_k, so this is its exact derivative).
+ * 0 <= dim < d_theta.  Use it with ph_matvec. */
+int ph_instantiate_grad(const ph_model* m, const double* theta, int T, int dim, ph_dtype dt,
+                        void* stream, ph_inst** inout);
+
+/* H^2 matrix-vector product (Alg. "H^2-matrix MVM": FastForward, coupling over the far
+ * blocks, near-field products, FastBackward), for every slot t:
+ *   y_t = alpha * (K~(theta_t) + nugget I) x_t + beta * y_t.
+ * x, y: device, slot-major [T][R][n] with each slot column-major n x R (leading
+ * dimension n) in the ORIGINAL point order; double for PH_F64, float for PH_F32.
+ * x and y must not overlap.  R = 0 is a no-op.  With beta == 0, y is not read.
+ * Scratch for R right-hand sides is allocated on the first call with a larger R and
+ * kept in the instance. */
+int ph_matvec(ph_inst* k, const void* x, void* y, int64_t R, double alpha, double beta,
+              double nugget, void* stream);
+
+/* Inspection (tests): copy the instantiated near block of canonical near index b for
+ * slot t (n_s x n_t column-major, as double) or the coupling matrix of class c
+ * (P x P column-major, as double) to host memory.  Synchronises the device. */
+int ph_inst_near_block(const ph_inst* k, int t, int64_t b, double* host_out);
+int ph_inst_coupling(const ph_inst* k, int t, int64_t c, double* host_out);
+
+void ph_inst_free(ph_inst* k);
+
+/* ---- tracing ---------------------------------------------------------------------------
+ * When enabled, every kernel launch of ph_instantiate / ph_matvec is bracketed by HIP
+ * events on its stream; ph_trace_read waits for the recorded events and returns the
+ * summed device time and launch count per stage (and clears them if reset != 0).
+ * Process-wide; meant for benchmarking, not for concurrent use from several threads. */
+enum {
+  PH_STAGE_THETA = 0,         /* parametric vectors v_k(theta_k) */
+  PH_STAGE_FAR_INST = 1,      /* far-field couplings C(theta) */
+  PH_STAGE_NEAR_INST = 2,     /* near-field blocks D_b(theta) */
+  PH_STAGE_PERM_IN = 3,
+  PH_STAGE_LEAF_UP = 4,       /* FastForward, leaves */
+  PH_STAGE_TRANSFER_UP = 5,   /* FastForward, inner nodes */
+  PH_STAGE_COUPLING = 6,      /* y_hat += C x_hat over far blocks */
+  PH_STAGE_TRANSFER_DOWN = 7, /* FastBackward, inner nodes */
+  PH_STAGE_LEAF_NEAR = 8,     /* FastBackward leaves + near-field products */
+  PH_STAGE_PERM_OUT = 9,
+  PH_STAGE_ZERO = 10,
+  PH_NUM_STAGES = 11
+};
+typedef struct {
+  double ms[16];
+  int64_t count[16];
+} ph_trace_stats;
+
+int ph_trace_enable(int on);
+int ph_trace_read(ph_trace_stats* out, int reset);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* ph_last_error(void);
+
+/* Library version string. */
+const char* ph_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PH_H */

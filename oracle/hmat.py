@@ -256,13 +256,19 @@ class PH2:
         coupling and near-field products of the blocks in the rows' leaf-to-root
         paths, and the downward pass along those paths.
         """
+        near, far, _, _ = self.blocks_for_rows(rows)
+        inst = self.instantiate(theta, deriv_dim, near_blocks=near, far_keys=far)
+        return self.matvec_rows_inst(inst, x, rows, nugget)
+
+    def matvec_rows_inst(self, inst, x, rows, nugget=0.0):
+        """``matvec`` restricted to the given rows, with an instance holding (at least) the
+        near blocks and far keys of those rows' leaf-to-root paths."""
         t = self.tree
         x = np.asarray(x, dtype=np.float64)
         squeeze = x.ndim == 1
         if squeeze:
             x = x[:, None]
-        near, far, anc, pos = self.blocks_for_rows(rows)
-        inst = self.instantiate(theta, deriv_dim, near_blocks=near, far_keys=far)
+        near, _, anc, pos = self.blocks_for_rows(rows)
         xt = x[t.perm]
         xh = self._upward(xt)
         yh = {s: np.zeros((self.P, x.shape[1])) for s in anc}

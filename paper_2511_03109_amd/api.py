@@ -1,0 +1,201 @@
+"""Thin Python binding over the C ABI (include/ph.h).
+
+Marshalling only: numpy arrays for host inputs, torch tensors for device
+buffers and the current HIP stream.  Every step of the online stage runs in
+the library's HIP kernels; nothing here computes.
+"""
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Tree:
+    """Cluster tree and block cluster tree (ph_build_tree)."""
+
+    def __init__(self, points, *, lo=0.0, hi=1.0, leaf_size=64, l_max=-1, eta2=None):
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        if pts.ndim != 2:
+            raise ValueError("points must be (n, d)")
+        n, d = pts.shape
+        num, den = eta2 if eta2 is not None else (d, 1)
+        opts = L.TreeOpts(d, lo, hi, leaf_size, l_max, num, den)
+        h = C.c_void_p()
+        L.check(L.lib().ph_build_tree(_dptr(pts), n, C.byref(opts), C.byref(h)), "ph_build_tree")
+        self._h = h
+        info = L.TreeInfo()
+        L.check(L.lib().ph_tree_info_get(h, C.byref(info)), "ph_tree_info_get")
+        self.info = {k: getattr(info, k) for k, _ in L.TreeInfo._fields_}
+        self.n, self.d = n, d
+
+    def perm(self):
+        out = np.empty(self.n, dtype=np.int64)
+        L.check(L.lib().ph_tree_perm(self._h, out.ctypes.data_as(C.POINTER(C.c_int64))), "ph_tree_perm")
+        return out
+
+    def nodes(self):
+        nn = self.info["n_nodes"]
+        level = np.empty(nn, np.int32)
+        coords = np.empty((nn, self.d), np.int32)
+        begin = np.empty(nn, np.int64)
+        end = np.empty(nn, np.int64)
+        parent = np.empty(nn, np.int32)
+        i32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        i64 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))
+        L.check(L.lib().ph_tree_nodes(self._h, i32(level), i32(coords), i64(begin), i64(end), i32(parent)),
+                "ph_tree_nodes")
+        return dict(level=level, coords=coords, begin=begin, end=end, parent=parent)
+
+    def blocks(self):
+        near = np.empty((self.info["n_near"], 2), np.int32)
+        far = np.empty((self.info["n_far"], 2), np.int32)
+        fcls = np.empty(self.info["n_far"], np.int32)
+        i32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        L.check(L.lib().ph_tree_blocks(self._h, i32(near), i32(far), i32(fcls)), "ph_tree_blocks")
+        return near, far, fcls
+
+    def classes(self):
+        lev = np.empty(self.info["n_classes"], np.int32)
+        off = np.empty((self.info["n_classes"], self.d), np.int32)
+        i32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        L.check(L.lib().ph_tree_classes(self._h, i32(lev), i32(off)), "ph_tree_classes")
+        return lev, off
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            L.lib().ph_tree_free(self._h)
+            self._h = None
+
+
+class Model:
+    """Offline stage output on the device (ph_offline_compress)."""
+
+    def __init__(self, tree, kernel, theta_lo, theta_hi, *, p_s, p_theta, tol, num_threads=0,
+                 stream=None):
+        lo = np.atleast_1d(np.asarray(theta_lo, dtype=np.float64))
+        hi = np.atleast_1d(np.asarray(theta_hi, dtype=np.float64))
+        opts = L.OfflineOpts()
+        opts.kernel = L.KERNELS[kernel]
+        opts.d_theta = lo.shape[0]
+        for k in range(lo.shape[0]):
+            opts.theta_lo[k] = lo[k]
+            opts.theta_hi[k] = hi[k]
+        opts.p_s, opts.p_theta, opts.tol, opts.num_threads = p_s, p_theta, tol, num_threads
+        h = C.c_void_p()
+        L.check(L.lib().ph_offline_compress(tree._h, C.byref(opts), _stream(stream), C.byref(h)),
+                "ph_offline_compress")
+        self._h = h
+        self.tree = tree
+        info = L.ModelInfo()
+        L.check(L.lib().ph_model_info_get(h, C.byref(info)), "ph_model_info_get")
+        self.info = {k: getattr(info, k) for k, _ in L.ModelInfo._fields_}
+        self.d_theta = lo.shape[0]
+
+    def near_ranks(self):
+        out = np.empty(self.tree.info["n_near"], np.int32)
+        L.check(L.lib().ph_model_near_ranks(self._h, out.ctypes.data_as(C.POINTER(C.c_int32))),
+                "ph_model_near_ranks")
+        return out
+
+    def class_ranks(self):
+        out = np.empty((self.tree.info["n_classes"], 2 + self.d_theta), np.int32)
+        L.check(L.lib().ph_model_class_ranks(self._h, out.ctypes.data_as(C.POINTER(C.c_int32))),
+                "ph_model_class_ranks")
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            L.lib().ph_model_free(self._h)
+            self._h = None
+
+
+class Instance:
+    """An instantiated H^2-matrix for T parameter values (ph_instantiate / ph_instantiate_grad)."""
+
+    def __init__(self, model, theta, *, dtype="f64", grad_dim=None, stream=None):
+        self.model = model
+        self._h = C.c_void_p()
+        self.dtype = dtype
+        th = self._theta(theta)
+        self.T = th.shape[0]
+        self._call(th, grad_dim, stream)
+
+    def _theta(self, theta):
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1, self.model.d_theta))
+        return th
+
+    def _call(self, th, grad_dim, stream):
+        if grad_dim is None:
+            code = L.lib().ph_instantiate(self.model._h, _dptr(th), th.shape[0], L.DTYPES[self.dtype],
+                                          _stream(stream), C.byref(self._h))
+            L.check(code, "ph_instantiate")
+        else:
+            code = L.lib().ph_instantiate_grad(self.model._h, _dptr(th), th.shape[0], grad_dim,
+                                               L.DTYPES[self.dtype], _stream(stream), C.byref(self._h))
+            L.check(code, "ph_instantiate_grad")
+
+    def reinstantiate(self, theta, *, grad_dim=None, stream=None):
+        """Re-instantiate in place (same T and dtype; no allocation)."""
+        th = self._theta(theta)
+        if th.shape[0] != self.T:
+            raise ValueError("T must match the instance")
+        self._call(th, grad_dim, stream)
+
+    def matvec(self, x, y=None, *, alpha=1.0, beta=0.0, nugget=0.0, stream=None):
+        """y = alpha (K~ + nugget I) x + beta y for device tensors x of shape (n,), (R, n) or (T, R, n)."""
+        import torch
+        want = torch.float64 if self.dtype == "f64" else torch.float32
+        if x.dtype != want or not x.is_cuda:
+            raise TypeError(f"x must be a {want} device tensor")
+        x = x.contiguous()
+        n = self.model.tree.n
+        if x.shape[-1] != n:
+            raise ValueError("last dimension of x must be n")
+        R = 1 if x.dim() == 1 else x.shape[-2]
+        if x.dim() == 3 and x.shape[0] != self.T:
+            raise ValueError("leading dimension must be T")
+        if x.dim() < 3 and self.T != 1:
+            raise ValueError("x must be (T, R, n) for a T > 1 instance")
+        if y is None:
+            y = torch.empty_like(x)
+            beta = 0.0
+        elif y.shape != x.shape or y.dtype != want or not y.is_contiguous():
+            raise ValueError("y must be a contiguous tensor shaped like x")
+        code = L.lib().ph_matvec(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), R,
+                                 alpha, beta, nugget, _stream(stream))
+        L.check(code, "ph_matvec")
+        return y
+
+    def near_block(self, b, t=0):
+        near, _, _ = self.model.tree.blocks()
+        nodes = self.model.tree.nodes()
+        s, u = near[b]
+        ns = nodes["end"][s] - nodes["begin"][s]
+        nt = nodes["end"][u] - nodes["begin"][u]
+        out = np.empty(ns * nt)
+        L.check(L.lib().ph_inst_near_block(self._h, t, b, _dptr(out)), "ph_inst_near_block")
+        return out.reshape(nt, ns).T
+
+    def coupling(self, c, t=0):
+        P = self.model.info["P"]
+        out = np.empty(P * P)
+        L.check(L.lib().ph_inst_coupling(self._h, t, c, _dptr(out)), "ph_inst_coupling")
+        return out.reshape(P, P).T
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            L.lib().ph_inst_free(self._h)
+            self._h = None

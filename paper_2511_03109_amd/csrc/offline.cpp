@@ -1,0 +1,553 @@
+// Offline stage on the host, FP64 (Alg. "Offline Stage: Parametric H^2-matrix",
+// arxiv 2511.03109).
+//
+//  * Chebyshev nodes of the first kind, ascending:
+//      eta_i = (a+b)/2 - (b-a)/2 cos((2i-1) pi / (2p))      (Sec. 2.2)
+//    Lagrange basis by the product formula of Sec. 2.2.
+//  * Leaf cluster-basis factors [U_{s,k}]_{ij} = l_j^{(B_{s,k})}(x_{s,i,k}) (Sec. 3.2).
+//  * Transfer factors (Sec. 3.4.1 with the orientation of the transfer lemma):
+//      [E_{s',k}]_{j,i} = l_i^{(B_{s,k})}(eta_j^{(B_{s',k})}).
+//    The Lagrange basis is invariant under affine maps of the interval, so the
+//    factor only depends on whether s' is the lower or the upper half of s along
+//    axis k; the two matrices are formed on [0, 1].
+//  * Far tensors (App. PTTK review) M[i, k, j] = kappa(eta_i^{(B_s)}, eta_j^{(B_t)}; eta_k),
+//    one per translation class (Sec. 5.2), built on the boxes of the class's first
+//    far block; near tensors (Sec. 4.3) A_b[e, k] = kappa(x_{s,i}, x_{t,j}; eta_k),
+//    e = i + j n_s.
+//  * Compression: truncated HOSVD (Tucker) over the grouped modes; per mode the
+//    smallest rank r with sum_{j>r} s_j^2 <= (tol^2 / N) ||M||_F^2 (N = number of
+//    modes), giving ||M - M^||_F <= tol ||M||_F.  Singular values and vectors of
+//    each unfolding come from a Householder QR of the tall orientation followed by a
+//    one-sided (Hestenes) Jacobi SVD of the small triangular factor.
+//  * Symmetry: kappa(x, y) = kappa(y, x), so A_{ts} is A_{st} with the pair index
+//    transposed and M_{(l,-o)}[i,k,j] = M_{(l,o)}[j,k,i]; only near blocks with
+//    s <= t and classes with offset >= 0 (lexicographic) are compressed.
+#include <omp.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+
+#include "ph_host.hpp"
+
+namespace ph {
+
+namespace {
+
+void cheb_nodes(double a, double b, int p, double* out) {
+  for (int i = 1; i <= p; ++i)
+    out[i - 1] = (a + b) / 2.0 - (b - a) / 2.0 * std::cos((2.0 * i - 1.0) * M_PI / (2.0 * p));
+}
+
+// l_k(x) for k = 0..p-1 by the product formula
+void lagrange_all(const double* nodes, int p, double x, double* out) {
+  for (int k = 0; k < p; ++k) {
+    double v = 1.0;
+    for (int i = 0; i < p; ++i)
+      if (i != k) v *= (x - nodes[i]) / (nodes[k] - nodes[i]);
+    out[k] = v;
+  }
+}
+
+// ---- dense linear algebra (column-major) ---------------------------------------------
+
+// Householder QR of the m x k matrix A (m >= k, leading dimension m), in place.
+// On return the upper triangle of A holds R, the columns below the diagonal hold
+// the Householder vectors v_j (v_j[j] = 1 implied), tau[j] their scalars.
+void householder_qr(double* A, int64_t m, int k, double* tau) {
+  for (int j = 0; j < k; ++j) {
+    double* a = A + (int64_t)j * m;
+    double norm2 = 0;
+    for (int64_t i = j + 1; i < m; ++i) norm2 += a[i] * a[i];
+    double alpha = a[j];
+    if (norm2 == 0.0) {
+      tau[j] = 0.0;
+      continue;
+    }
+    double beta = -std::copysign(std::sqrt(alpha * alpha + norm2), alpha);
+    double scale = 1.0 / (alpha - beta);
+    for (int64_t i = j + 1; i < m; ++i) a[i] *= scale;
+    tau[j] = (beta - alpha) / beta;
+    a[j] = beta;
+    // apply H_j = I - tau v v^T to the remaining columns
+    for (int c = j + 1; c < k; ++c) {
+      double* b = A + (int64_t)c * m;
+      double dot = b[j];
+      for (int64_t i = j + 1; i < m; ++i) dot += a[i] * b[i];
+      dot *= tau[j];
+      b[j] -= dot;
+      for (int64_t i = j + 1; i < m; ++i) b[i] -= dot * a[i];
+    }
+  }
+}
+
+// Y (m x r, leading dimension m) <- Q Y, with Q = H_0 H_1 ... H_{k-1} from householder_qr.
+void apply_q(const double* A, int64_t m, int k, const double* tau, double* Y, int r) {
+  for (int j = k - 1; j >= 0; --j) {
+    if (tau[j] == 0.0) continue;
+    const double* a = A + (int64_t)j * m;
+    for (int c = 0; c < r; ++c) {
+      double* y = Y + (int64_t)c * m;
+      double dot = y[j];
+      for (int64_t i = j + 1; i < m; ++i) dot += a[i] * y[i];
+      dot *= tau[j];
+      y[j] -= dot;
+      for (int64_t i = j + 1; i < m; ++i) y[i] -= dot * a[i];
+    }
+  }
+}
+
+// One-sided Jacobi SVD of the k x k matrix W (overwritten): W V = U S.
+// Outputs s (descending), U and V (k x k column-major).
+void jacobi_svd(double* W, int k, double* s, double* U, double* V) {
+  std::vector<double> Vw((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i) Vw[(size_t)i * k + i] = 1.0;
+  const double eps = 2.220446049250313e-16;
+  for (int sweep = 0; sweep < 80; ++sweep) {
+    bool rotated = false;
+    for (int p = 0; p < k - 1; ++p) {
+      for (int q = p + 1; q < k; ++q) {
+        double* wp = W + (size_t)p * k;
+        double* wq = W + (size_t)q * k;
+        double al = 0, be = 0, ga = 0;
+        for (int i = 0; i < k; ++i) {
+          al += wp[i] * wp[i];
+          be += wq[i] * wq[i];
+          ga += wp[i] * wq[i];
+        }
+        if (al == 0.0 || be == 0.0) continue;
+        if (std::fabs(ga) <= eps * std::sqrt(al * be)) continue;
+        rotated = true;
+        double zeta = (be - al) / (2.0 * ga);
+        double t = std::copysign(1.0, zeta) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        double c = 1.0 / std::sqrt(1.0 + t * t);
+        double sn = c * t;
+        for (int i = 0; i < k; ++i) {
+          double x = wp[i], y = wq[i];
+          wp[i] = c * x - sn * y;
+          wq[i] = sn * x + c * y;
+        }
+        double* vp = Vw.data() + (size_t)p * k;
+        double* vq = Vw.data() + (size_t)q * k;
+        for (int i = 0; i < k; ++i) {
+          double x = vp[i], y = vq[i];
+          vp[i] = c * x - sn * y;
+          vq[i] = sn * x + c * y;
+        }
+      }
+    }
+    if (!rotated) break;
+  }
+  std::vector<double> nrm(k);
+  for (int j = 0; j < k; ++j) {
+    double a = 0;
+    for (int i = 0; i < k; ++i) a += W[(size_t)j * k + i] * W[(size_t)j * k + i];
+    nrm[j] = std::sqrt(a);
+  }
+  std::vector<int> order(k);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nrm[a] > nrm[b]; });
+  for (int jj = 0; jj < k; ++jj) {
+    int j = order[jj];
+    s[jj] = nrm[j];
+    for (int i = 0; i < k; ++i) {
+      U[(size_t)jj * k + i] = nrm[j] > 0 ? W[(size_t)j * k + i] / nrm[j] : (i == jj ? 1.0 : 0.0);
+      V[(size_t)jj * k + i] = Vw[(size_t)j * k + i];
+    }
+  }
+}
+
+// Smallest r >= 0 with sum_{j >= r} s_j^2 <= thr (tail summed from the smallest value up).
+int truncation_rank(const double* s, int k, double thr) {
+  std::vector<double> tail(k + 1, 0.0);
+  for (int j = k - 1; j >= 0; --j) tail[j] = tail[j + 1] + s[j] * s[j];
+  for (int r = 0; r <= k; ++r)
+    if (tail[r] <= thr) return r;
+  return k;
+}
+
+// Left singular vectors (first r columns) and singular values of the m x q matrix X
+// given by an accessor that fills it column-major.  Chooses the tall orientation.
+struct LeftSV {
+  std::vector<double> U;  // m x kk, column-major, kk = min(m, q)
+  std::vector<double> s;  // kk
+  int64_t m = 0;
+  int kk = 0;
+};
+
+// X column-major m x q (leading dimension m).
+LeftSV left_sv(const double* X, int64_t m, int64_t q) {
+  LeftSV out;
+  out.m = m;
+  if (m >= q) {
+    // tall: X = Q R, R = U_R S V_R^T  ->  left sv = Q U_R
+    int k = (int)q;
+    std::vector<double> A(X, X + m * q), tau(k);
+    householder_qr(A.data(), m, k, tau.data());
+    std::vector<double> R((size_t)k * k, 0.0), UR((size_t)k * k), VR((size_t)k * k);
+    for (int c = 0; c < k; ++c)
+      for (int i = 0; i <= c; ++i) R[(size_t)c * k + i] = A[(size_t)c * m + i];
+    out.s.resize(k);
+    jacobi_svd(R.data(), k, out.s.data(), UR.data(), VR.data());
+    out.U.assign((size_t)m * k, 0.0);
+    for (int c = 0; c < k; ++c)
+      for (int i = 0; i < k; ++i) out.U[(size_t)c * m + i] = UR[(size_t)c * k + i];
+    apply_q(A.data(), m, k, tau.data(), out.U.data(), k);
+    out.kk = k;
+  } else {
+    // wide: X^T = Q R, R = U_R S V_R^T  ->  X = V_R S (Q U_R)^T, left sv = V_R
+    int k = (int)m;
+    std::vector<double> A((size_t)q * m), tau(k);
+    for (int64_t i = 0; i < m; ++i)
+      for (int64_t j = 0; j < q; ++j) A[(size_t)i * q + j] = X[(size_t)j * m + i];
+    householder_qr(A.data(), q, k, tau.data());
+    std::vector<double> R((size_t)k * k, 0.0), UR((size_t)k * k), VR((size_t)k * k);
+    for (int c = 0; c < k; ++c)
+      for (int i = 0; i <= c; ++i) R[(size_t)c * k + i] = A[(size_t)c * q + i];
+    out.s.resize(k);
+    jacobi_svd(R.data(), k, out.s.data(), UR.data(), VR.data());
+    out.U = VR;
+    out.kk = k;
+  }
+  return out;
+}
+
+// Mode-m unfolding of a column-major tensor with dims n[0..N-1] (first index fastest),
+// written column-major as n[m] x (prod of the others).
+std::vector<double> unfold(const std::vector<double>& T, const std::vector<int64_t>& n, int m) {
+  int64_t left = 1, right = 1;
+  for (int i = 0; i < m; ++i) left *= n[i];
+  for (size_t i = m + 1; i < n.size(); ++i) right *= n[i];
+  const int64_t mid = n[m];
+  std::vector<double> X((size_t)mid * left * right);
+  for (int64_t rr = 0; rr < right; ++rr)
+    for (int64_t i = 0; i < mid; ++i)
+      for (int64_t l = 0; l < left; ++l)
+        X[(size_t)i + mid * (l + left * rr)] = T[(size_t)l + left * (i + mid * rr)];
+  return X;
+}
+
+// Y = T x_m A^T, A (n[m] x r column-major): Y[.., a, ..] = sum_i T[.., i, ..] A[i, a]
+std::vector<double> mode_contract(const std::vector<double>& T, std::vector<int64_t>& n, int m,
+                                  const double* A, int r) {
+  int64_t left = 1, right = 1;
+  for (int i = 0; i < m; ++i) left *= n[i];
+  for (size_t i = m + 1; i < n.size(); ++i) right *= n[i];
+  const int64_t mid = n[m];
+  std::vector<double> Y((size_t)left * r * right, 0.0);
+  for (int64_t rr = 0; rr < right; ++rr)
+    for (int a = 0; a < r; ++a)
+      for (int64_t i = 0; i < mid; ++i) {
+        const double w = A[(size_t)a * mid + i];
+        const double* src = T.data() + (size_t)left * (i + mid * rr);
+        double* dst = Y.data() + (size_t)left * (a + r * rr);
+        for (int64_t l = 0; l < left; ++l) dst[l] += w * src[l];
+      }
+  n[m] = r;
+  return Y;
+}
+
+struct Tucker {
+  std::vector<std::vector<double>> factors;  // column-major n[m] x r[m]
+  std::vector<int> ranks;
+  std::vector<double> core;                  // column-major r[0] x r[1] x ...
+};
+
+// Truncated HOSVD of the column-major tensor T with dims n.
+Tucker thosvd(const std::vector<double>& T, const std::vector<int64_t>& n, double tol) {
+  const int N = (int)n.size();
+  double normsq = 0;
+  for (double v : T) normsq += v * v;
+  const double thr = (tol * tol / N) * normsq;
+  Tucker out;
+  for (int m = 0; m < N; ++m) {
+    int64_t rest = 1;
+    for (int i = 0; i < N; ++i)
+      if (i != m) rest *= n[i];
+    LeftSV sv;
+    if (m == 0) {
+      sv = left_sv(T.data(), n[0], rest);
+    } else {
+      std::vector<double> X = unfold(T, n, m);
+      sv = left_sv(X.data(), n[m], rest);
+    }
+    int r = normsq == 0.0 ? 0 : truncation_rank(sv.s.data(), sv.kk, thr);
+    out.ranks.push_back(r);
+    out.factors.emplace_back(sv.U.begin(), sv.U.begin() + (size_t)n[m] * r);
+  }
+  std::vector<int64_t> dims = n;
+  std::vector<double> core = T;
+  for (int m = 0; m < N; ++m) core = mode_contract(core, dims, m, out.factors[m].data(), out.ranks[m]);
+  out.core = std::move(core);
+  return out;
+}
+
+}  // namespace
+
+int kernel_dtheta(ph_kernel k, int d) {
+  switch (k) {
+    case PH_KERNEL_GAUSSIAN:
+    case PH_KERNEL_MATERN32:
+    case PH_KERNEL_MATERN12:
+    case PH_KERNEL_POLY_TEST:
+      return 1;
+    case PH_KERNEL_ANISO_GAUSSIAN:
+      return d;
+    case PH_KERNEL_POLY2_TEST:
+      return 2;
+  }
+  return -1;
+}
+
+double kernel_value(ph_kernel k, int d, const double* x, const double* y, const double* th) {
+  double r2 = 0;
+  for (int i = 0; i < d; ++i) r2 += (x[i] - y[i]) * (x[i] - y[i]);
+  switch (k) {
+    case PH_KERNEL_GAUSSIAN:
+      return std::exp(-r2 / (2.0 * th[0] * th[0]));
+    case PH_KERNEL_MATERN32: {
+      double s = std::sqrt(3.0) * std::sqrt(r2) / th[0];
+      return (1.0 + s) * std::exp(-s);
+    }
+    case PH_KERNEL_MATERN12:
+      return std::exp(-std::sqrt(r2) / th[0]);
+    case PH_KERNEL_ANISO_GAUSSIAN: {
+      double e = 0;
+      for (int i = 0; i < d; ++i) e += (x[i] - y[i]) * (x[i] - y[i]) / (2.0 * th[i] * th[i]);
+      return std::exp(-e);
+    }
+    case PH_KERNEL_POLY_TEST:
+      return th[0] * th[0] * r2 + th[0];
+    case PH_KERNEL_POLY2_TEST:
+      return th[0] * r2 + th[1] * th[1];
+  }
+  return 0.0;
+}
+
+std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts& o) {
+  const int d = t.d;
+  if (o.p_s < 1 || o.p_s > 16 || o.p_theta < 1 || o.p_theta > 16)
+    fail(PH_EINVAL, "ph_offline_compress: p_s and p_theta must be in 1..16");
+  if (!(o.tol >= 0.0)) fail(PH_EINVAL, "ph_offline_compress: tol must be >= 0");
+  const int dth = kernel_dtheta(o.kernel, d);
+  if (dth < 0) fail(PH_EUNSUPPORTED, "ph_offline_compress: unknown kernel");
+  if (o.kernel == PH_KERNEL_ANISO_GAUSSIAN && d > 2)
+    fail(PH_EUNSUPPORTED, "ph_offline_compress: anisotropic Gaussian supports d <= 2");
+  if (o.d_theta != dth) fail(PH_EUNSUPPORTED, "ph_offline_compress: d_theta does not match the kernel");
+  for (int k = 0; k < dth; ++k)
+    if (!(o.theta_lo[k] < o.theta_hi[k])) fail(PH_EINVAL, "ph_offline_compress: need theta_lo < theta_hi");
+  int P = 1;
+  for (int k = 0; k < d; ++k) P *= o.p_s;
+  if (P > 128) fail(PH_EUNSUPPORTED, "ph_offline_compress: p_s^d must be <= 128");
+
+  auto m = std::make_shared<HostModel>();
+  m->d = d; m->p_s = o.p_s; m->P = P; m->p_theta = o.p_theta; m->d_theta = dth;
+  m->kernel = o.kernel; m->tol = o.tol;
+  for (int k = 0; k < dth; ++k) { m->th_lo[k] = o.theta_lo[k]; m->th_hi[k] = o.theta_hi[k]; }
+  const int ps = o.p_s, pt = o.p_theta;
+  int nthreads = o.num_threads > 0 ? o.num_threads : omp_get_max_threads();
+
+  // parameter grid: q = p^dth nodes, little-endian (k_1 fastest)
+  const int q = dth == 1 ? pt : pt * pt;
+  std::vector<double> thn(2 * 16), grid((size_t)q * 2, 0.0);
+  for (int k = 0; k < dth; ++k) cheb_nodes(o.theta_lo[k], o.theta_hi[k], pt, thn.data() + 16 * k);
+  for (int kk = 0; kk < q; ++kk) {
+    grid[2 * kk] = thn[kk % pt];
+    if (dth == 2) grid[2 * kk + 1] = thn[16 + kk / pt];
+  }
+
+  // leaf factors
+  const int64_t n = t.n;
+  m->U.assign((size_t)n * d * ps, 0.0);
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 4)
+  for (int64_t li = 0; li < (int64_t)t.leaves.size(); ++li) {
+    int32_t s = t.leaves[li];
+    double nodes[16];
+    for (int k = 0; k < d; ++k) {
+      cheb_nodes(t.box_lo[s * d + k], t.box_hi[s * d + k], ps, nodes);
+      for (int64_t i = t.begin[s]; i < t.end[s]; ++i)
+        lagrange_all(nodes, ps, t.pts_t[i * d + k], m->U.data() + (i * d + k) * ps);
+    }
+  }
+  // transfer factors on the reference interval
+  {
+    double par[16], ch[16], row[16];
+    cheb_nodes(0.0, 1.0, ps, par);
+    m->E.assign((size_t)2 * ps * ps, 0.0);
+    for (int h = 0; h < 2; ++h) {
+      cheb_nodes(h ? 0.5 : 0.0, h ? 1.0 : 0.5, ps, ch);
+      for (int j = 0; j < ps; ++j) {
+        lagrange_all(par, ps, ch[j], row);
+        for (int i = 0; i < ps; ++i) m->E[((size_t)h * ps + j) * ps + i] = row[i];
+      }
+    }
+  }
+
+  // ---- far classes
+  const int64_t ncls = t.n_classes();
+  m->class_src.assign(ncls, -1);
+  m->class_tr.assign(ncls, 0);
+  std::vector<int32_t> canon;
+  {
+    std::map<std::vector<int32_t>, int32_t> bykey;
+    for (int64_t c = 0; c < ncls; ++c) {
+      std::vector<int32_t> kk{t.class_level[c]};
+      for (int k = 0; k < d; ++k) kk.push_back(t.class_off[c * d + k]);
+      bykey[kk] = (int32_t)c;
+    }
+    for (int64_t c = 0; c < ncls; ++c) {
+      std::vector<int32_t> off(t.class_off.begin() + c * d, t.class_off.begin() + (c + 1) * d);
+      std::vector<int32_t> neg(d);
+      for (int k = 0; k < d; ++k) neg[k] = -off[k];
+      if (off >= neg) {  // lexicographic, offset >= its negative
+        ClassStored cs{};
+        cs.cls = (int32_t)c;
+        std::vector<int32_t> mk{t.class_level[c]};
+        mk.insert(mk.end(), neg.begin(), neg.end());
+        auto it = bykey.find(mk);
+        cs.mirror = (it != bykey.end() && it->second != c) ? it->second : -1;
+        m->class_src[c] = (int32_t)m->cstore.size();
+        if (cs.mirror >= 0) {
+          m->class_src[cs.mirror] = (int32_t)m->cstore.size();
+          m->class_tr[cs.mirror] = 1;
+        }
+        m->cstore.push_back(cs);
+      }
+    }
+  }
+  const int64_t nfc = (int64_t)m->cstore.size();
+  std::vector<Tucker> ftuck(nfc);
+  int64_t evals_far = 0;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) reduction(+ : evals_far)
+  for (int64_t ci = 0; ci < nfc; ++ci) {
+    const int32_t c = m->cstore[ci].cls;
+    const int32_t b = t.class_first_block[c];
+    const int32_t s = t.far[2 * b], u = t.far[2 * b + 1];
+    std::vector<double> ns((size_t)P * d), nt((size_t)P * d);
+    for (int k = 0; k < d; ++k) {
+      double bs[16], bt[16];
+      cheb_nodes(t.box_lo[s * d + k], t.box_hi[s * d + k], ps, bs);
+      cheb_nodes(t.box_lo[u * d + k], t.box_hi[u * d + k], ps, bt);
+      int stride = 1;
+      for (int kk = 0; kk < k; ++kk) stride *= ps;
+      for (int i = 0; i < P; ++i) {
+        ns[(size_t)i * d + k] = bs[(i / stride) % ps];
+        nt[(size_t)i * d + k] = bt[(i / stride) % ps];
+      }
+    }
+    std::vector<double> M((size_t)P * q * P);
+    for (int j = 0; j < P; ++j)
+      for (int kk = 0; kk < q; ++kk)
+        for (int i = 0; i < P; ++i)
+          M[(size_t)i + P * (kk + (size_t)q * j)] =
+              kernel_value(o.kernel, d, &ns[(size_t)i * d], &nt[(size_t)j * d], &grid[2 * kk]);
+    evals_far += (int64_t)P * q * P;
+    std::vector<int64_t> dims{P};
+    if (dth == 1) dims.push_back(pt);
+    else { dims.push_back(pt); dims.push_back(pt); }
+    dims.push_back(P);
+    ftuck[ci] = thosvd(M, dims, o.tol);
+  }
+  for (int64_t ci = 0; ci < nfc; ++ci) {
+    ClassStored& cs = m->cstore[ci];
+    Tucker& tk = ftuck[ci];
+    cs.rL = tk.ranks.front();
+    cs.rR = tk.ranks.back();
+    cs.r1 = tk.ranks[1];
+    cs.r2 = dth == 2 ? tk.ranks[2] : 1;
+    cs.L_off = (int64_t)m->ff_L.size();
+    m->ff_L.insert(m->ff_L.end(), tk.factors.front().begin(), tk.factors.front().end());
+    cs.R_off = (int64_t)m->ff_R.size();
+    m->ff_R.insert(m->ff_R.end(), tk.factors.back().begin(), tk.factors.back().end());
+    cs.th1_off = (int64_t)m->ff_theta.size();
+    m->ff_theta.insert(m->ff_theta.end(), tk.factors[1].begin(), tk.factors[1].end());
+    cs.th2_off = (int64_t)m->ff_theta.size();
+    if (dth == 2) m->ff_theta.insert(m->ff_theta.end(), tk.factors[2].begin(), tk.factors[2].end());
+    cs.core_off = (int64_t)m->ff_core.size();
+    m->ff_core.insert(m->ff_core.end(), tk.core.begin(), tk.core.end());
+  }
+
+  // ---- near blocks (s <= t stored)
+  const int64_t nn = t.n_near();
+  m->near_src.assign(nn, -1);
+  m->near_tr.assign(nn, 0);
+  {
+    std::map<std::pair<int32_t, int32_t>, int32_t> idx;
+    for (int64_t b = 0; b < nn; ++b) idx[{t.near[2 * b], t.near[2 * b + 1]}] = (int32_t)b;
+    for (int64_t b = 0; b < nn; ++b) {
+      int32_t s = t.near[2 * b], u = t.near[2 * b + 1];
+      if (s > u) continue;
+      NearStored ns{};
+      ns.s = s; ns.t = u;
+      ns.s_begin = t.begin[s]; ns.t_begin = t.begin[u];
+      ns.ns = (int32_t)t.size(s); ns.nt = (int32_t)t.size(u);
+      ns.b_st = (int32_t)b;
+      ns.b_ts = -1;
+      m->near_src[b] = (int32_t)m->nstore.size();
+      if (s != u) {
+        auto it = idx.find({u, s});
+        if (it == idx.end()) fail(PH_ESTATE, "near block list is not symmetric");
+        ns.b_ts = it->second;
+        m->near_src[it->second] = (int32_t)m->nstore.size();
+        m->near_tr[it->second] = 1;
+      }
+      m->nstore.push_back(ns);
+    }
+  }
+  const int64_t nst = (int64_t)m->nstore.size();
+  std::vector<Tucker> ntuck(nst);
+  int64_t evals_near = 0;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) reduction(+ : evals_near)
+  for (int64_t bi = 0; bi < nst; ++bi) {
+    const NearStored& b = m->nstore[bi];
+    const int64_t Ne = (int64_t)b.ns * b.nt;
+    std::vector<double> A((size_t)Ne * q);
+    for (int kk = 0; kk < q; ++kk)
+      for (int32_t j = 0; j < b.nt; ++j) {
+        const double* y = &t.pts_t[(size_t)(b.t_begin + j) * d];
+        double* col = A.data() + (size_t)kk * Ne + (size_t)j * b.ns;
+        for (int32_t i = 0; i < b.ns; ++i)
+          col[i] = kernel_value(o.kernel, d, &t.pts_t[(size_t)(b.s_begin + i) * d], y, &grid[2 * kk]);
+      }
+    evals_near += Ne * q;
+    std::vector<int64_t> dims{Ne};
+    if (dth == 1) dims.push_back(pt);
+    else { dims.push_back(pt); dims.push_back(pt); }
+    ntuck[bi] = thosvd(A, dims, o.tol);
+  }
+  {
+    size_t totP = 0, totC = 0, totT = 0;
+    for (const Tucker& tk : ntuck) {
+      totP += tk.factors[0].size();
+      totC += tk.core.size();
+      for (size_t f = 1; f < tk.factors.size(); ++f) totT += tk.factors[f].size();
+    }
+    m->nf_P.reserve(totP);
+    m->nf_core.reserve(totC);
+    m->nf_theta.reserve(totT);
+  }
+  for (int64_t bi = 0; bi < nst; ++bi) {
+    NearStored& b = m->nstore[bi];
+    Tucker& tk = ntuck[bi];
+    b.r_e = tk.ranks[0];
+    b.r1 = tk.ranks[1];
+    b.r2 = dth == 2 ? tk.ranks[2] : 1;
+    b.P_off = (int64_t)m->nf_P.size();
+    // rank-outer: the column-major N_e x r_e factor is already [k][e]
+    m->nf_P.insert(m->nf_P.end(), tk.factors[0].begin(), tk.factors[0].end());
+    m->near_factor_entries += (int64_t)b.ns * b.nt * b.r_e;
+    b.core_off = (int64_t)m->nf_core.size();
+    m->nf_core.insert(m->nf_core.end(), tk.core.begin(), tk.core.end());
+    b.th1_off = (int64_t)m->nf_theta.size();
+    m->nf_theta.insert(m->nf_theta.end(), tk.factors[1].begin(), tk.factors[1].end());
+    b.th2_off = (int64_t)m->nf_theta.size();
+    if (dth == 2) m->nf_theta.insert(m->nf_theta.end(), tk.factors[2].begin(), tk.factors[2].end());
+    tk = Tucker();
+  }
+  m->kernel_evals = evals_far + evals_near;
+  return m;
+}
+
+}  // namespace ph

@@ -1,0 +1,99 @@
+// Host-side data structures of the parametric H^2 library: cluster tree, block
+// lists, translation classes (Sec. 3.2, 3.3, 5.2 of arxiv 2511.03109) and the
+// offline stage's compressed tensors (Alg. "Offline Stage: Parametric H^2").
+// Pure C++ (no HIP); the device side uploads what it needs from these.
+#pragma once
+
+#include <cstdint>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "ph.h"
+
+namespace ph {
+
+// A failure carrying a ph status code; converted to a return code at the C ABI.
+struct Failure : std::runtime_error {
+  int code;
+  Failure(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+[[noreturn]] inline void fail(int code, const std::string& msg) { throw Failure(code, msg); }
+
+struct TreeData {
+  int64_t n = 0;
+  int d = 0;
+  int l_max = 0;
+  double lo = 0, hi = 1;
+  int eta2_num = 1, eta2_den = 1;
+  std::vector<double> pts_t;       // tree-ordered points, n x d row-major
+  std::vector<int64_t> perm;       // tree position -> original index
+  // nodes, breadth-first ids
+  std::vector<int32_t> level, coords, parent, first_child, nchild, cid;
+  std::vector<int64_t> begin, end;
+  std::vector<double> box_lo, box_hi;  // n_nodes x d
+  std::vector<int32_t> level_start;    // nodes of level l are [level_start[l], level_start[l+1])
+  std::vector<int32_t> leaves;         // leaf node ids in tree order
+  // leaf blocks, sorted by (level, sigma, tau)
+  std::vector<int32_t> near, far, far_class;   // near/far: 2 entries per block
+  std::vector<int32_t> class_level, class_off; // class_off: d entries per class
+  std::vector<int32_t> class_first_block;      // first far block of each class
+  int64_t near_entries = 0;
+  int min_far_level = -1;
+
+  int64_t n_nodes() const { return (int64_t)level.size(); }
+  int64_t n_near() const { return (int64_t)near.size() / 2; }
+  int64_t n_far() const { return (int64_t)far.size() / 2; }
+  int64_t n_classes() const { return (int64_t)class_level.size(); }
+  int64_t size(int32_t node) const { return end[node] - begin[node]; }
+};
+
+std::shared_ptr<TreeData> build_tree(const double* pts, int64_t n, const ph_tree_opts& o);
+
+// Offline stage output (host).  Layout conventions:
+//  U        n x d x p_s, tree order: U[(i*d + k)*p_s + j] = l_j^{(B_leaf,k)}(x_{i,k})
+//  E        2 x p_s x p_s: E[(h*p_s + j)*p_s + i] = l_i^{parent}(eta_j^{child half h})
+//  near P   rank-outer per stored block: P[P_off + k*N_e + e], e = i + j*n_s
+//  near core  c-major: core[core_off + k + r_e*(a + r_1*b)]
+//  Theta factors (near and far) column-major p_theta x r: th[off + q + p_theta*a]
+//  far L, R  column-major P x r
+//  far core  core[off + a + r_L*(k_1 + r_1*(k_2 + r_2*b))]
+struct NearStored {
+  int32_t s, t;             // node ids, s <= t
+  int64_t s_begin, t_begin; // tree-order offsets
+  int32_t ns, nt;
+  int32_t r_e, r1, r2;      // r2 = 1 when d_theta = 1
+  int64_t P_off, core_off, th1_off, th2_off;
+  int32_t b_st, b_ts;       // canonical near indices of (s,t) and (t,s) (b_ts = -1 if s == t)
+};
+
+struct ClassStored {
+  int32_t cls, mirror;      // class index and its mirror (-1 if none)
+  int32_t rL, r1, r2, rR;
+  int64_t L_off, R_off, core_off, th1_off, th2_off;
+};
+
+struct HostModel {
+  int d = 0, p_s = 0, P = 0, p_theta = 0, d_theta = 0;
+  ph_kernel kernel = PH_KERNEL_GAUSSIAN;
+  double th_lo[2] = {0, 0}, th_hi[2] = {0, 0};
+  double tol = 0;
+  std::vector<double> U, E;
+  std::vector<NearStored> nstore;
+  std::vector<double> nf_P, nf_core, nf_theta;
+  std::vector<int32_t> near_src, near_tr;   // per canonical near block
+  std::vector<ClassStored> cstore;
+  std::vector<double> ff_L, ff_R, ff_core, ff_theta;
+  std::vector<int32_t> class_src, class_tr; // per class: stored index, transposed?
+  int64_t kernel_evals = 0;
+  int64_t near_factor_entries = 0;
+};
+
+std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts& o);
+
+// kernel value kappa(x, y; theta) on the host
+double kernel_value(ph_kernel k, int d, const double* x, const double* y, const double* th);
+int kernel_dtheta(ph_kernel k, int d);
+
+}  // namespace ph

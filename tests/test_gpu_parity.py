@@ -1,0 +1,227 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element by element.
+
+Tolerance (FP64): ||gpu - oracle||_F <= 1e-12 ||oracle||_F over each compared array
+(all instantiated near blocks together, all couplings together, the MVM output).
+Both sides compute the same truncated HOSVD of the same tensors and differ only by
+rounding: different SVD algorithms (LAPACK in the oracle, Householder QR + one-sided
+Jacobi in the library) and summation orders.  A backward-stable SVD of A_b perturbs
+the result by O(eps ||A_b||_F), a norm-wise quantity that grows with the block size
+relative to any single entry, so the comparison is norm-wise; the max-norm error is
+reported as well and must stay below 1e-10 of the largest entry.  Ranks are integers
+and must agree exactly.
+"""
+
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import hmat, kernels, tree as otree
+from paper_2511_03109_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _setup(X, kernel, lo, hi, p_s, p_theta, tol, l_max, eta2, num_threads=0):
+    from paper_2511_03109_amd import api
+    lt = api.Tree(X, l_max=l_max, eta2=eta2)
+    lm = api.Model(lt, kernel, lo, hi, p_s=p_s, p_theta=p_theta, tol=tol, num_threads=num_threads)
+    om = hmat.PH2(X, l_max=l_max, eta2=Fraction(*eta2),
+                  kernel=kernels.KERNELS[kernel][0], theta_lo=lo, theta_hi=hi, p_s=p_s,
+                  p_theta=p_theta, tol=tol)
+    return lt, lm, om
+
+
+def _close(a, b, tol=TOL64, what=""):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+    emax = np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+    print(f"[parity] {what} norm-wise {err:.3e} max-norm {emax:.3e} (tol {tol:.1e})", flush=True)
+    assert err <= tol, f"{what}: relative norm-wise error {err:.3e} > {tol:.1e}"
+    assert emax <= max(100 * tol, 1e-10), f"{what}: relative max-norm error {emax:.3e}"
+    return err
+
+
+def _check_ranks(lm, om):
+    near_r = lm.near_ranks()
+    for bi in range(len(om.near)):
+        if near_r[bi] >= 0:
+            core, facs = om.near_factors(bi)
+            assert near_r[bi] == facs[0].shape[1], f"near block {bi}"
+    cr = lm.class_ranks()
+    for c in range(len(om.classes)):
+        core, facs = om.far_factors(c)
+        assert tuple(cr[c]) == tuple(f.shape[1] for f in facs), f"class {c}"
+
+
+def _mvm_case(X, kernel, lo, hi, p_s, p_theta, tol, l_max, eta2, theta, R, nugget=0.0,
+              check_blocks=True):
+    torch = _torch()
+    lt, lm, om = _setup(X, kernel, lo, hi, p_s, p_theta, tol, l_max, eta2)
+    _check_ranks(lm, om)
+    from paper_2511_03109_amd import api
+    inst = api.Instance(lm, theta)
+    oi = om.instantiate(theta)
+    if check_blocks:
+        Dg = np.concatenate([inst.near_block(b).ravel() for b in range(len(om.near))])
+        Do = np.concatenate([oi["D"][b].ravel() for b in range(len(om.near))])
+        _close(Dg, Do, what="near blocks")
+        if len(om.classes):
+            Cg = np.stack([inst.coupling(c) for c in range(len(om.classes))])
+            Co = np.stack([oi["C"][c] for c in range(len(om.classes))])
+            _close(Cg, Co, what="couplings")
+    n = X.shape[0]
+    x = inputs.normal_vectors(n, R, 77)
+    y_o = om.matvec(oi, x, nugget=nugget)
+    xd = torch.tensor(np.ascontiguousarray(x.T), device="cuda")
+    y_g = inst.matvec(xd, nugget=nugget).cpu().numpy().T
+    return _close(y_g, y_o, what="mvm")
+
+
+def test_workload1_full():
+    """n = 2048 uniform in [0,1]^2, Gaussian, l in [0.1, 0.5], eta = 1, 6x6 / 9 nodes, tol 1e-8, l = 0.25."""
+    w = inputs.WORKLOADS[1]
+    X = inputs.points_for(1)
+    l_max = otree.default_l_max(w["n"], w["d"], w["leaf"])
+    _mvm_case(X, w["kernel"], w["theta_lo"], w["theta_hi"], w["p_s"], w["p_theta"], w["tol"], l_max,
+              w["eta2"], w["theta"], R=1)
+
+
+def test_3d_matern_small():
+    """Workload-2 recipe (Matern-3/2, 5^3 / 11 nodes, eta = sqrt 3) at n = 4096, l_max = 2, 16 RHS."""
+    w = inputs.WORKLOADS[2]
+    X = inputs.points_for(2, 4096)
+    _mvm_case(X, w["kernel"], w["theta_lo"], w["theta_hi"], w["p_s"], w["p_theta"], w["tol"], 2,
+              w["eta2"], [0.137], R=16)
+
+
+@pytest.mark.parametrize("d,n,l,eta2,R", [(1, 777, 5, (1, 1), 3), (2, 1500, 3, (2, 1), 5),
+                                           (3, 1100, 2, (3, 1), 2), (2, 300, 0, (2, 1), 2),
+                                           (2, 37, 2, (2, 1), 1)])
+def test_ragged_and_degenerate(d, n, l, eta2, R):
+    X = np.random.default_rng([5, d, n]).random((n, d))
+    _mvm_case(X, "matern12", [0.05], [0.5], 4, 7, 1e-8, l, eta2, [0.31], R=R, nugget=0.01)
+
+
+def test_polynomial_kernel_against_dense_product():
+    """Exactly interpolated kernel: the GPU MVM equals the textbook dense K(theta) x."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    X = inputs.points_for(1, 1200)
+    lt = api.Tree(X, l_max=3, eta2=(2, 1))
+    lm = api.Model(lt, "poly_test", [0.1], [0.9], p_s=3, p_theta=3, tol=1e-10)
+    x = inputs.normal_vectors(1200, 2, 3)
+    for th in (0.1, 0.45, 0.9):
+        K = kernels.poly_test(X[:, None, :], X[None, :, :], [th])
+        y = api.Instance(lm, [th]).matvec(torch.tensor(np.ascontiguousarray(x.T), device="cuda"))
+        _close(y.cpu().numpy().T, K @ x, 1e-11)
+
+
+def test_two_parameter_mixture():
+    """Anisotropic Gaussian with (l1, l2), 7 x 7 parameter grid, uneven mixture clusters."""
+    X = inputs.points_for(3, 3000)
+    _mvm_case(X, "aniso_gaussian", [0.05, 0.05], [0.5, 0.5], 5, 7, 1e-8, 4, (2, 1), [0.21, 0.09], R=4)
+
+
+def test_multi_theta_slots_and_alpha_beta():
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    X = inputs.points_for(2, 3000)
+    lt, lm, om = _setup(X, "matern32", [0.05], [0.5], 4, 9, 1e-8, 2, (3, 1))
+    thetas = np.array([[0.06], [0.2], [0.49]])
+    inst = api.Instance(lm, thetas)
+    x = inputs.normal_vectors(3000, 3 * 2, 5).T.reshape(3, 2, 3000)
+    y0 = inputs.normal_vectors(3000, 3 * 2, 6).T.reshape(3, 2, 3000)
+    xd = torch.tensor(np.ascontiguousarray(x), device="cuda")
+    yd = torch.tensor(np.ascontiguousarray(y0), device="cuda")
+    inst.matvec(xd, yd, alpha=0.7, beta=-1.3, nugget=0.25)
+    got = yd.cpu().numpy()
+    for t in range(3):
+        ref = 0.7 * om.matvec(om.instantiate(thetas[t]), x[t].T, nugget=0.25).T - 1.3 * y0[t]
+        _close(got[t], ref)
+
+
+def test_reinstantiate_in_place_and_domain_errors():
+    torch = _torch()
+    from paper_2511_03109_amd import api, _lib
+    X = inputs.points_for(1, 800)
+    lt, lm, om = _setup(X, "gaussian", [0.1], [0.5], 5, 9, 1e-8, 3, (1, 1))
+    inst = api.Instance(lm, [0.2])
+    x = torch.tensor(inputs.normal_vectors(800, 1, 1)[:, 0], device="cuda")
+    inst.reinstantiate([0.4])
+    y = inst.matvec(x).cpu().numpy()
+    _close(y, om.matvec(om.instantiate(0.4), x.cpu().numpy()))
+    with pytest.raises(_lib.PHError) as e:
+        api.Instance(lm, [0.55])
+    assert e.value.code == _lib.PH_EDOMAIN
+    # R = 0 is a no-op
+    from paper_2511_03109_amd._lib import lib
+    import ctypes as C
+    assert lib().ph_matvec(inst._h, C.c_void_p(0), C.c_void_p(0), 0, 1.0, 0.0, 0.0, None) == 0
+
+
+def test_gradient_instance_matches_oracle_and_fd():
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    X = inputs.points_for(4, 2000)
+    lt, lm, om = _setup(X, "gaussian", [0.05], [0.5], 6, 9, 1e-8, 3, (2, 1))
+    u = inputs.normal_vectors(2000, 1, 4, inputs.STREAM_U)[:, 0]
+    x = inputs.normal_vectors(2000, 1, 4)[:, 0]
+    l0 = 0.2
+    g = api.Instance(lm, [l0], grad_dim=0)
+    xd = torch.tensor(x, device="cuda")
+    dy = g.matvec(xd).cpu().numpy()
+    dy_o = om.matvec(om.instantiate(l0, deriv_dim=0), x)
+    _close(dy, dy_o)
+    h = 1e-5
+    yp = api.Instance(lm, [l0 + h]).matvec(xd).cpu().numpy()
+    ym = api.Instance(lm, [l0 - h]).matvec(xd).cpu().numpy()
+    fd = (u @ yp - u @ ym) / (2 * h)
+    assert abs(u @ dy - fd) <= 1e-7 * abs(u @ dy)
+
+
+def test_fp32_instance_error_bound():
+    """FP32 storage and arithmetic: error against the FP64 oracle within a stated 2e-6 relative bound."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    X = inputs.points_for(2, 4096)
+    lt, lm, om = _setup(X, "matern32", [0.05], [0.5], 5, 11, 1e-8, 2, (3, 1))
+    inst = api.Instance(lm, [0.3], dtype="f32")
+    x = inputs.normal_vectors(4096, 4, 9)
+    y = inst.matvec(torch.tensor(np.ascontiguousarray(x.T), device="cuda", dtype=torch.float32))
+    y_o = om.matvec(om.instantiate(0.3), x)
+    _close(y.cpu().numpy().T.astype(np.float64), y_o, 2e-6)
+
+
+def test_workload2_full_size_sampled_rows():
+    """n = 65536 uniform in [0,1]^3, Matern-3/2, 8 parameter values in one instance, 16 RHS:
+    the launch configuration of the benchmark, checked on rows of three leaves."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    w = inputs.WORKLOADS[2]
+    X = inputs.points_for(2)
+    l_max = otree.default_l_max(w["n"], w["d"], w["leaf"])
+    lt = api.Tree(X, l_max=l_max, eta2=w["eta2"])
+    lm = api.Model(lt, w["kernel"], w["theta_lo"], w["theta_hi"], p_s=w["p_s"], p_theta=w["p_theta"],
+                   tol=w["tol"])
+    thetas = inputs.theta_samples(w["T"], w["theta_lo"], w["theta_hi"], 2)
+    inst = api.Instance(lm, thetas)
+    x = inputs.normal_vectors(w["n"], w["T"] * w["R"], 2).T.reshape(w["T"], w["R"], w["n"])
+    y = inst.matvec(torch.tensor(np.ascontiguousarray(x), device="cuda")).cpu().numpy()
+    om = hmat.PH2(X, l_max=l_max, eta2=3, kernel=kernels.matern32, theta_lo=w["theta_lo"],
+                  theta_hi=w["theta_hi"], p_s=w["p_s"], p_theta=w["p_theta"], tol=w["tol"])
+    perm = lt.perm()
+    rows = np.concatenate([perm[0:5], perm[40000:40007], perm[-4:]])
+    for t in (0, 5):
+        ref = om.matvec_rows(thetas[t], x[t].T, rows)
+        _close(y[t][:, rows].T, ref)

@@ -1,0 +1,99 @@
+"""CPU tests of the native library's host logic: symbol exports and the cluster tree,
+block lists and translation classes, compared bit for bit with the oracle."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import tree as otree
+from paper_2511_03109_amd import _lib, api, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "ph.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|void|const char\*)\s+(ph_\w+)\s*\(", header, re.M))
+    assert len(declared) >= 20
+    lib = _lib.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(_lib.SIGNATURES) == declared
+    assert lib.ph_version().startswith(b"ph-mi355x")
+
+
+def _compare(X, l_max, eta2, lo=0.0, hi=1.0):
+    n, d = X.shape
+    lt = api.Tree(X, lo=lo, hi=hi, l_max=l_max, eta2=eta2)
+    ot = otree.build_cluster_tree(X, lo, hi, l_max)
+    near_o, far_o = otree.build_block_tree(ot, eta2[0] if eta2[1] == 1 else
+                                           __import__("fractions").Fraction(*eta2))
+    cls_o, bc_o = otree.translation_classes(ot, far_o)
+    assert np.array_equal(lt.perm(), ot.perm)
+    nd = lt.nodes()
+    assert nd["level"].tolist() == ot.level
+    assert [tuple(c) for c in nd["coords"].tolist()] == [tuple(c) for c in ot.coords]
+    assert nd["begin"].tolist() == ot.begin and nd["end"].tolist() == ot.end
+    assert nd["parent"].tolist() == ot.parent
+    near, far, fcls = lt.blocks()
+    assert [tuple(b) for b in near.tolist()] == near_o
+    assert [tuple(b) for b in far.tolist()] == far_o
+    assert fcls.tolist() == bc_o
+    lev, off = lt.classes()
+    assert [(int(l), tuple(o)) for l, o in zip(lev.tolist(), off.tolist())] == cls_o
+    assert lt.info["near_entries"] == sum(len(ot.idx[s]) * len(ot.idx[u]) for s, u in near_o)
+    return lt
+
+
+@pytest.mark.parametrize("wid", [1, 2])
+def test_tree_bit_exact_workload_geometry(wid):
+    w = inputs.WORKLOADS[wid]
+    n = w["n"] if wid == 1 else 8192
+    X = inputs.points_for(wid, n)
+    l_max = otree.default_l_max(n, w["d"], w["leaf"])
+    _compare(X, l_max, w["eta2"])
+
+
+def test_tree_bit_exact_mixture_uneven():
+    X = inputs.points_for(3, 4096)
+    _compare(X, 4, (2, 1))
+
+
+@pytest.mark.parametrize("d,n,l,eta2", [(1, 333, 5, (1, 1)), (2, 100, 4, (2, 1)), (3, 700, 2, (3, 1)),
+                                         (2, 50, 0, (2, 1)), (2, 1, 3, (2, 1)), (3, 500, 3, (1, 2))])
+def test_tree_bit_exact_small_and_degenerate(d, n, l, eta2):
+    X = np.random.default_rng([d, n]).random((n, d))
+    _compare(X, l, eta2)
+
+
+def test_tree_ties_on_split_planes():
+    # points on dyadic grid lines: every tie must go to the lower half, as in the oracle
+    g = np.arange(0, 9) / 8.0
+    X = np.array([(a, b) for a in g for b in g])
+    _compare(X, 3, (2, 1))
+
+
+def test_leaf_size_derivation():
+    X = inputs.points_for(1)
+    t = api.Tree(X, leaf_size=64, l_max=-1, eta2=(1, 1))
+    assert t.info["l_max"] == otree.default_l_max(2048, 2, 64) == 3
+    assert t.info["n_near"] == 1012
+
+
+@pytest.mark.parametrize("bad", ["nan", "outside", "d4", "eta"])
+def test_tree_rejects_bad_input(bad):
+    X = np.random.default_rng(0).random((10, 2))
+    kw = dict(l_max=2)
+    if bad == "nan":
+        X[3, 1] = np.nan
+    elif bad == "outside":
+        X[0, 0] = 1.5
+    elif bad == "d4":
+        X = np.random.default_rng(0).random((10, 4))
+    else:
+        kw["eta2"] = (0, 1)
+    with pytest.raises(_lib.PHError) as e:
+        api.Tree(X, **kw)
+    assert e.value.code == _lib.PH_EINVAL
