@@ -29,15 +29,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, X, l_max, thetas, x_host, sample_leaves=4):
+def cpu_baseline(w, X, l_max, thetas, x_host, sample_leaves=32):
     """Time the CPU oracle on a bounded sample of the same workload.
 
-    Sample: all rows of `sample_leaves` target leaves (spread over the tree), for one
-    theta and the workload's R right-hand sides.  Timed: near-field instantiation of
-    those leaves' near blocks, instantiation of every far coupling, the full upward
-    pass, and the coupling / near products / downward pass of those leaves' paths.
-    The per-leaf part is extrapolated linearly to all leaves; compression (offline) is
-    not timed.
+    Sample: all rows of `sample_leaves` target leaves spread over the tree, for every
+    theta of the step and the workload's R right-hand sides.  Timed per theta: the
+    parametric vectors, near-field instantiation of those leaves' near blocks,
+    instantiation of every far coupling, the full upward pass, and the coupling / near
+    products / downward pass of those leaves' paths.  The per-leaf parts are scaled
+    linearly to all leaves.  Compression (the offline stage) is not timed.
     """
     from threadpoolctl import threadpool_info
 
@@ -56,31 +56,32 @@ def cpu_baseline(w, X, l_max, thetas, x_host, sample_leaves=4):
     for b in near:
         om.near_factors(b)
     log(f"[cpu_baseline] oracle setup + compression (untimed) {time.time() - t0:.1f} s")
-    theta = thetas[0]
-    xs = x_host[0].T                     # (n, R)
-    ta = time.perf_counter()
-    vs = om.theta_vectors(theta)
-    D = {b: om.near_block(b, vs) for b in near}
-    tb = time.perf_counter()
-    C = {k: om.coupling(k, vs) for k in all_keys}
-    tc = time.perf_counter()
-    xt = xs[t.perm]
-    om._upward(xt)
-    td = time.perf_counter()
-    om.matvec_rows_inst({"D": D, "C": C}, xs, rows)
-    te = time.perf_counter()
     nleaf = len(t.leaves)
     scale = nleaf / sample_leaves
-    # matvec_rows_inst repeats the upward pass: subtract it from the per-leaf part
-    per_leaf_mvm = max((te - td) - (td - tc), 0.0)
-    est_s = (tb - ta) * scale + (tc - tb) + (td - tc) + per_leaf_mvm * scale
+    est, measured = [], 0.0
+    for ti, theta in enumerate(thetas):
+        xs = x_host[ti].T                     # (n, R)
+        ta = time.perf_counter()
+        vs = om.theta_vectors(theta)
+        D = {b: om.near_block(b, vs) for b in near}
+        tb = time.perf_counter()
+        C = {k: om.coupling(k, vs) for k in all_keys}
+        tc = time.perf_counter()
+        om._upward(xs[t.perm])
+        td = time.perf_counter()
+        om.matvec_rows_inst({"D": D, "C": C}, xs, rows)
+        te = time.perf_counter()
+        # matvec_rows_inst repeats the upward pass: subtract it from the per-leaf part
+        per_leaf_mvm = max((te - td) - (td - tc), 0.0)
+        est.append((tb - ta) * scale + (tc - tb) + (td - tc) + per_leaf_mvm * scale)
+        measured += te - ta
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     return {
-        "value": est_s * 1e3, "unit": "ms per theta (instantiate + MVM, 16 RHS), extrapolated",
+        "value": float(np.mean(est)) * 1e3, "unit": "ms per theta (instantiate + MVM, 16 RHS), extrapolated",
         "cores": int(threads), "kind": "oracle",
-        "sample": f"{sample_leaves} of {nleaf} target leaves ({len(rows)} rows, {len(near)} near blocks), "
-                  f"all {len(all_keys)} far couplings, full upward pass; per-leaf work scaled by "
-                  f"{scale:.0f}x; measured {te - ta:.2f} s",
+        "sample": f"{sample_leaves} of {nleaf} target leaves ({len(rows)} rows, {len(near)} near blocks) for "
+                  f"each of {len(thetas)} theta, all {len(all_keys)} far couplings, full upward pass; "
+                  f"per-leaf work scaled by {scale:.0f}x; measured {measured:.1f} s of oracle work",
     }
 
 
@@ -90,7 +91,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-leaves", type=int, default=4)
+    ap.add_argument("--cpu-sample-leaves", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "

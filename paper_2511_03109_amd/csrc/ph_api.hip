@@ -1,0 +1,501 @@
+// Model upload, tracing state and the C ABI of the parametric H^2 library (arxiv
+// 2511.03109) on MI355X.  The online-stage kernels live in k_instantiate.hip and the
+// MVM kernels in k_matvec.hip.
+#include <algorithm>
+#include <cstring>
+#include <map>
+
+#include "ph_device.hpp"
+
+namespace ph {
+
+static thread_local std::string g_last_error;
+
+std::mutex g_trace_mu;
+bool g_trace_on = false;
+std::vector<TraceRec> g_trace_recs;
+static std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t pooled_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  PH_HIP(hipEventCreate(&e));
+  return e;
+}
+
+// ------------------------------------------------------------------ model upload
+static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData> tp, HostModel& hm,
+                                                 hipStream_t st) {
+  const TreeData& t = *tp;
+  auto m = std::make_shared<DeviceModel>();
+  m->tree = tp;
+  m->d = hm.d; m->p_s = hm.p_s; m->P = hm.P; m->p_theta = hm.p_theta; m->d_theta = hm.d_theta;
+  m->Pp = (hm.P + 15) / 16 * 16;
+  m->nsib = 1 << hm.d;
+  m->l_max = t.l_max; m->min_far = t.min_far_level;
+  for (int k = 0; k < 2; ++k) { m->th_lo[k] = hm.th_lo[k]; m->th_hi[k] = hm.th_hi[k]; }
+  m->n = t.n; m->n_nodes = t.n_nodes(); m->n_leaves = (int64_t)t.leaves.size();
+  m->n_near = t.n_near(); m->n_classes = t.n_classes(); m->N_nf = t.near_entries;
+  m->n_stored_near = (int64_t)hm.nstore.size();
+  m->n_stored_cls = (int64_t)hm.cstore.size();
+  m->kernel_evals = hm.kernel_evals;
+  m->near_factor_entries = hm.near_factor_entries;
+
+  // canonical near D offsets
+  m->D_off_host.assign(m->n_near + 1, 0);
+  for (int64_t b = 0; b < m->n_near; ++b)
+    m->D_off_host[b + 1] = m->D_off_host[b] + t.size(t.near[2 * b]) * t.size(t.near[2 * b + 1]);
+
+  // near stored blocks and tiles
+  std::vector<NearDev> nd(hm.nstore.size());
+  std::vector<int32_t> tiles;
+  m->near_rank_canon.assign(m->n_near, -1);
+  double wsum = 0, rsum = 0;
+  for (size_t q = 0; q < hm.nstore.size(); ++q) {
+    const NearStored& s = hm.nstore[q];
+    NearDev& x = nd[q];
+    x.s_begin = s.s_begin; x.t_begin = s.t_begin;
+    x.P_off = s.P_off; x.core_off = s.core_off; x.th1_off = s.th1_off; x.th2_off = s.th2_off;
+    x.D_st = m->D_off_host[s.b_st];
+    x.D_ts = s.b_ts >= 0 ? m->D_off_host[s.b_ts] : -1;
+    x.ns = s.ns; x.nt = s.nt; x.r_e = s.r_e; x.r1 = s.r1; x.r2 = s.r2; x.pad = 0;
+    m->near_rank_canon[s.b_st] = s.r_e;
+    const double w = (double)s.ns * s.nt * (s.b_ts >= 0 ? 2 : 1);
+    wsum += w;
+    rsum += w * s.r_e;
+    m->near_rank_max = std::max(m->near_rank_max, s.r_e);
+    for (int32_t j0 = 0; j0 < s.nt; j0 += TILE)
+      for (int32_t i0 = 0; i0 < s.ns; i0 += TILE) {
+        tiles.push_back((int32_t)q);
+        tiles.push_back(i0);
+        tiles.push_back(j0);
+      }
+  }
+  m->near_rank_mean = wsum > 0 ? rsum / wsum : 0;
+  m->n_tiles = (int64_t)tiles.size() / 3;
+
+  // far classes
+  const int P = hm.P;
+  std::vector<ClassDev> cd(hm.cstore.size());
+  int64_t soff = 0;
+  double fr = 0;
+  m->class_ranks.assign(m->n_classes * (2 + hm.d_theta), 0);
+  for (size_t q = 0; q < hm.cstore.size(); ++q) {
+    const ClassStored& c = hm.cstore[q];
+    ClassDev& x = cd[q];
+    x.L_off = c.L_off; x.R_off = c.R_off; x.core_off = c.core_off;
+    x.th1_off = c.th1_off; x.th2_off = c.th2_off;
+    const int64_t Pp = m->Pp;
+    x.C_off = (int64_t)c.cls * Pp * Pp;
+    x.Cm_off = c.mirror >= 0 ? (int64_t)c.mirror * Pp * Pp : -1;
+    x.S_off = soff;
+    soff += (int64_t)c.rL * c.rR + Pp * (int64_t)((c.rL + 15) / 16 * 16);
+    x.rL = c.rL; x.r1 = c.r1; x.r2 = c.r2; x.rR = c.rR;
+    fr += 0.5 * (c.rL + c.rR);
+    m->far_rank_max = std::max({m->far_rank_max, c.rL, c.rR});
+    int32_t* cr = &m->class_ranks[(size_t)c.cls * (2 + hm.d_theta)];
+    cr[0] = c.rL; cr[1] = c.r1; if (hm.d_theta == 2) cr[2] = c.r2; cr[1 + hm.d_theta] = c.rR;
+    if (c.mirror >= 0) {
+      int32_t* mr = &m->class_ranks[(size_t)c.mirror * (2 + hm.d_theta)];
+      mr[0] = c.rR; mr[1] = c.r1; if (hm.d_theta == 2) mr[2] = c.r2; mr[1 + hm.d_theta] = c.rL;
+    }
+  }
+  m->far_rank_mean = cd.empty() ? 0 : fr / cd.size();
+  m->ff_scratch = soff;
+
+  // CSR of near blocks by target leaf (canonical list is sorted by sigma)
+  const int32_t leaf0 = t.leaves.empty() ? 0 : t.leaves.front();
+  std::vector<int64_t> nrow(m->n_leaves + 1, 0), ntb(m->n_near), nD(m->n_near);
+  std::vector<int32_t> nnt(m->n_near);
+  for (int64_t b = 0; b < m->n_near; ++b) {
+    const int32_t s = t.near[2 * b], u = t.near[2 * b + 1];
+    nrow[s - leaf0 + 1]++;
+    ntb[b] = t.begin[u];
+    nnt[b] = (int32_t)t.size(u);
+    nD[b] = m->D_off_host[b];
+  }
+  for (int64_t i = 0; i < m->n_leaves; ++i) nrow[i + 1] += nrow[i];
+  // Coupling work list.  Every node at a level >= min_far belongs to the sibling group
+  // of its parent; for each group, one entry per translation class used by any sibling,
+  // holding the source node of every sibling that uses it (-1 otherwise).
+  std::vector<int32_t> gt, gptr{0}, ecls, etau;
+  if (t.min_far_level >= 0) {
+    const int nsib = m->nsib;
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> far_of(t.n_nodes());  // node -> (tau, class)
+    for (int64_t b = 0; b < t.n_far(); ++b) far_of[t.far[2 * b]].push_back({t.far[2 * b + 1], t.far_class[b]});
+    for (int l = t.min_far_level - 1; l < t.l_max; ++l) {
+      for (int32_t par = t.level_start[l]; par < t.level_start[l + 1]; ++par) {
+        const int32_t f = t.first_child[par], nc = t.nchild[par];
+        std::vector<int32_t> slots(nsib, -1);
+        std::map<int32_t, std::vector<int32_t>> bycls;
+        for (int32_t c = 0; c < nc; ++c) {
+          const int32_t ch = f + c;
+          const int sl = t.cid[ch];
+          slots[sl] = ch;
+          for (auto& pr : far_of[ch]) {
+            auto& v = bycls[pr.second];
+            if (v.empty()) v.assign(nsib, -1);
+            v[sl] = pr.first;
+          }
+        }
+        gt.insert(gt.end(), slots.begin(), slots.end());
+        for (auto& kv : bycls) {
+          ecls.push_back(kv.first);
+          etau.insert(etau.end(), kv.second.begin(), kv.second.end());
+        }
+        gptr.push_back((int32_t)ecls.size());
+        m->max_group_entries = std::max<int64_t>(m->max_group_entries, (int64_t)bycls.size());
+      }
+    }
+  }
+  m->n_groups = (int64_t)gptr.size() - 1;
+  m->n_entries = (int64_t)ecls.size();
+
+  m->U.upload(hm.U.data(), hm.U.size(), st);
+  m->E.upload(hm.E.data(), hm.E.size(), st);
+  m->perm.upload(t.perm.data(), t.perm.size(), st);
+  m->first_child.upload(t.first_child.data(), t.first_child.size(), st);
+  m->nchild.upload(t.nchild.data(), t.nchild.size(), st);
+  m->cid.upload(t.cid.data(), t.cid.size(), st);
+  m->parent.upload(t.parent.data(), t.parent.size(), st);
+  m->nbegin.upload(t.begin.data(), t.begin.size(), st);
+  m->nend.upload(t.end.data(), t.end.size(), st);
+  m->nstore.upload(nd.data(), nd.size(), st);
+  m->nf_P.upload(hm.nf_P.data(), hm.nf_P.size(), st);
+  m->nf_core.upload(hm.nf_core.data(), hm.nf_core.size(), st);
+  m->nf_theta.upload(hm.nf_theta.data(), hm.nf_theta.size(), st);
+  m->tiles.upload(tiles.data(), tiles.size(), st);
+  m->near_rowptr.upload(nrow.data(), nrow.size(), st);
+  m->near_tb.upload(ntb.data(), ntb.size(), st);
+  m->near_D.upload(nD.data(), nD.size(), st);
+  m->near_nt.upload(nnt.data(), nnt.size(), st);
+  m->cstore.upload(cd.data(), cd.size(), st);
+  m->ff_L.upload(hm.ff_L.data(), hm.ff_L.size(), st);
+  m->ff_R.upload(hm.ff_R.data(), hm.ff_R.size(), st);
+  m->ff_core.upload(hm.ff_core.data(), hm.ff_core.size(), st);
+  m->ff_theta.upload(hm.ff_theta.data(), hm.ff_theta.size(), st);
+  m->grp_targets.upload(gt.data(), gt.size(), st);
+  m->grp_entry.upload(gptr.data(), gptr.size(), st);
+  m->ent_cls.upload(ecls.data(), ecls.size(), st);
+  m->ent_tau.upload(etau.data(), etau.size(), st);
+  PH_HIP(hipStreamSynchronize(st));  // host staging buffers die with this call
+  m->device_bytes = (int64_t)(m->U.bytes() + m->E.bytes() + m->perm.bytes() + m->first_child.bytes() +
+                              m->nchild.bytes() + m->cid.bytes() + m->parent.bytes() + m->nbegin.bytes() + m->nend.bytes() +
+                              m->nstore.bytes() + m->nf_P.bytes() + m->nf_core.bytes() +
+                              m->nf_theta.bytes() + m->tiles.bytes() + m->near_rowptr.bytes() +
+                              m->near_tb.bytes() + m->near_D.bytes() + m->near_nt.bytes() +
+                              m->cstore.bytes() + m->ff_L.bytes() + m->ff_R.bytes() +
+                              m->ff_core.bytes() + m->ff_theta.bytes() + m->grp_targets.bytes() +
+                              m->grp_entry.bytes() + m->ent_cls.bytes() + m->ent_tau.bytes());
+  return m;
+}
+
+}  // namespace ph
+
+// ====================================================================== C ABI
+struct ph_tree {
+  std::shared_ptr<const ph::TreeData> p;
+};
+struct ph_model {
+  std::shared_ptr<const ph::DeviceModel> p;
+};
+struct ph_inst {
+  std::shared_ptr<ph::InstData> p;
+};
+
+namespace {
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    ph::g_last_error.clear();
+    f();
+    return PH_OK;
+  } catch (const ph::Failure& e) {
+    ph::g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    ph::g_last_error = "host allocation failed";
+    return PH_ENOMEM;
+  } catch (const std::exception& e) {
+    ph::g_last_error = e.what();
+    return PH_EINVAL;
+  } catch (...) {
+    ph::g_last_error = "unknown failure";
+    return PH_EINVAL;
+  }
+}
+
+void need(bool ok, const char* msg) {
+  if (!ok) ph::fail(PH_EINVAL, msg);
+}
+
+int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype dt, void* stream,
+                ph_inst** inout) {
+  return guarded([&] {
+    need(m && m->p, "model is NULL");
+    need(theta != nullptr, "theta is NULL");
+    need(inout != nullptr, "inout is NULL");
+    need(T >= 1, "T must be >= 1");
+    need(dt == PH_F64 || dt == PH_F32, "dtype must be PH_F64 or PH_F32");
+    const ph::DeviceModel& md = *m->p;
+    if (dim >= 0) need(dim < md.d_theta, "gradient dimension out of range");
+    for (int t = 0; t < T; ++t)
+      for (int k = 0; k < md.d_theta; ++k) {
+        const double v = theta[(size_t)t * md.d_theta + k];
+        if (!(v >= md.th_lo[k] && v <= md.th_hi[k]))
+          ph::fail(PH_EDOMAIN, "theta outside the parameter box");
+      }
+    hipStream_t st = (hipStream_t)stream;
+    std::shared_ptr<ph::InstData> in;
+    if (*inout) {
+      in = (*inout)->p;
+      need(in && in->m.get() == &md && in->T == T && in->dt == dt,
+           "instance does not match (model, T, dtype)");
+      in->grad_dim = dim;
+    } else {
+      in = std::make_shared<ph::InstData>();
+      in->m = m->p;
+      in->T = T;
+      in->dt = dt;
+      in->grad_dim = dim;
+      in->esize = dt == PH_F64 ? sizeof(double) : sizeof(float);
+      in->D.alloc((size_t)T * md.N_nf * in->esize);
+      in->C.alloc((size_t)T * md.n_classes * md.Pp * md.Pp * in->esize);
+      in->v.alloc((size_t)T * md.d_theta * md.p_theta);
+      in->ffs.alloc((size_t)T * std::max<int64_t>(md.ff_scratch, 1));
+    }
+    if (dt == PH_F64) ph::instantiate_impl<double>(*in, theta, st);
+    else ph::instantiate_impl<float>(*in, theta, st);
+    if (!*inout) *inout = new ph_inst{in};
+  });
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ph_last_error(void) { return ph::g_last_error.c_str(); }
+
+const char* ph_version(void) { return "ph-mi355x 0.1 (gfx950)"; }
+
+int ph_build_tree(const double* pts, int64_t n, const ph_tree_opts* opts, ph_tree** out) {
+  return guarded([&] {
+    need(opts != nullptr && out != nullptr, "opts or out is NULL");
+    auto t = ph::build_tree(pts, n, *opts);
+    *out = new ph_tree{t};
+  });
+}
+
+int ph_tree_info_get(const ph_tree* t, ph_tree_info* info) {
+  return guarded([&] {
+    need(t && t->p && info, "NULL argument");
+    const ph::TreeData& d = *t->p;
+    info->n = d.n;
+    info->d = d.d;
+    info->l_max = d.l_max;
+    info->n_nodes = d.n_nodes();
+    info->n_leaves = (int64_t)d.leaves.size();
+    info->n_near = d.n_near();
+    info->n_far = d.n_far();
+    info->n_classes = d.n_classes();
+    info->near_entries = d.near_entries;
+    info->min_far_level = d.min_far_level;
+  });
+}
+
+int ph_tree_perm(const ph_tree* t, int64_t* perm) {
+  return guarded([&] {
+    need(t && t->p && perm, "NULL argument");
+    std::memcpy(perm, t->p->perm.data(), t->p->perm.size() * sizeof(int64_t));
+  });
+}
+
+int ph_tree_nodes(const ph_tree* t, int32_t* level, int32_t* coords, int64_t* begin, int64_t* end,
+                  int32_t* parent) {
+  return guarded([&] {
+    need(t && t->p, "NULL tree");
+    const ph::TreeData& d = *t->p;
+    const size_t nn = (size_t)d.n_nodes();
+    if (level) std::memcpy(level, d.level.data(), nn * sizeof(int32_t));
+    if (coords) std::memcpy(coords, d.coords.data(), nn * d.d * sizeof(int32_t));
+    if (begin) std::memcpy(begin, d.begin.data(), nn * sizeof(int64_t));
+    if (end) std::memcpy(end, d.end.data(), nn * sizeof(int64_t));
+    if (parent) std::memcpy(parent, d.parent.data(), nn * sizeof(int32_t));
+  });
+}
+
+int ph_tree_blocks(const ph_tree* t, int32_t* near, int32_t* far, int32_t* far_class) {
+  return guarded([&] {
+    need(t && t->p, "NULL tree");
+    const ph::TreeData& d = *t->p;
+    if (near) std::memcpy(near, d.near.data(), d.near.size() * sizeof(int32_t));
+    if (far) std::memcpy(far, d.far.data(), d.far.size() * sizeof(int32_t));
+    if (far_class) std::memcpy(far_class, d.far_class.data(), d.far_class.size() * sizeof(int32_t));
+  });
+}
+
+int ph_tree_classes(const ph_tree* t, int32_t* level, int32_t* offset) {
+  return guarded([&] {
+    need(t && t->p, "NULL tree");
+    const ph::TreeData& d = *t->p;
+    if (level) std::memcpy(level, d.class_level.data(), d.class_level.size() * sizeof(int32_t));
+    if (offset) std::memcpy(offset, d.class_off.data(), d.class_off.size() * sizeof(int32_t));
+  });
+}
+
+void ph_tree_free(ph_tree* t) { delete t; }
+
+int ph_offline_compress(const ph_tree* t, const ph_offline_opts* opts, void* stream, ph_model** out) {
+  return guarded([&] {
+    need(t && t->p && opts && out, "NULL argument");
+    auto hm = ph::offline_host(*t->p, *opts);
+    auto dm = ph::upload_model(t->p, *hm, (hipStream_t)stream);
+    *out = new ph_model{dm};
+  });
+}
+
+int ph_model_info_get(const ph_model* m, ph_model_info* info) {
+  return guarded([&] {
+    need(m && m->p && info, "NULL argument");
+    const ph::DeviceModel& d = *m->p;
+    info->n = d.n;
+    info->n_near_stored = d.n_stored_near;
+    info->n_classes_stored = d.n_stored_cls;
+    info->near_entries = d.N_nf;
+    info->near_factor_entries = d.near_factor_entries;
+    info->near_rank_mean = d.near_rank_mean;
+    info->near_rank_max = d.near_rank_max;
+    info->far_rank_mean = d.far_rank_mean;
+    info->far_rank_max = d.far_rank_max;
+    info->device_bytes = d.device_bytes;
+    info->kernel_evals = d.kernel_evals;
+    info->P = d.P;
+    info->p_theta = d.p_theta;
+    info->d_theta = d.d_theta;
+  });
+}
+
+int ph_model_near_ranks(const ph_model* m, int32_t* ranks) {
+  return guarded([&] {
+    need(m && m->p && ranks, "NULL argument");
+    std::memcpy(ranks, m->p->near_rank_canon.data(), m->p->near_rank_canon.size() * sizeof(int32_t));
+  });
+}
+
+int ph_model_class_ranks(const ph_model* m, int32_t* ranks) {
+  return guarded([&] {
+    need(m && m->p && ranks, "NULL argument");
+    std::memcpy(ranks, m->p->class_ranks.data(), m->p->class_ranks.size() * sizeof(int32_t));
+  });
+}
+
+void ph_model_free(ph_model* m) { delete m; }
+
+int ph_instantiate(const ph_model* m, const double* theta, int T, ph_dtype dt, void* stream,
+                   ph_inst** inout) {
+  return inst_common(m, theta, T, -1, dt, stream, inout);
+}
+
+int ph_instantiate_grad(const ph_model* m, const double* theta, int T, int dim, ph_dtype dt, void* stream,
+                        ph_inst** inout) {
+  if (dim < 0) {
+    ph::g_last_error = "gradient dimension out of range";
+    return PH_EINVAL;
+  }
+  return inst_common(m, theta, T, dim, dt, stream, inout);
+}
+
+int ph_matvec(ph_inst* k, const void* x, void* y, int64_t R, double alpha, double beta, double nugget,
+              void* stream) {
+  return guarded([&] {
+    need(k && k->p, "instance is NULL");
+    need(R >= 0, "R must be >= 0");
+    if (R == 0) return;
+    need(x && y, "x or y is NULL");
+    ph::InstData& in = *k->p;
+    hipStream_t st = (hipStream_t)stream;
+    if (in.dt == PH_F64)
+      ph::matvec_impl<double>(in, (const double*)x, (double*)y, R, alpha, beta, nugget, st);
+    else
+      ph::matvec_impl<float>(in, (const float*)x, (float*)y, R, alpha, beta, nugget, st);
+  });
+}
+
+int ph_inst_near_block(const ph_inst* k, int t, int64_t b, double* host_out) {
+  return guarded([&] {
+    need(k && k->p && host_out, "NULL argument");
+    const ph::InstData& in = *k->p;
+    const ph::DeviceModel& m = *in.m;
+    need(t >= 0 && t < in.T, "slot out of range");
+    need(b >= 0 && b < m.n_near, "near block index out of range");
+    const int64_t off = m.D_off_host[b], cnt = m.D_off_host[b + 1] - off;
+    PH_HIP(hipDeviceSynchronize());
+    std::vector<char> buf(cnt * in.esize);
+    PH_HIP(hipMemcpy(buf.data(), in.D.p + ((size_t)t * m.N_nf + off) * in.esize, buf.size(),
+                     hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < cnt; ++i)
+      host_out[i] = in.dt == PH_F64 ? ((double*)buf.data())[i] : (double)((float*)buf.data())[i];
+  });
+}
+
+int ph_inst_coupling(const ph_inst* k, int t, int64_t c, double* host_out) {
+  return guarded([&] {
+    need(k && k->p && host_out, "NULL argument");
+    const ph::InstData& in = *k->p;
+    const ph::DeviceModel& m = *in.m;
+    need(t >= 0 && t < in.T, "slot out of range");
+    need(c >= 0 && c < m.n_classes, "class index out of range");
+    const int64_t cnt = (int64_t)m.Pp * m.Pp;
+    PH_HIP(hipDeviceSynchronize());
+    std::vector<char> buf(cnt * in.esize);
+    PH_HIP(hipMemcpy(buf.data(), in.C.p + ((size_t)t * m.n_classes * cnt + c * cnt) * in.esize, buf.size(),
+                     hipMemcpyDeviceToHost));
+    for (int j = 0; j < m.P; ++j)
+      for (int i = 0; i < m.P; ++i) {
+        const int64_t src = i + (int64_t)m.Pp * j;
+        host_out[i + (int64_t)m.P * j] =
+            in.dt == PH_F64 ? ((double*)buf.data())[src] : (double)((float*)buf.data())[src];
+      }
+  });
+}
+
+void ph_inst_free(ph_inst* k) { delete k; }
+
+int ph_trace_enable(int on) {
+  return guarded([&] {
+    std::lock_guard<std::mutex> lk(ph::g_trace_mu);
+    ph::g_trace_on = on != 0;
+  });
+}
+
+int ph_trace_read(ph_trace_stats* out, int reset) {
+  return guarded([&] {
+    need(out != nullptr, "out is NULL");
+    std::lock_guard<std::mutex> lk(ph::g_trace_mu);
+    for (int i = 0; i < PH_NUM_STAGES; ++i) {
+      out->ms[i] = 0;
+      out->count[i] = 0;
+    }
+    for (auto& r : ph::g_trace_recs) {
+      PH_HIP(hipEventSynchronize(r.b));
+      float ms = 0;
+      PH_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      out->ms[r.stage] += ms;
+      out->count[r.stage] += 1;
+    }
+    if (reset) {
+      for (auto& r : ph::g_trace_recs) {
+        ph::g_event_pool.push_back(r.a);
+        ph::g_event_pool.push_back(r.b);
+      }
+      ph::g_trace_recs.clear();
+    }
+  });
+}
+
+}  // extern "C"
