@@ -92,7 +92,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-leaves", type=int, default=32)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes 5 times (to scale "
+                         "profiler byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(args.copy_calibration // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_calibration, "repeats": 5}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(multi-GPU sharding is described in the design notes, not built)"}))
@@ -151,7 +164,7 @@ def main():
                         "ms_avg": stats.ms[i] / max(stats.count[i], 1)}
                  for i, name in enumerate(_lib.STAGES)}
     inst_ms = sum(per_stage[k]["ms_total"] for k in ("theta", "far_inst", "near_inst")) / args.steps
-    mvm_ms = sum(per_stage[k]["ms_total"] for k in _lib.STAGES[3:]) / args.steps
+    mvm_ms = sum(per_stage[k]["ms_total"] for k in _lib.STAGES[3:]) / args.steps  # sum of kernel times (streams overlap)
 
     # algorithmic bytes of one near-field instantiation launch (all T slots):
     # each stored factor entry P_b[k][e] read once, each near-block entry written once per slot

@@ -242,10 +242,11 @@ enum {
   PH_STAGE_TRANSFER_UP = 5,   /* FastForward, inner nodes */
   PH_STAGE_COUPLING = 6,      /* y_hat += C x_hat over far blocks */
   PH_STAGE_TRANSFER_DOWN = 7, /* FastBackward, inner nodes */
-  PH_STAGE_LEAF_NEAR = 8,     /* FastBackward leaves + near-field products */
+  PH_STAGE_NEAR_MVM = 8,      /* near-field products y_s = sum_t D_st x_t */
   PH_STAGE_PERM_OUT = 9,
-  PH_STAGE_ZERO = 10,
-  PH_NUM_STAGES = 11
+  PH_STAGE_ZERO = 10,         /* reduction of split coupling partial sums */
+  PH_STAGE_LEAF_DOWN = 11,    /* FastBackward, leaves */
+  PH_NUM_STAGES = 12
 };
 typedef struct {
   double ms[16];

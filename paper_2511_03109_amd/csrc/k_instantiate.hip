@@ -47,7 +47,8 @@ __global__ void k_theta_vectors(ThetaPack tp, double* __restrict__ v, int t0) {
 //   w_k = Theta_k^T v_k;  H = core x_theta w  (r_L x r_R, global scratch);
 //   St = (H R^T)^T, i.e. St[j + Pp a] = sum_b R[j, b] H[a, b]     (MFMA, M = j, N = a, K = b);
 //   C[i + Pp j] = sum_a L[i, a] St[j + Pp a]                     (MFMA, M = i, N = j, K = a);
-// the mirrored class receives C^T.  All Pp x Pp entries are written (zero padding).
+// the mirrored class receives C^T.  All Pp x Pp entries are written (zero padding), in
+// fragment order (frag_index).
 template <typename S>
 __global__ void __launch_bounds__(NT) k_far_instantiate(
     const ClassDev* __restrict__ cls, const double* __restrict__ L, const double* __restrict__ R,
@@ -58,7 +59,8 @@ __global__ void __launch_bounds__(NT) k_far_instantiate(
   __shared__ double w1[16], w2[16];
   const ClassDev c = cls[blockIdx.x];
   const int t = blockIdx.y;
-  const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+  const int lane = threadIdx.x % WAVE;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const double* vt = v + (size_t)t * dth * p;
   for (int a = threadIdx.x; a < c.r1; a += blockDim.x) {
     double s = 0;
@@ -124,8 +126,8 @@ __global__ void __launch_bounds__(NT) k_far_instantiate(
       }
       for (int q = 0; q < 4; ++q) {
         const int row = it * 16 + MF::row(lane, q);
-        Ct[c.C_off + row + (size_t)Pp * j] = (S)acc[q];
-        if (c.Cm_off >= 0) Ct[c.Cm_off + j + (size_t)Pp * row] = (S)acc[q];
+        Ct[c.C_off + frag_index(row, j, Pp)] = (S)acc[q];
+        if (c.Cm_off >= 0) Ct[c.Cm_off + frag_index(j, row, Pp)] = (S)acc[q];
       }
     }
   }
@@ -144,7 +146,7 @@ __global__ void __launch_bounds__(NT) k_near_instantiate(
   __shared__ double tile[TILE][TILE + 1];
   const int32_t bi = tiles[3 * blockIdx.x], i0 = tiles[3 * blockIdx.x + 1], j0 = tiles[3 * blockIdx.x + 2];
   const NearDev b = blocks[bi];
-  const int64_t Ne = (int64_t)b.ns * b.nt;
+  const int64_t Nep = (int64_t)b.ldp * b.nt;                     // padded factor column length
   const int ti = threadIdx.x % TILE, tj0 = threadIdx.x / TILE;   // 8 rows of 32
   const int i = i0 + ti;
   constexpr int NQ = TILE / (NT / TILE);                          // 4 entries per thread
@@ -182,16 +184,18 @@ __global__ void __launch_bounds__(NT) k_near_instantiate(
     for (int tt = 0; tt < TC; ++tt)
       for (int q = 0; q < NQ; ++q) acc[tt][q] = 0.0;
     bool ok[NQ];
-    int64_t e[NQ];
+    int64_t e[NQ], ed[NQ];
     for (int q = 0; q < NQ; ++q) {
       const int j = j0 + tj0 + q * (NT / TILE);
       ok[q] = i < b.ns && j < b.nt;
-      e[q] = ok[q] ? i + (int64_t)j * b.ns : 0;
+      e[q] = ok[q] ? i + (int64_t)j * b.ldp : 0;
+      ed[q] = ok[q] ? i + (int64_t)j * b.lds : 0;
     }
     const double* pb = Pf + b.P_off;
-    for (int k = 0; k < b.r_e; ++k) {
+    int k = 0;
+    for (; k < b.r_e; ++k) {
       double pv[NQ];
-      for (int q = 0; q < NQ; ++q) pv[q] = ok[q] ? pb[(size_t)k * Ne + e[q]] : 0.0;
+      for (int q = 0; q < NQ; ++q) pv[q] = ok[q] ? pb[(size_t)k * Nep + e[q]] : 0.0;
 #pragma unroll
       for (int tt = 0; tt < TC; ++tt) {
         const double cv = cc[tt][k];
@@ -203,7 +207,7 @@ __global__ void __launch_bounds__(NT) k_near_instantiate(
       if (tt >= tc) break;
       S* Dt = D + (size_t)(t0 + tt) * D_per_slot;
       for (int q = 0; q < NQ; ++q)
-        if (ok[q]) Dt[b.D_st + e[q]] = (S)acc[tt][q];
+        if (ok[q]) Dt[b.D_st + ed[q]] = (S)acc[tt][q];
       if (b.D_ts >= 0) {
         __syncthreads();
         for (int q = 0; q < NQ; ++q) tile[tj0 + q * (NT / TILE)][ti] = acc[tt][q];
@@ -212,7 +216,7 @@ __global__ void __launch_bounds__(NT) k_near_instantiate(
         const int jj = j0 + ti;
         for (int q = 0; q < NQ; ++q) {
           const int ii = i0 + tj0 + q * (NT / TILE);
-          if (ii < b.ns && jj < b.nt) Dt[b.D_ts + jj + (int64_t)ii * b.nt] = (S)tile[ti][tj0 + q * (NT / TILE)];
+          if (ii < b.ns && jj < b.nt) Dt[b.D_ts + jj + (int64_t)ii * b.ldt] = (S)tile[ti][tj0 + q * (NT / TILE)];
         }
       }
     }
@@ -244,7 +248,7 @@ void instantiate_impl(InstData& in, const double* theta, hipStream_t st) {
   launch(PH_STAGE_NEAR_INST, k_near_instantiate<S>, dim3((unsigned)m.n_tiles), dim3(NT), st,
          (const NearDev*)m.nstore.p, (const int32_t*)m.tiles.p, (const double*)m.nf_P.p,
          (const double*)m.nf_core.p, (const double*)m.nf_theta.p, (const double*)in.v.p, (S*)in.D.p,
-         m.N_nf, in.T, m.p_theta, m.d_theta);
+         m.N_nf_pad, in.T, m.p_theta, m.d_theta);
 }
 
 template void instantiate_impl<double>(InstData&, const double*, hipStream_t);

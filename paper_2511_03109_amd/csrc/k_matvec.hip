@@ -2,37 +2,42 @@
 // FastForward / FastBackward; coupling y_hat_s += C_b x_hat_t as in Alg. "Modified
 // H^2-Matrix MVM"), for all parameter slots of an instance in one pass.
 //
-// Scratch layouts (S = double or float):
-//   xt, yt   [T][n][R]             tree order, R fastest
-//   xh, yh   [T][nodes][Pp][R]     P padded to Pp (multiple of 16) with zero rows
-//   part     [G][T][nodes][Pp][R]  coupling partial sums when the class list is split
+// Scratch layouts (S = double or float; Rs = R rounded up to a multiple of 16, the
+// padding columns hold zeros):
+//   xt, yt   [T][n][Rs]             tree order, right-hand side fastest
+//   xh, yh   [T][nodes][Pp][Rs]     P padded to Pp (multiple of 16) with zero rows
+//   part     [G][T][nodes][Pp][Rs]  coupling partial sums when the class list is split
+#include <cstdlib>
+#include <type_traits>
+
 #include "ph_device.hpp"
 
 namespace ph {
 
-// xt[slot][t][r] = x[slot][r][perm[t]]
+// xt[slot][t][r] = x[slot][r][perm[t]] (0 for the padding columns r >= R)
 template <typename S>
 __global__ void k_perm_in(const S* __restrict__ x, S* __restrict__ xt, const int64_t* __restrict__ perm,
-                          int64_t n, int64_t R, int64_t total) {
+                          int64_t n, int64_t R, int64_t Rs, int64_t total) {
   for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total;
        o += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t slot = o / (n * R), rem = o % (n * R);
-    const int64_t t = rem / R, r = rem % R;
-    xt[o] = x[slot * n * R + r * n + perm[t]];
+    const int64_t slot = o / (n * Rs), rem = o % (n * Rs);
+    const int64_t t = rem / Rs, r = rem % Rs;
+    xt[o] = r < R ? x[slot * n * R + r * n + perm[t]] : (S)0;
   }
 }
 
 // y[slot][r][perm[t]] = alpha (yt + nugget xt) + beta y
 template <typename S>
 __global__ void k_perm_out(S* __restrict__ y, const S* __restrict__ yt, const S* __restrict__ xt,
-                           const int64_t* __restrict__ perm, int64_t n, int64_t R, int64_t total, double alpha,
-                           double beta, double nugget) {
+                           const int64_t* __restrict__ perm, int64_t n, int64_t R, int64_t Rs, int64_t total,
+                           double alpha, double beta, double nugget) {
   for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total;
        o += (int64_t)gridDim.x * blockDim.x) {
     const int64_t slot = o / (n * R), rem = o % (n * R);
     const int64_t t = rem / R, r = rem % R;
+    const int64_t src = (slot * n + t) * Rs + r;
     const int64_t dst = slot * n * R + r * n + perm[t];
-    double val = alpha * ((double)yt[o] + nugget * (double)xt[o]);
+    double val = alpha * ((double)yt[src] + nugget * (double)xt[src]);
     if (beta != 0.0) val += beta * (double)y[dst];
     y[dst] = (S)val;
   }
@@ -53,7 +58,8 @@ __global__ void __launch_bounds__(NT) k_leaf_up(const S* __restrict__ xt, S* __r
   const int32_t s = leaf0 + blockIdx.x;
   const int r0 = blockIdx.y * RC;
   const int64_t slot = blockIdx.z;
-  const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+  const int lane = threadIdx.x % WAVE;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int m16 = lane & 15, kq = lane >> 4;
   const int64_t b = nbegin[s], ns = nend[s] - b;
   const int dps = d * ps, nMt = Pp / 16;
@@ -215,65 +221,168 @@ __global__ void __launch_bounds__(NT) k_transfer_down(S* __restrict__ yh, const 
 }
 
 // Coupling y_hat_s = sum over far blocks (s, t) of C_class x_hat_t on the matrix cores.
-// One workgroup per (sibling group, class chunk, RHS tile, slot): the 2^d children of
-// one parent share most translation classes, so each C_class fragment loaded from
-// L2 / Infinity Cache feeds up to 2^d MFMAs.  Wave w owns row tiles w and w + 4 of the
-// Pp x 16 outputs.  With G > 1 chunks the outputs are partial sums.
-template <typename S, int NSIB>
-__global__ void __launch_bounds__(NT) k_coupling(
+// One workgroup of NW wavefronts per (class chunk g, target box, RHS tile, slot); a box
+// holds NTG nodes of one level and its work list has one entry per translation class,
+// so each C_class panel staged in LDS feeds the MFMAs of every target in the box that
+// uses the class.  The class list of every box is cut into G chunks and g is the fastest
+// grid index: with G = 8, chunk g of every box lands on XCD g (workgroups are dealt to the
+// 8 XCDs round robin), so each XCD's L2 serves about one eighth of the classes.
+// Pipeline: stage = (entry, 16-wide K panel).  C is stored in fragment order (frag_index),
+// so a stage of C is one contiguous Pp x 16 panel, copied with 16-byte loads; the x_hat
+// rows of each used target are copied the same way.  Global loads run PD stages ahead in
+// registers, LDS is double buffered, one barrier per stage.  Entry metadata (class,
+// sources) is wave-uniform and read with scalar loads.  Waves form a WR x (NW / WR) grid:
+// wave (wr, wt) owns row tiles wr + WR j (j < TPW) of targets wt NTW .. wt NTW + NTW - 1;
+// FULL: the row tiles are exactly Pp / 16 (no tile test).
+template <typename S, int NW, int WR, int TPW, int PD, bool FULL>
+__global__ void __launch_bounds__(NW * 64) k_coupling(
     const S* __restrict__ xh, S* __restrict__ out, const S* __restrict__ C,
     const int32_t* __restrict__ grp_targets, const int32_t* __restrict__ grp_entry,
-    const int32_t* __restrict__ ent_cls, const int32_t* __restrict__ ent_tau, int Pp, int64_t nodes,
-    int64_t R, int G, int64_t Cps, int64_t part_stride, int T) {
-  typedef Mfma<S> MF;
-  const int grp = blockIdx.x;
-  const int g = blockIdx.y % G;
-  const int r0 = (blockIdx.y / G) * RC;
+    const int32_t* __restrict__ ent_cls, const int32_t* __restrict__ ent_tau,
+    const int32_t* __restrict__ ent_wpre, const int32_t* __restrict__ grp_w, int Pp, int64_t nodes,
+    int64_t Rs, int G, int64_t Cps, int64_t part_stride, int n_groups) {
+  typedef Tile16<S> MF;
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  constexpr int NTH = NW * 64;
+  constexpr int WT = NW / WR, NTW = NTG / WT, MT = WR * TPW;
+  constexpr int KC = 16;                        // K rows per stage
+  constexpr int EPU = 16 / (int)sizeof(S);      // elements per 16-byte unit
+  constexpr int AU = (MT * 256 / EPU + NTH - 1) / NTH;   // C units per thread per stage
+  constexpr int TSW = NTG / NW;                 // targets staged per wave
+  constexpr int BUT = 256 / EPU / 64;           // x_hat units per lane per target
+  static_assert(NTG % WT == 0 && NTG % NW == 0 && BUT >= 1, "work split");
+  __shared__ __attribute__((aligned(16))) S As[2][MT * 256];
+  __shared__ __attribute__((aligned(16))) S Bs[2][NTG][256];
+  const int g = blockIdx.x;
+  const int grp = blockIdx.y % n_groups;
+  const int r0 = (blockIdx.y / n_groups) * RC;
   const int64_t slot = blockIdx.z;
-  const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
-  const int m16 = lane & 15, kq = lane >> 4;
+  const int lane = threadIdx.x % WAVE;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int wr = wave % WR, wt = wave / WR;
   const int nMt = Pp / 16;
-  const bool t0ok = wave < nMt, t1ok = wave + 4 < nMt;
-  const bool colok = r0 + m16 < R;
-  typename MF::acc_t acc[NSIB][2];
+  const int a_units = Pp * KC / EPU;
+  typename MF::acc_t acc[NTW][TPW];
 #pragma unroll
-  for (int s = 0; s < NSIB; ++s) {
-    acc[s][0] = (typename MF::acc_t){0, 0, 0, 0};
-    acc[s][1] = (typename MF::acc_t){0, 0, 0, 0};
-  }
+  for (int s = 0; s < NTW; ++s)
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) acc[s][j] = (typename MF::acc_t){0, 0, 0, 0};
+  // chunk g = the entries whose work prefix lies in [W g / G, W (g + 1) / G)
   const int e_begin = grp_entry[grp], e_end = grp_entry[grp + 1];
-  const int ne = e_end - e_begin;
-  const int ea = e_begin + (int)((int64_t)ne * g / G), eb = e_begin + (int)((int64_t)ne * (g + 1) / G);
-  const S* xs = xh + slot * nodes * Pp * R;
-  const S* Cs = C + slot * Cps;
-  for (int e = ea; e < eb; ++e) {
-    const S* Cc = Cs + (int64_t)ent_cls[e] * Pp * Pp;
-    int tau[NSIB];
+  const int64_t W = grp_w[grp];
+  auto first_at = [&](int64_t lim) {   // first entry of the box with prefix >= lim
+    int lo = e_begin, hi = e_end;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (ent_wpre[mid] < lim) lo = mid + 1;
+      else hi = mid;
+    }
+    return lo;
+  };
+  const int ea = first_at((W * g + G - 1) / G), eb = first_at((W * (g + 1) + G - 1) / G);
+  // raw buffer views of this slot's x_hat and C: an offset past the end reads zeros
+  // without touching memory (targets that do not use an entry's class)
+  const __amdgpu_buffer_rsrc_t xrs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(xh + slot * nodes * Pp * Rs), (short)0, (int)(nodes * Pp * Rs * (int64_t)sizeof(S)), BUF_WORD3);
+  const __amdgpu_buffer_rsrc_t crs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(C + slot * Cps), (short)0, (int)(Cps * (int64_t)sizeof(S)), BUF_WORD3);
+  const int nk = Pp / KC;
+  const int nsteps = (eb - ea) * nk;
+  constexpr int A_LDS_UNITS = MT * 256 / EPU;
+  u4 areg[PD][AU], breg[PD][TSW][BUT];
+  // every load and LDS store below is unconditional (clamped stage, out-of-range offsets),
+  // so the compiler tracks each register's pending load exactly and waits only at stash
+  auto fetch = [&](int step, int rb) {
+    const int e = ea + step / nk, kc = step % nk;
+    const int cbase = (ent_cls[e] * Pp * Pp + kc * Pp * KC) * (int)sizeof(S);
 #pragma unroll
-    for (int s = 0; s < NSIB; ++s) tau[s] = ent_tau[(int64_t)e * NSIB + s];
-    for (int k0 = 0; k0 < Pp; k0 += 4) {
-      const int k = k0 + kq;
-      const S a0 = t0ok ? Cc[(wave * 16 + m16) + (int64_t)Pp * k] : (S)0;
-      const S a1 = t1ok ? Cc[((wave + 4) * 16 + m16) + (int64_t)Pp * k] : (S)0;
+    for (int q = 0; q < AU; ++q) {
+      const int u = threadIdx.x + q * NTH;
+      const int off = (FULL || u < a_units) ? cbase + u * 16 : BUF_OOB;
+      areg[rb][q] = __builtin_amdgcn_raw_buffer_load_b128(crs, off, 0, 0);
+    }
 #pragma unroll
-      for (int s = 0; s < NSIB; ++s) {
-        if (tau[s] < 0) continue;
-        const S bv = colok ? xs[((int64_t)tau[s] * Pp + k) * R + r0 + m16] : (S)0;
-        if (t0ok) acc[s][0] = MF::mac(a0, bv, acc[s][0]);
-        if (t1ok) acc[s][1] = MF::mac(a1, bv, acc[s][1]);
+    for (int q = 0; q < TSW; ++q) {
+      const int tv = ent_tau[e * NTG + wave * TSW + q];
+      const int base = ((tv * Pp + kc * KC) * (int)Rs + r0) * (int)sizeof(S);
+#pragma unroll
+      for (int h = 0; h < BUT; ++h) {
+        const int u = lane + 64 * h;
+        const int rel = ((u / (RC / EPU)) * (int)Rs + (u % (RC / EPU)) * EPU) * (int)sizeof(S);
+        breg[rb][q][h] = __builtin_amdgcn_raw_buffer_load_b128(xrs, tv >= 0 ? base + rel : BUF_OOB, 0, 0);
       }
     }
-  }
-  if (!colok) return;
-  S* o = out + (int64_t)g * part_stride + slot * nodes * Pp * R;
+  };
+  auto stash = [&](int rb, int buf) {
 #pragma unroll
-  for (int s = 0; s < NSIB; ++s) {
-    const int32_t node = grp_targets[grp * NSIB + s];
+    for (int q = 0; q < AU; ++q) {
+      const int u = threadIdx.x + q * NTH;
+      if (u < A_LDS_UNITS) reinterpret_cast<u4*>(As[buf])[u] = areg[rb][q];
+    }
+#pragma unroll
+    for (int q = 0; q < TSW; ++q)
+#pragma unroll
+      for (int h = 0; h < BUT; ++h) reinterpret_cast<u4*>(Bs[buf][wave * TSW + q])[lane + 64 * h] = breg[rb][q][h];
+  };
+  // one stage: prefetch stage st + PD into ring slot RF, multiply from LDS buffer BUF,
+  // store stage st + 1 (ring slot RS) into the other LDS buffer
+  auto body = [&](int st, auto BUF, auto RF, auto RS) {
+    constexpr int buf = decltype(BUF)::value;
+    fetch(min(st + PD, nsteps - 1), decltype(RF)::value);
+    const int e = ea + st / nk;
+    bool use[NTW];
+#pragma unroll
+    for (int s = 0; s < NTW; ++s) use[s] = ent_tau[e * NTG + wt * NTW + s] >= 0;
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const int k = kk + (lane >> 4);
+      typename MF::a_t a[TPW];
+      S bv[NTW];
+#pragma unroll
+      for (int j = 0; j < TPW; ++j) {
+        const int mt = wr + WR * j;
+        if (FULL || mt < nMt) a[j] = MF::load_tiled(&As[buf][mt * 256 + k * 16], lane);
+      }
+#pragma unroll
+      for (int s = 0; s < NTW; ++s) bv[s] = Bs[buf][wt * NTW + s][k * 16 + (lane & 15)];
+#pragma unroll
+      for (int s = 0; s < NTW; ++s) {
+        if (!use[s]) continue;
+#pragma unroll
+        for (int j = 0; j < TPW; ++j)
+          if (FULL || wr + WR * j < nMt) acc[s][j] = MF::mac(a[j], bv[s], acc[s][j]);
+      }
+    }
+    stash(decltype(RS)::value, buf ^ 1);
+    __syncthreads();
+  };
+  typedef std::integral_constant<int, 0> I0;
+  typedef std::integral_constant<int, 1> I1;
+  typedef std::integral_constant<int, 1 % PD> R1;
+  if (nsteps > 0) {
+    fetch(0, 0);
+    stash(0, 0);
+    if (PD == 2) fetch(min(1, nsteps - 1), 1 % PD);
+  }
+  __syncthreads();
+  // stages in pairs, so that LDS buffers and register ring slots are compile-time
+#pragma unroll 1
+  for (int st = 0; st < nsteps; st += 2) {
+    body(st, I0(), I0(), R1());
+    if (st + 1 < nsteps) body(st + 1, I1(), R1(), I0());
+  }
+  S* o = out + (int64_t)g * part_stride + slot * nodes * Pp * Rs;
+#pragma unroll
+  for (int s = 0; s < NTW; ++s) {
+    const int32_t node = grp_targets[grp * NTG + wt * NTW + s];
     if (node < 0) continue;
-    S* on = o + (int64_t)node * Pp * R;
-    for (int q = 0; q < 4; ++q) {
-      if (t0ok) on[(int64_t)(wave * 16 + MF::row(lane, q)) * R + r0 + m16] = acc[s][0][q];
-      if (t1ok) on[(int64_t)((wave + 4) * 16 + MF::row(lane, q)) * R + r0 + m16] = acc[s][1][q];
+    S* on = o + (int64_t)node * Pp * Rs + r0 + (lane & 15);
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+      const int mt = wr + WR * j;
+      if (!FULL && mt >= nMt) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) on[(int64_t)(mt * 16 + MF::row(lane, q)) * Rs] = acc[s][j][q];
     }
   }
 }
@@ -293,82 +402,76 @@ __global__ void k_coupling_reduce(S* __restrict__ yh, const S* __restrict__ part
   }
 }
 
-// Near field and the leaf step of FastBackward on the matrix cores, one workgroup per
-// (leaf s, RHS tile, slot):
-//   y_s = sum_{near t} D_st x_t + U_s y_hat_s
-// M = rows of the leaf (row tiles w, w + 4 per wave, in chunks of 128 rows),
-// K = columns of each near block, then the Chebyshev multi-index for U_s y_hat_s.
+// Near field on the matrix cores, one workgroup per (leaf s, RHS tile, slot):
+//   y_s = sum_{near t} D_st x_t        (writes y_s)
+// M = rows of the leaf (row tiles w, w + 4 per wave, in chunks of 128 rows), K = the
+// columns of each near block; each A fragment is 16 consecutive rows of one column of
+// D (one aligned 128-byte line).  The (block, 16-column group) sequence is software
+// pipelined: the next group's D and x values are loaded while the current one feeds
+// the MFMAs.
 template <typename S>
-__global__ void __launch_bounds__(NT) k_leaf_near(
-    const S* __restrict__ xt, S* __restrict__ yt, const S* __restrict__ yh, const S* __restrict__ D,
-    const double* __restrict__ U, const int64_t* __restrict__ nbegin, const int64_t* __restrict__ nend,
-    const int64_t* __restrict__ rowptr, const int64_t* __restrict__ ntb, const int32_t* __restrict__ nnt,
-    const int64_t* __restrict__ nD, int32_t leaf0, int use_far, int d, int ps, int P, int Pp, int64_t n,
-    int64_t nodes, int64_t R, int64_t N_nf) {
+__global__ void __launch_bounds__(NT) k_near_mvm(
+    const S* __restrict__ xt, S* __restrict__ yt, const S* __restrict__ D, const int64_t* __restrict__ nbegin,
+    const int64_t* __restrict__ nend, const int64_t* __restrict__ rowptr, const int64_t* __restrict__ ntb,
+    const int32_t* __restrict__ nnt, const int64_t* __restrict__ nD, int32_t leaf0, int64_t n, int64_t R,
+    int64_t N_nf) {
   typedef Mfma<S> MF;
   constexpr int CH = 128;
-  __shared__ double Us[CH * 22];
   const int32_t li = blockIdx.x;
   const int32_t s = leaf0 + li;
   const int r0 = blockIdx.y * RC;
   const int64_t slot = blockIdx.z;
-  const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+  const int lane = threadIdx.x % WAVE;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int m16 = lane & 15, kq = lane >> 4;
   const int64_t b = nbegin[s], ns = nend[s] - b;
-  const int dps = d * ps;
+  const int64_t ld = (ns + 15) / 16 * 16;   // leading dimension of this leaf's row blocks
   const bool colok = r0 + m16 < R;
   const S* xs = xt + slot * n * R;
   const S* Ds = D + slot * N_nf;
-  const S* yhs = yh + (slot * nodes + s) * Pp * R;
   const int64_t bb0 = rowptr[li], bb1 = rowptr[li + 1];
   for (int64_t c0 = 0; c0 < ns; c0 += CH) {
     const int cn = (int)min<int64_t>(CH, ns - c0);
-    if (use_far) {
-      __syncthreads();
-      for (int q = threadIdx.x; q < cn * dps; q += NT) Us[q] = U[(b + c0) * dps + q];
-      __syncthreads();
-    }
     const int i0 = wave * 16 + m16, i1 = (wave + 4) * 16 + m16;   // rows within the chunk
     const bool t0ok = wave * 16 < cn, t1ok = (wave + 4) * 16 < cn;
     const bool r0ok = i0 < cn, r1ok = i1 < cn;
     typename MF::acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    for (int64_t bb = bb0; bb < bb1; ++bb) {
-      const S* Db = Ds + nD[bb] + c0;
-      const int64_t tb = ntb[bb];
-      const int nt = nnt[bb];
-#pragma unroll 4
-      for (int k0 = 0; k0 < nt; k0 += 4) {
-        const int j = k0 + kq;
+    // pipeline state: block bb, column group kb (16 columns = 4 MFMA K-steps)
+    int64_t bb = bb0;
+    int kb = 0;
+    S a0n[4], a1n[4], bn[4];
+    auto fetch = [&](int64_t fb, int fk) {
+      const S* Db = Ds + nD[fb] + c0;
+      const int64_t tb = ntb[fb];
+      const int nt = nnt[fb];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = fk * 16 + u * 4 + kq;
         const bool jok = j < nt;
-        const S bv = (jok && colok) ? xs[(tb + j) * R + r0 + m16] : (S)0;
-        const S a0 = (jok && r0ok) ? Db[i0 + (int64_t)j * ns] : (S)0;
-        const S a1 = (jok && r1ok) ? Db[i1 + (int64_t)j * ns] : (S)0;
-        if (t0ok) acc0 = MF::mac(a0, bv, acc0);
-        if (t1ok) acc1 = MF::mac(a1, bv, acc1);
+        bn[u] = (jok && colok) ? xs[(tb + j) * R + r0 + m16] : (S)0;
+        a0n[u] = (jok && r0ok) ? Db[i0 + (int64_t)j * ld] : (S)0;
+        a1n[u] = (jok && r1ok) ? Db[i1 + (int64_t)j * ld] : (S)0;
       }
-    }
-    if (use_far) {
-      for (int k0 = 0; k0 < Pp; k0 += 4) {
-        const int ii = k0 + kq;
-        const bool iok = ii < P;
-        const S bv = (iok && colok) ? yhs[(int64_t)ii * R + r0 + m16] : (S)0;
-        int dg[3];
-        int rem = ii;
-        for (int k = 0; k < 3; ++k) {
-          dg[k] = rem % ps;
-          rem /= ps;
-        }
-        double u0 = 0.0, u1 = 0.0;
-        if (iok && r0ok) {
-          u0 = Us[m16 * 0 + (wave * 16 + m16) * dps + dg[0]];
-          for (int k = 1; k < d; ++k) u0 *= Us[(wave * 16 + m16) * dps + k * ps + dg[k]];
-        }
-        if (iok && r1ok) {
-          u1 = Us[((wave + 4) * 16 + m16) * dps + dg[0]];
-          for (int k = 1; k < d; ++k) u1 *= Us[((wave + 4) * 16 + m16) * dps + k * ps + dg[k]];
-        }
-        if (t0ok) acc0 = MF::mac((S)u0, bv, acc0);
-        if (t1ok) acc1 = MF::mac((S)u1, bv, acc1);
+    };
+    if (bb < bb1) fetch(bb, kb);
+    while (bb < bb1) {
+      S a0[4], a1[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a0[u] = a0n[u];
+        a1[u] = a1n[u];
+        bv[u] = bn[u];
+      }
+      ++kb;
+      if (kb * 16 >= nnt[bb]) {
+        ++bb;
+        kb = 0;
+      }
+      if (bb < bb1) fetch(bb, kb);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (t0ok) acc0 = MF::mac(a0[u], bv[u], acc0);
+        if (t1ok) acc1 = MF::mac(a1[u], bv[u], acc1);
       }
     }
     if (colok) {
@@ -382,22 +485,97 @@ __global__ void __launch_bounds__(NT) k_leaf_near(
   }
 }
 
+// FastBackward, leaves: y_s += U_s y_hat_s on the matrix cores, one workgroup per
+// (leaf, RHS tile, slot); U_s[i, i'] = prod_k U_k[i][i'_k] formed from factor rows in LDS.
+template <typename S>
+__global__ void __launch_bounds__(NT) k_leaf_down(S* __restrict__ yt, const S* __restrict__ yh,
+                                                  const double* __restrict__ U,
+                                                  const int64_t* __restrict__ nbegin,
+                                                  const int64_t* __restrict__ nend, int32_t leaf0, int d,
+                                                  int ps, int P, int Pp, int64_t n, int64_t nodes, int64_t R) {
+  typedef Mfma<S> MF;
+  constexpr int CH = 128;
+  __shared__ double Us[CH * 22];
+  const int32_t s = leaf0 + blockIdx.x;
+  const int r0 = blockIdx.y * RC;
+  const int64_t slot = blockIdx.z;
+  const int lane = threadIdx.x % WAVE;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int m16 = lane & 15, kq = lane >> 4;
+  const int64_t b = nbegin[s], ns = nend[s] - b;
+  const int dps = d * ps;
+  const bool colok = r0 + m16 < R;
+  const S* yhs = yh + (slot * nodes + s) * Pp * R;
+  S* ys = yt + slot * n * R;
+  for (int64_t c0 = 0; c0 < ns; c0 += CH) {
+    const int cn = (int)min<int64_t>(CH, ns - c0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < cn * dps; q += NT) Us[q] = U[(b + c0) * dps + q];
+    __syncthreads();
+    const int i0 = wave * 16 + m16, i1 = (wave + 4) * 16 + m16;
+    const bool t0ok = wave * 16 < cn, t1ok = (wave + 4) * 16 < cn;
+    const bool r0ok = i0 < cn, r1ok = i1 < cn;
+    typename MF::acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < Pp; k0 += 4) {
+      const int ii = k0 + kq;
+      const bool iok = ii < P;
+      const S bv = (iok && colok) ? yhs[(int64_t)ii * R + r0 + m16] : (S)0;
+      int dg[3];
+      int rem = ii;
+      for (int k = 0; k < 3; ++k) {
+        dg[k] = rem % ps;
+        rem /= ps;
+      }
+      double u0 = 0.0, u1 = 0.0;
+      if (iok && r0ok) {
+        u0 = Us[i0 * dps + dg[0]];
+        for (int k = 1; k < d; ++k) u0 *= Us[i0 * dps + k * ps + dg[k]];
+      }
+      if (iok && r1ok) {
+        u1 = Us[i1 * dps + dg[0]];
+        for (int k = 1; k < d; ++k) u1 *= Us[i1 * dps + k * ps + dg[k]];
+      }
+      if (t0ok) acc0 = MF::mac((S)u0, bv, acc0);
+      if (t1ok) acc1 = MF::mac((S)u1, bv, acc1);
+    }
+    if (colok) {
+      for (int q = 0; q < 4; ++q) {
+        const int ra = wave * 16 + MF::row(lane, q), rb = (wave + 4) * 16 + MF::row(lane, q);
+        if (t0ok && ra < cn) {
+          S* p = ys + (b + c0 + ra) * R + r0 + m16;
+          *p = *p + acc0[q];
+        }
+        if (t1ok && rb < cn) {
+          S* p = ys + (b + c0 + rb) * R + r0 + m16;
+          *p = *p + acc1[q];
+        }
+      }
+    }
+  }
+}
+
 template <typename S>
 void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double beta, double nugget,
                  hipStream_t st) {
   const DeviceModel& m = *in.m;
   const TreeData& t = *m.tree;
   const int64_t T = in.T;
-  const int64_t nrc = (R + RC - 1) / RC;
+  const int64_t Rs = rhs_stride(R);
+  const int64_t nrc = Rs / RC;
   const bool use_far = m.min_far >= 0;
-  // split the class list when the sibling groups alone give too few workgroups
+  // class-list chunks per target box: 8 (one per XCD) unless the lists are too short;
+  // PH_COUPLING_CHUNKS overrides (tuning)
   int G = 1;
-  if (use_far && m.n_groups > 0) {
-    const int64_t wgs = m.n_groups * nrc * T;
-    while (G < 16 && wgs * G < 1024 && m.max_group_entries >= 2 * G) G *= 2;
+  if (use_far && m.n_groups > 0) G = m.max_group_entries >= 16 ? 8 : (m.max_group_entries >= 4 ? 2 : 1);
+  if (const char* env = std::getenv("PH_COUPLING_CHUNKS")) {
+    const int g = std::atoi(env);
+    if (g >= 1 && g <= 64 && g <= std::max<int64_t>(m.max_group_entries, 1)) G = g;
   }
-  if (R > in.Rcap || G > in.Gcap) {
-    const int64_t Rc = std::max<int64_t>(R, in.Rcap);
+  // PH_SERIAL_MVM=1 runs the near field on the caller's stream (no overlap; profiling)
+  const bool serial = std::getenv("PH_SERIAL_MVM") && std::atoi(std::getenv("PH_SERIAL_MVM")) != 0;
+  hipStream_t nst = serial ? st : in.aux;
+  if (Rs > in.Rcap || G > in.Gcap) {
+    const int64_t Rc = std::max<int64_t>(Rs, in.Rcap);
     const int Gc = std::max(G, in.Gcap);
     in.xt.alloc((size_t)T * m.n * Rc * sizeof(S));
     in.yt.alloc((size_t)T * m.n * Rc * sizeof(S));
@@ -407,43 +585,70 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     in.Rcap = Rc;
     in.Gcap = Gc;
   }
+  if (use_far && (m.n_nodes * m.Pp * Rs * (int64_t)sizeof(S) > BUF_MAX_BYTES ||
+                  m.n_classes * m.Pp * m.Pp * (int64_t)sizeof(S) > BUF_MAX_BYTES))
+    fail(PH_EUNSUPPORTED, "ph_matvec: per-slot coupling buffers exceed 2 GiB (reduce R)");
   S* xt = (S*)in.xt.p;
   S* yt = (S*)in.yt.p;
   S* xh = (S*)in.xh.p;
   S* yh = (S*)in.yh.p;
   const int32_t leaf0 = t.leaves.front();
   const int64_t Cps = m.n_classes * m.Pp * m.Pp;
-  const int64_t total = T * m.n * R;
-  launch(PH_STAGE_PERM_IN, k_perm_in<S>, dim3((unsigned)grid_for(total)), dim3(NT), st, x, xt,
-         (const int64_t*)m.perm.p, m.n, R, total);
+  const int64_t total_in = T * m.n * Rs;
+  launch(PH_STAGE_PERM_IN, k_perm_in<S>, dim3((unsigned)grid_for(total_in)), dim3(NT), st, x, xt,
+         (const int64_t*)m.perm.p, m.n, R, Rs, total_in);
+  // The near field (HBM-bound) runs on the instance's second stream, concurrently with
+  // the far-field chain (matrix-core bound) on the caller's stream.
+  if (!serial) {
+    PH_HIP(hipEventRecord(in.ev_fork, st));
+    PH_HIP(hipStreamWaitEvent(in.aux, in.ev_fork, 0));
+  }
+  launch(PH_STAGE_NEAR_MVM, k_near_mvm<S>, dim3((unsigned)m.n_leaves, (unsigned)nrc, (unsigned)T), dim3(NT),
+         nst, (const S*)xt, yt, (const S*)in.D.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
+         (const int64_t*)m.near_rowptr.p, (const int64_t*)m.near_tb.p, (const int32_t*)m.near_nt.p,
+         (const int64_t*)m.near_D.p, leaf0, m.n, Rs, m.N_nf_pad);
+  if (!serial) PH_HIP(hipEventRecord(in.ev_join, in.aux));
   if (use_far) {
     launch(PH_STAGE_LEAF_UP, k_leaf_up<S>, dim3((unsigned)m.n_leaves, (unsigned)nrc, (unsigned)T), dim3(NT),
            st, (const S*)xt, xh, (const double*)m.U.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
-           leaf0, m.d, m.p_s, m.P, m.Pp, m.n, m.n_nodes, R);
+           leaf0, m.d, m.p_s, m.P, m.Pp, m.n, m.n_nodes, Rs);
     for (int l = m.l_max - 1; l >= m.min_far; --l) {
       const int32_t a = t.level_start[l], b = t.level_start[l + 1];
       launch(PH_STAGE_TRANSFER_UP, k_transfer_up<S>, dim3((unsigned)(b - a), (unsigned)nrc, (unsigned)T),
              dim3(NT), st, xh, (const double*)m.E.p, (const int32_t*)m.first_child.p,
-             (const int32_t*)m.nchild.p, (const int32_t*)m.cid.p, a, m.d, m.p_s, m.P, m.Pp, m.n_nodes, R);
+             (const int32_t*)m.nchild.p, (const int32_t*)m.cid.p, a, m.d, m.p_s, m.P, m.Pp, m.n_nodes, Rs);
     }
-    const int64_t part_stride = T * m.n_nodes * m.Pp * R;
+    const int64_t part_stride = T * m.n_nodes * m.Pp * Rs;
     S* cout = G > 1 ? (S*)in.part.p : yh;
-    dim3 cg((unsigned)m.n_groups, (unsigned)(G * nrc), (unsigned)T);
-    if (m.nsib == 2)
-      launch(PH_STAGE_COUPLING, k_coupling<S, 2>, cg, dim3(NT), st, (const S*)xh, cout, (const S*)in.C.p,
+    dim3 cg((unsigned)G, (unsigned)(m.n_groups * nrc), (unsigned)T);
+    auto run = [&](auto kern, int nw) {
+      launch(PH_STAGE_COUPLING, kern, cg, dim3(64 * nw), st, (const S*)xh, cout, (const S*)in.C.p,
              (const int32_t*)m.grp_targets.p, (const int32_t*)m.grp_entry.p, (const int32_t*)m.ent_cls.p,
-             (const int32_t*)m.ent_tau.p, m.Pp, m.n_nodes, R, G, Cps, part_stride, (int)T);
-    else if (m.nsib == 4)
-      launch(PH_STAGE_COUPLING, k_coupling<S, 4>, cg, dim3(NT), st, (const S*)xh, cout, (const S*)in.C.p,
-             (const int32_t*)m.grp_targets.p, (const int32_t*)m.grp_entry.p, (const int32_t*)m.ent_cls.p,
-             (const int32_t*)m.ent_tau.p, m.Pp, m.n_nodes, R, G, Cps, part_stride, (int)T);
-    else
-      launch(PH_STAGE_COUPLING, k_coupling<S, 8>, cg, dim3(NT), st, (const S*)xh, cout, (const S*)in.C.p,
-             (const int32_t*)m.grp_targets.p, (const int32_t*)m.grp_entry.p, (const int32_t*)m.ent_cls.p,
-             (const int32_t*)m.ent_tau.p, m.Pp, m.n_nodes, R, G, Cps, part_stride, (int)T);
+             (const int32_t*)m.ent_tau.p, (const int32_t*)m.ent_wpre.p, (const int32_t*)m.grp_w.p, m.Pp,
+             m.n_nodes, Rs, G, Cps, part_stride, (int)m.n_groups);
+    };
+    // 8 waves (4 row groups x 2 target halves) for Pp > 64, else 4 waves over the targets;
+    // PH_COUPLING_PD selects the register prefetch depth (1 or 2)
+    int pd = 1;
+    if (const char* env = std::getenv("PH_COUPLING_PD")) pd = std::atoi(env) == 2 ? 2 : 1;
+    const int nMt = m.Pp / 16;
+    if (nMt == 8) {
+      if (pd == 2) run(k_coupling<S, 8, 4, 2, 2, true>, 8);
+      else run(k_coupling<S, 8, 4, 2, 1, true>, 8);
+    } else if (nMt > 4) {
+      run(k_coupling<S, 8, 4, 2, 1, false>, 8);
+    } else if (nMt == 4) {
+      run(k_coupling<S, 4, 1, 4, 1, true>, 4);
+    } else if (nMt == 3) {
+      run(k_coupling<S, 4, 1, 3, 1, true>, 4);
+    } else if (nMt == 2) {
+      run(k_coupling<S, 4, 1, 2, 1, true>, 4);
+    } else {
+      run(k_coupling<S, 4, 1, 1, 1, true>, 4);
+    }
     if (G > 1) {
       const int64_t a0 = t.level_start[m.min_far];
-      const int64_t node_elems = (int64_t)m.Pp * R;
+      const int64_t node_elems = (int64_t)m.Pp * Rs;
       const int64_t rtotal = T * (m.n_nodes - a0) * node_elems;
       launch(PH_STAGE_ZERO, k_coupling_reduce<S>, dim3((unsigned)grid_for(rtotal)), dim3(NT), st, yh,
              (const S*)in.part.p, G, part_stride, node_elems, a0, m.n_nodes, rtotal);
@@ -452,16 +657,17 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
       const int32_t a = t.level_start[l + 1], b = t.level_start[l + 2];
       launch(PH_STAGE_TRANSFER_DOWN, k_transfer_down<S>, dim3((unsigned)(b - a), (unsigned)nrc, (unsigned)T),
              dim3(NT), st, yh, (const double*)m.E.p, (const int32_t*)m.parent.p, (const int32_t*)m.cid.p, a,
-             m.d, m.p_s, m.P, m.Pp, m.n_nodes, R);
+             m.d, m.p_s, m.P, m.Pp, m.n_nodes, Rs);
     }
   }
-  launch(PH_STAGE_LEAF_NEAR, k_leaf_near<S>, dim3((unsigned)m.n_leaves, (unsigned)nrc, (unsigned)T), dim3(NT),
-         st, (const S*)xt, yt, (const S*)yh, (const S*)in.D.p, (const double*)m.U.p,
-         (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p, (const int64_t*)m.near_rowptr.p,
-         (const int64_t*)m.near_tb.p, (const int32_t*)m.near_nt.p, (const int64_t*)m.near_D.p, leaf0,
-         use_far ? 1 : 0, m.d, m.p_s, m.P, m.Pp, m.n, m.n_nodes, R, m.N_nf);
-  launch(PH_STAGE_PERM_OUT, k_perm_out<S>, dim3((unsigned)grid_for(total)), dim3(NT), st, y, (const S*)yt,
-         (const S*)xt, (const int64_t*)m.perm.p, m.n, R, total, alpha, beta, nugget);
+  if (!serial) PH_HIP(hipStreamWaitEvent(st, in.ev_join, 0));
+  if (use_far)
+    launch(PH_STAGE_LEAF_DOWN, k_leaf_down<S>, dim3((unsigned)m.n_leaves, (unsigned)nrc, (unsigned)T),
+           dim3(NT), st, yt, (const S*)yh, (const double*)m.U.p, (const int64_t*)m.nbegin.p,
+           (const int64_t*)m.nend.p, leaf0, m.d, m.p_s, m.P, m.Pp, m.n, m.n_nodes, Rs);
+  const int64_t total_out = T * m.n * R;
+  launch(PH_STAGE_PERM_OUT, k_perm_out<S>, dim3((unsigned)grid_for(total_out)), dim3(NT), st, y, (const S*)yt,
+         (const S*)xt, (const int64_t*)m.perm.p, m.n, R, Rs, total_out, alpha, beta, nugget);
 }
 
 template void matvec_impl<double>(InstData&, const double*, double*, int64_t, double, double, double,

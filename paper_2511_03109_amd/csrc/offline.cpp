@@ -519,8 +519,10 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
   }
   {
     size_t totP = 0, totC = 0, totT = 0;
-    for (const Tucker& tk : ntuck) {
-      totP += tk.factors[0].size();
+    for (int64_t bi = 0; bi < nst; ++bi) {
+      const Tucker& tk = ntuck[bi];
+      const NearStored& b = m->nstore[bi];
+      totP += (size_t)((b.ns + 15) / 16 * 16) * b.nt * tk.ranks[0];
       totC += tk.core.size();
       for (size_t f = 1; f < tk.factors.size(); ++f) totT += tk.factors[f].size();
     }
@@ -534,9 +536,19 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
     b.r_e = tk.ranks[0];
     b.r1 = tk.ranks[1];
     b.r2 = dth == 2 ? tk.ranks[2] : 1;
+    // rank-outer [k][i + j ldp] with the pair index padded to a leading dimension that is a
+    // multiple of 16 entries, so every column starts on a 128-byte boundary
+    b.ldp = (b.ns + 15) / 16 * 16;
     b.P_off = (int64_t)m->nf_P.size();
-    // rank-outer: the column-major N_e x r_e factor is already [k][e]
-    m->nf_P.insert(m->nf_P.end(), tk.factors[0].begin(), tk.factors[0].end());
+    {
+      const int64_t Ne = (int64_t)b.ns * b.nt, Nep = (int64_t)b.ldp * b.nt;
+      m->nf_P.resize(m->nf_P.size() + (size_t)Nep * b.r_e, 0.0);
+      double* dst = m->nf_P.data() + b.P_off;
+      for (int k = 0; k < b.r_e; ++k)
+        for (int32_t j = 0; j < b.nt; ++j)
+          std::memcpy(dst + k * Nep + (int64_t)j * b.ldp, tk.factors[0].data() + k * Ne + (int64_t)j * b.ns,
+                      sizeof(double) * b.ns);
+    }
     m->near_factor_entries += (int64_t)b.ns * b.nt * b.r_e;
     b.core_off = (int64_t)m->nf_core.size();
     m->nf_core.insert(m->nf_core.end(), tk.core.begin(), tk.core.end());

@@ -35,7 +35,6 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   m->tree = tp;
   m->d = hm.d; m->p_s = hm.p_s; m->P = hm.P; m->p_theta = hm.p_theta; m->d_theta = hm.d_theta;
   m->Pp = (hm.P + 15) / 16 * 16;
-  m->nsib = 1 << hm.d;
   m->l_max = t.l_max; m->min_far = t.min_far_level;
   for (int k = 0; k < 2; ++k) { m->th_lo[k] = hm.th_lo[k]; m->th_hi[k] = hm.th_hi[k]; }
   m->n = t.n; m->n_nodes = t.n_nodes(); m->n_leaves = (int64_t)t.leaves.size();
@@ -48,7 +47,8 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   // canonical near D offsets
   m->D_off_host.assign(m->n_near + 1, 0);
   for (int64_t b = 0; b < m->n_near; ++b)
-    m->D_off_host[b + 1] = m->D_off_host[b] + t.size(t.near[2 * b]) * t.size(t.near[2 * b + 1]);
+    m->D_off_host[b + 1] = m->D_off_host[b] + (t.size(t.near[2 * b]) + 15) / 16 * 16 * t.size(t.near[2 * b + 1]);
+  m->N_nf_pad = m->D_off_host[m->n_near];
 
   // near stored blocks and tiles
   std::vector<NearDev> nd(hm.nstore.size());
@@ -62,7 +62,8 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
     x.P_off = s.P_off; x.core_off = s.core_off; x.th1_off = s.th1_off; x.th2_off = s.th2_off;
     x.D_st = m->D_off_host[s.b_st];
     x.D_ts = s.b_ts >= 0 ? m->D_off_host[s.b_ts] : -1;
-    x.ns = s.ns; x.nt = s.nt; x.r_e = s.r_e; x.r1 = s.r1; x.r2 = s.r2; x.pad = 0;
+    x.ns = s.ns; x.nt = s.nt; x.r_e = s.r_e; x.r1 = s.r1; x.r2 = s.r2;
+    x.ldp = s.ldp; x.lds = (s.ns + 15) / 16 * 16; x.ldt = (s.nt + 15) / 16 * 16;
     m->near_rank_canon[s.b_st] = s.r_e;
     const double w = (double)s.ns * s.nt * (s.b_ts >= 0 ? 2 : 1);
     wsum += w;
@@ -119,37 +120,77 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
     nD[b] = m->D_off_host[b];
   }
   for (int64_t i = 0; i < m->n_leaves; ++i) nrow[i + 1] += nrow[i];
-  // Coupling work list.  Every node at a level >= min_far belongs to the sibling group
-  // of its parent; for each group, one entry per translation class used by any sibling,
-  // holding the source node of every sibling that uses it (-1 otherwise).
-  std::vector<int32_t> gt, gptr{0}, ecls, etau;
+  // Coupling work list.  The nodes of every level >= min_far are cut into boxes of NTG = 16
+  // nodes (4 x 2 x 2 in 3-D, 4 x 4 in 2-D, 16 in 1-D, axis 1 longest); neighbouring
+  // targets share most translation classes, so one coupling matrix fetched for a box
+  // serves several targets.  For each box, one entry per class used by any of its nodes,
+  // holding the source node of every target that uses it (-1 otherwise), classes ascending.
+  std::vector<int32_t> gt, gptr{0}, ecls, etau, ewpre, gw;
+  struct Box {
+    std::vector<int32_t> targets, cls, tau, w;
+    int64_t wsum = 0;
+  };
+  std::vector<Box> boxes_all;
   if (t.min_far_level >= 0) {
-    const int nsib = m->nsib;
+    static const int box_bits[4][3] = {{0, 0, 0}, {4, 0, 0}, {2, 2, 0}, {2, 1, 1}};
+    const int* bits = box_bits[t.d];
     std::vector<std::vector<std::pair<int32_t, int32_t>>> far_of(t.n_nodes());  // node -> (tau, class)
     for (int64_t b = 0; b < t.n_far(); ++b) far_of[t.far[2 * b]].push_back({t.far[2 * b + 1], t.far_class[b]});
-    for (int l = t.min_far_level - 1; l < t.l_max; ++l) {
-      for (int32_t par = t.level_start[l]; par < t.level_start[l + 1]; ++par) {
-        const int32_t f = t.first_child[par], nc = t.nchild[par];
-        std::vector<int32_t> slots(nsib, -1);
+    for (int l = t.min_far_level; l <= t.l_max; ++l) {
+      std::map<std::vector<int32_t>, std::vector<int32_t>> boxes;   // box coordinates -> NTG slots
+      for (int32_t v = t.level_start[l]; v < t.level_start[l + 1]; ++v) {
+        std::vector<int32_t> key(t.d);
+        int slot = 0, shift = 0;
+        for (int k = 0; k < t.d; ++k) {
+          const int32_t c = t.coords[(size_t)v * t.d + k];
+          key[k] = c >> bits[k];
+          slot |= (c & ((1 << bits[k]) - 1)) << shift;
+          shift += bits[k];
+        }
+        auto& slots = boxes[key];
+        if (slots.empty()) slots.assign(NTG, -1);
+        slots[slot] = v;
+      }
+      for (auto& bx : boxes) {
         std::map<int32_t, std::vector<int32_t>> bycls;
-        for (int32_t c = 0; c < nc; ++c) {
-          const int32_t ch = f + c;
-          const int sl = t.cid[ch];
-          slots[sl] = ch;
-          for (auto& pr : far_of[ch]) {
-            auto& v = bycls[pr.second];
-            if (v.empty()) v.assign(nsib, -1);
-            v[sl] = pr.first;
+        for (int sl = 0; sl < NTG; ++sl) {
+          const int32_t v = bx.second[sl];
+          if (v < 0) continue;
+          for (auto& pr : far_of[v]) {
+            auto& e = bycls[pr.second];
+            if (e.empty()) e.assign(NTG, -1);
+            e[sl] = pr.first;
           }
         }
-        gt.insert(gt.end(), slots.begin(), slots.end());
+        Box b;
+        b.targets = bx.second;
         for (auto& kv : bycls) {
-          ecls.push_back(kv.first);
-          etau.insert(etau.end(), kv.second.begin(), kv.second.end());
+          int act = 0;
+          for (int32_t v : kv.second) act += v >= 0;
+          b.cls.push_back(kv.first);
+          b.tau.insert(b.tau.end(), kv.second.begin(), kv.second.end());
+          b.w.push_back(coupling_entry_weight(act));
+          b.wsum += b.w.back();
         }
-        gptr.push_back((int32_t)ecls.size());
-        m->max_group_entries = std::max<int64_t>(m->max_group_entries, (int64_t)bycls.size());
+        boxes_all.push_back(std::move(b));
       }
+    }
+    // heaviest boxes first: workgroups are dispatched in grid order, so the short ones
+    // fill the end of the launch
+    std::stable_sort(boxes_all.begin(), boxes_all.end(),
+                     [](const Box& a, const Box& b) { return a.wsum > b.wsum; });
+    for (const Box& b : boxes_all) {
+      gt.insert(gt.end(), b.targets.begin(), b.targets.end());
+      int32_t pre = 0;
+      for (size_t e = 0; e < b.cls.size(); ++e) {
+        ecls.push_back(b.cls[e]);
+        ewpre.push_back(pre);
+        pre += b.w[e];
+      }
+      etau.insert(etau.end(), b.tau.begin(), b.tau.end());
+      gptr.push_back((int32_t)ecls.size());
+      gw.push_back(pre);
+      m->max_group_entries = std::max<int64_t>(m->max_group_entries, (int64_t)b.cls.size());
     }
   }
   m->n_groups = (int64_t)gptr.size() - 1;
@@ -182,6 +223,8 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   m->grp_entry.upload(gptr.data(), gptr.size(), st);
   m->ent_cls.upload(ecls.data(), ecls.size(), st);
   m->ent_tau.upload(etau.data(), etau.size(), st);
+  m->ent_wpre.upload(ewpre.data(), ewpre.size(), st);
+  m->grp_w.upload(gw.data(), gw.size(), st);
   PH_HIP(hipStreamSynchronize(st));  // host staging buffers die with this call
   m->device_bytes = (int64_t)(m->U.bytes() + m->E.bytes() + m->perm.bytes() + m->first_child.bytes() +
                               m->nchild.bytes() + m->cid.bytes() + m->parent.bytes() + m->nbegin.bytes() + m->nend.bytes() +
@@ -190,7 +233,8 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
                               m->near_tb.bytes() + m->near_D.bytes() + m->near_nt.bytes() +
                               m->cstore.bytes() + m->ff_L.bytes() + m->ff_R.bytes() +
                               m->ff_core.bytes() + m->ff_theta.bytes() + m->grp_targets.bytes() +
-                              m->grp_entry.bytes() + m->ent_cls.bytes() + m->ent_tau.bytes());
+                              m->grp_entry.bytes() + m->ent_cls.bytes() + m->ent_tau.bytes() +
+                              m->ent_wpre.bytes() + m->grp_w.bytes());
   return m;
 }
 
@@ -264,10 +308,13 @@ int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype
       in->dt = dt;
       in->grad_dim = dim;
       in->esize = dt == PH_F64 ? sizeof(double) : sizeof(float);
-      in->D.alloc((size_t)T * md.N_nf * in->esize);
+      in->D.alloc((size_t)T * md.N_nf_pad * in->esize);
       in->C.alloc((size_t)T * md.n_classes * md.Pp * md.Pp * in->esize);
       in->v.alloc((size_t)T * md.d_theta * md.p_theta);
       in->ffs.alloc((size_t)T * std::max<int64_t>(md.ff_scratch, 1));
+      PH_HIP(hipStreamCreateWithFlags(&in->aux, hipStreamNonBlocking));
+      PH_HIP(hipEventCreateWithFlags(&in->ev_fork, hipEventDisableTiming));
+      PH_HIP(hipEventCreateWithFlags(&in->ev_join, hipEventDisableTiming));
     }
     if (dt == PH_F64) ph::instantiate_impl<double>(*in, theta, st);
     else ph::instantiate_impl<float>(*in, theta, st);
@@ -434,12 +481,17 @@ int ph_inst_near_block(const ph_inst* k, int t, int64_t b, double* host_out) {
     need(t >= 0 && t < in.T, "slot out of range");
     need(b >= 0 && b < m.n_near, "near block index out of range");
     const int64_t off = m.D_off_host[b], cnt = m.D_off_host[b + 1] - off;
+    const ph::TreeData& tr = *m.tree;
+    const int64_t ns = tr.size(tr.near[2 * b]), nt = tr.size(tr.near[2 * b + 1]), ld = (ns + 15) / 16 * 16;
     PH_HIP(hipDeviceSynchronize());
     std::vector<char> buf(cnt * in.esize);
-    PH_HIP(hipMemcpy(buf.data(), in.D.p + ((size_t)t * m.N_nf + off) * in.esize, buf.size(),
+    PH_HIP(hipMemcpy(buf.data(), in.D.p + ((size_t)t * m.N_nf_pad + off) * in.esize, buf.size(),
                      hipMemcpyDeviceToHost));
-    for (int64_t i = 0; i < cnt; ++i)
-      host_out[i] = in.dt == PH_F64 ? ((double*)buf.data())[i] : (double)((float*)buf.data())[i];
+    for (int64_t j = 0; j < nt; ++j)
+      for (int64_t i = 0; i < ns; ++i) {
+        const int64_t src = i + j * ld;
+        host_out[i + j * ns] = in.dt == PH_F64 ? ((double*)buf.data())[src] : (double)((float*)buf.data())[src];
+      }
   });
 }
 
@@ -457,7 +509,7 @@ int ph_inst_coupling(const ph_inst* k, int t, int64_t c, double* host_out) {
                      hipMemcpyDeviceToHost));
     for (int j = 0; j < m.P; ++j)
       for (int i = 0; i < m.P; ++i) {
-        const int64_t src = i + (int64_t)m.Pp * j;
+        const int64_t src = ph::frag_index(i, j, m.Pp);
         host_out[i + (int64_t)m.P * j] =
             in.dt == PH_F64 ? ((double*)buf.data())[src] : (double)((float*)buf.data())[src];
       }

@@ -53,9 +53,11 @@ struct DevArr {
 };
 
 // per stored near block (s <= t)
+// (leading dimensions: ldp of the stored factor columns, lds / ldt of the instantiated
+// (s, t) / (t, s) blocks; all are the row counts rounded up to a multiple of 16)
 struct NearDev {
   int64_t s_begin, t_begin, P_off, core_off, th1_off, th2_off, D_st, D_ts;
-  int32_t ns, nt, r_e, r1, r2, pad;
+  int32_t ns, nt, r_e, r1, r2, ldp, lds, ldt;
 };
 
 // per stored far class (offset >= 0 lexicographically)
@@ -70,12 +72,13 @@ constexpr int TILE = 32;   // near-field instantiation tile edge
 constexpr int TC = 8;      // parameter slots processed together by the near-field kernel
 constexpr int MAXT = 64;   // parameter values per theta-vector launch
 constexpr int RC = 16;     // right-hand sides per MFMA column tile
+constexpr int NTG = 16;    // coupling targets per work group (one box of nodes of a level)
 
 struct DeviceModel {
   std::shared_ptr<const TreeData> tree;
-  int d = 0, p_s = 0, P = 0, Pp = 0, p_theta = 0, d_theta = 0, l_max = 0, min_far = -1, nsib = 0;
+  int d = 0, p_s = 0, P = 0, Pp = 0, p_theta = 0, d_theta = 0, l_max = 0, min_far = -1;
   double th_lo[2] = {0, 0}, th_hi[2] = {0, 0};
-  int64_t n = 0, n_nodes = 0, n_leaves = 0, n_near = 0, n_classes = 0, N_nf = 0;
+  int64_t n = 0, n_nodes = 0, n_leaves = 0, n_near = 0, n_classes = 0, N_nf = 0, N_nf_pad = 0;
   int64_t n_stored_near = 0, n_stored_cls = 0, n_tiles = 0, ff_scratch = 0;
   int64_t n_groups = 0, n_entries = 0, max_group_entries = 0;
   int64_t near_factor_entries = 0, kernel_evals = 0;
@@ -83,7 +86,8 @@ struct DeviceModel {
   int near_rank_max = 0, far_rank_max = 0;
   std::vector<int32_t> near_rank_canon;   // per canonical near block (-1 if transposed copy)
   std::vector<int32_t> class_ranks;       // per class, 2 + d_theta entries
-  std::vector<int64_t> D_off_host;        // per canonical near block, n_near + 1
+  std::vector<int64_t> D_off_host;        // per canonical near block, n_near + 1 (padded blocks:
+                                          // leading dimension = rows rounded up to 16)
   // device arrays
   DevArr<double> U, E;
   DevArr<int64_t> perm;
@@ -97,11 +101,13 @@ struct DeviceModel {
   DevArr<int32_t> near_nt;
   DevArr<ClassDev> cstore;
   DevArr<double> ff_L, ff_R, ff_core, ff_theta;
-  // coupling work list: sibling groups (children of one parent at levels >= min_far)
-  DevArr<int32_t> grp_targets;            // n_groups x nsib node ids (-1 = absent)
+  // coupling work list: target boxes of NTG nodes of one level (see coupling_groups)
+  DevArr<int32_t> grp_targets;            // n_groups x NTG node ids (-1 = absent)
   DevArr<int32_t> grp_entry;              // n_groups + 1
   DevArr<int32_t> ent_cls;                // per entry: class
-  DevArr<int32_t> ent_tau;                // per entry: nsib source nodes (-1 = sibling unused)
+  DevArr<int32_t> ent_tau;                // per entry: NTG source nodes (-1 = target unused)
+  DevArr<int32_t> ent_wpre;               // per entry: work of the box's earlier entries
+  DevArr<int32_t> grp_w;                  // per box: total work
   int64_t device_bytes = 0;
 };
 
@@ -116,6 +122,13 @@ struct InstData {
   int64_t Rcap = 0;
   int Gcap = 0;
   DevArr<char> xt, yt, xh, yh, part;
+  hipStream_t aux = nullptr;          // second stream: near field concurrent with the far chain
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  ~InstData() {
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (aux) (void)hipStreamDestroy(aux);
+  }
 };
 
 template <typename S>
@@ -179,6 +192,84 @@ struct Mfma<float> {
   }
   static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
+
+// ---- 16 x 16 x 4 multiply-accumulate used by the hot kernels.
+// B operand (both types): lane l holds B[k = l / 16][n = l % 16].
+// FP32: one V_MFMA_F32_16X16X4 (A lane l = A[l % 16][l / 16]; result element i of
+//   lane l at row 4 (l / 16) + i, column l % 16).
+// FP64: four V_MFMA_F64_4X4X4 (4-block) instructions, one per group of 4 rows; in
+//   instruction c, lane l holds A[4c + l % 4][l / 16] and block (l % 16) / 4 multiplies
+//   it with columns 4 ((l % 16) / 4) .. + 3 of B, so the B register is the same as
+//   above; result element c of lane l sits at row 4c + l / 16, column l % 16.  On gfx950
+//   this issues at twice the rate of V_MFMA_F64_16X16X4 (measured: 71 vs 34 TFLOP/s).
+// load_a(f, lane) builds the A operand from an accessor f(row) of the lane's K column;
+// load_tiled(kr, lane) reads it from one K row of a matrix stored in fragment order
+// (frag_index below), where the four FP64 values of a lane are adjacent.
+template <typename S>
+struct Tile16;
+
+template <>
+struct Tile16<double> {
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  typedef double a_t __attribute__((ext_vector_type(4)));
+  template <typename F>
+  static __device__ __forceinline__ a_t load_a(F f, int lane) {
+    a_t a;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] = f(4 * c + (lane & 3));
+    return a;
+  }
+  static __device__ __forceinline__ a_t load_tiled(const double* kr, int lane) {
+    return *reinterpret_cast<const a_t*>(kr + (lane & 3) * 4);
+  }
+  static __device__ __forceinline__ acc_t mac(a_t a, double b, acc_t acc) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[c], b, acc[c], 0, 0, 0);
+    return acc;
+  }
+  static __device__ __forceinline__ int row(int lane, int i) { return 4 * i + (lane >> 4); }
+};
+
+template <>
+struct Tile16<float> {
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  typedef float a_t;
+  template <typename F>
+  static __device__ __forceinline__ a_t load_a(F f, int lane) {
+    return f(lane & 15);
+  }
+  static __device__ __forceinline__ a_t load_tiled(const float* kr, int lane) {
+    const int m = lane & 15;
+    return kr[(m & 3) * 4 + (m >> 2)];
+  }
+  static __device__ __forceinline__ acc_t mac(a_t a, float b, acc_t acc) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+
+// Fragment order of a Pp x Pp coupling matrix (Pp a multiple of 16): entry (m, k) sits in
+// the 16-column panel k / 16, 16-row tile m / 16, and inside the 256-entry tile at
+// (k % 16) * 16 + (m % 4) * 4 + (m % 16) / 4.  A panel is one contiguous pipeline stage of
+// the coupling kernel, and the four rows 4c + q (c = 0..3) a lane feeds to the FP64
+// matrix cores are adjacent.
+__host__ __device__ inline int64_t frag_index(int m, int k, int Pp) {
+  return (int64_t)(k >> 4) * Pp * 16 + (m >> 4) * 256 + (k & 15) * 16 + (m & 3) * 4 + ((m & 15) >> 2);
+}
+
+// Work estimate of one coupling entry with `act` targets using its class, in units of
+// half a target's matrix-core time for one stage: the multiplications plus the fixed
+// cost of staging a panel (loads, LDS stores, barrier).
+inline int32_t coupling_entry_weight(int act) { return 2 * act + 3; }
+
+// Raw buffer resources (CDNA3/4 word 3: 32-bit data format, no swizzle); a load at
+// BUF_OOB lies past any buffer the library creates and returns zeros.
+constexpr int BUF_WORD3 = 0x00020000;
+constexpr int BUF_OOB = 0x7ffffff0;
+constexpr int64_t BUF_MAX_BYTES = 0x7fff0000;
+
+// Right-hand sides are padded to a multiple of RC in every internal buffer.
+inline int64_t rhs_stride(int64_t R) { return (R + RC - 1) / RC * RC; }
 
 inline int64_t grid_for(int64_t work) {
   int64_t g = (work + NT - 1) / NT;

@@ -54,7 +54,8 @@ std::shared_ptr<TreeData> build_tree(const double* pts, int64_t n, const ph_tree
 // Offline stage output (host).  Layout conventions:
 //  U        n x d x p_s, tree order: U[(i*d + k)*p_s + j] = l_j^{(B_leaf,k)}(x_{i,k})
 //  E        2 x p_s x p_s: E[(h*p_s + j)*p_s + i] = l_i^{parent}(eta_j^{child half h})
-//  near P   rank-outer per stored block: P[P_off + k*N_e + e], e = i + j*n_s
+//  near P   rank-outer per stored block: P[P_off + k*ldp*n_t + i + j*ldp],
+//           ldp = n_s rounded up to a multiple of 16 (padding entries are 0)
 //  near core  c-major: core[core_off + k + r_e*(a + r_1*b)]
 //  Theta factors (near and far) column-major p_theta x r: th[off + q + p_theta*a]
 //  far L, R  column-major P x r
@@ -63,6 +64,7 @@ struct NearStored {
   int32_t s, t;             // node ids, s <= t
   int64_t s_begin, t_begin; // tree-order offsets
   int32_t ns, nt;
+  int32_t ldp;              // leading dimension of the stored factor columns (multiple of 16)
   int32_t r_e, r1, r2;      // r2 = 1 when d_theta = 1
   int64_t P_off, core_off, th1_off, th2_off;
   int32_t b_st, b_ts;       // canonical near indices of (s,t) and (t,s) (b_ts = -1 if s == t)
