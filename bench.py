@@ -22,14 +22,45 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "ms per θ-instantiate + H-MVM and HBM GB/s at n=65536; batched/BF16 vs FP64"
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_MFMA_PEAK_TFS = 78.6      # MI355X dense FP64 matrix
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+CSRC = os.path.join(ROOT, "paper_2511_03109_amd", "csrc")
+# source files whose text determines each hot kernel's code
+KERNEL_SOURCES = {
+    "k_coupling": ["k_matvec.hip", "ph_device.hpp"],
+    "k_near_mvm": ["k_matvec.hip", "ph_device.hpp"],
+    "k_near_instantiate": ["k_instantiate.hip", "ph_device.hpp"],
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, X, l_max, thetas, x_host, sample_leaves=32):
+def source_hash(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter record, or None when absent or
+    taken on a different version of the kernel's source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_sha") != source_hash(kernel):
+        return None
+    return rec["bytes_per_launch"]
+
+
+def cpu_baseline(w, X, l_max, thetas, x_host, sample_leaves=160):
     """Time the CPU oracle on a bounded sample of the same workload.
 
     Sample: all rows of `sample_leaves` target leaves spread over the tree, for every
@@ -91,7 +122,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-leaves", type=int, default=32)
+    ap.add_argument("--cpu-sample-leaves", type=int, default=160)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (to scale "
                          "profiler byte counters) and exit")
@@ -166,16 +197,34 @@ def main():
     inst_ms = sum(per_stage[k]["ms_total"] for k in ("theta", "far_inst", "near_inst")) / args.steps
     mvm_ms = sum(per_stage[k]["ms_total"] for k in _lib.STAGES[3:]) / args.steps  # sum of kernel times (streams overlap)
 
-    # algorithmic bytes of one near-field instantiation launch (all T slots):
-    # each stored factor entry P_b[k][e] read once, each near-block entry written once per slot
+    # Roofline of the hot kernels, from algorithmic work per launch (all T slots) and the
+    # average launch time measured above with HIP events on the launching stream.
     mi = model.info
-    nf_bytes = 8.0 * mi["near_factor_entries"] + 8.0 * T * mi["near_entries"]
-    nf_ms = per_stage["near_inst"]["ms_avg"]
-    nf_gbs = nf_bytes / (nf_ms * 1e-3) / 1e9
-    # whole-step algorithmic bytes per theta (near factors once per step, D write + read,
-    # couplings, vectors)
     P = mi["P"]
     ncls = tree.info["n_classes"]
+    nfar = tree.info["n_far"]
+    kernels = {
+        # each stored factor entry P_b[k][e] read once, each near-block entry written once per slot
+        "k_near_instantiate": ("near_inst", "hbm", 8.0 * mi["near_factor_entries"] + 8.0 * T * mi["near_entries"]),
+        # D read once, x and y once per slot
+        "k_near_mvm": ("near_mvm", "hbm", 8.0 * T * (mi["near_entries"] + 2.0 * n * R)),
+        # y_hat_s += C x_hat_t for every far block: 2 P^2 R flops per block and slot
+        "k_coupling": ("coupling", "mfma", 2.0 * P * P * R * nfar * T),
+    }
+    roof = {}
+    for kname, (stage, bound, work) in kernels.items():
+        ms = per_stage[stage]["ms_avg"]
+        if bound == "hbm":
+            ach, peak, unit = work / (ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s"
+        else:
+            ach, peak, unit = work / (ms * 1e-3) / 1e12, FP64_MFMA_PEAK_TFS, "TFLOP/s"
+        roof[kname] = {"bound": bound, "kernel": kname, "achieved": ach, "peak": peak, "unit": unit,
+                       "frac": ach / peak, "traffic": measured_traffic(kname),
+                       "algorithmic_per_launch": work, "avg_launch_ms": ms,
+                       "ms_per_step": per_stage[stage]["ms_total"] / args.steps}
+    dominant = max(roof, key=lambda k: roof[k]["ms_per_step"])
+    # whole-step algorithmic bytes per theta (near factors once per step, D write + read,
+    # couplings, vectors)
     step_bytes = (8.0 * mi["near_factor_entries"] + T * 8.0 * (2 * mi["near_entries"]
                   + 2 * ncls * P * P + 4 * n * R + 2 * tree.info["n_nodes"] * P * R))
     out = {
@@ -193,10 +242,8 @@ def main():
         "ms_matvec_per_theta": mvm_ms / T,
         "step_algorithmic_GBps": step_bytes / (ms_step * 1e-3) / 1e9,
         "stages": per_stage,
-        "roofline": {"bound": "hbm", "kernel": "k_near_instantiate", "achieved": nf_gbs,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": nf_gbs / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes_per_launch": nf_bytes,
-                     "avg_launch_ms": nf_ms},
+        "roofline": roof[dominant],
+        "kernels": roof,
         "model": {"near_entries": mi["near_entries"], "near_factor_entries": mi["near_factor_entries"],
                   "near_rank_mean": mi["near_rank_mean"], "far_rank_mean": mi["far_rank_mean"],
                   "classes": ncls, "far_blocks": tree.info["n_far"], "near_blocks": tree.info["n_near"],

@@ -220,6 +220,16 @@ int ph_instantiate_grad(const ph_model* m, const double* theta, int T, int dim, 
 int ph_matvec(ph_inst* k, const void* x, void* y, int64_t R, double alpha, double beta,
               double nugget, void* stream);
 
+/* Bilinear form per parameter slot:  out[t] = sum_r u_t[:, r]^T K~(theta_t) x_t[:, r]
+ * (nugget excluded).  With an instance of ph_instantiate_grad(dim) this is
+ * dL/dtheta_dim of L = sum_r u_r^T K~(theta) x_r, the parameter gradient of the
+ * backward pass of y = K~(theta) x (multilinearity in the parametric vectors, Sec. 4.2
+ * and 4.3).  u, x: device, layout of ph_matvec's x; out: device, T doubles.  The
+ * product K~ x goes to a scratch buffer of the instance (allocated on the first call
+ * with a larger R); the sum over points and right-hand sides is a fixed-order two-pass
+ * reduction in FP64, so repeated calls give identical results.  Stream-ordered. */
+int ph_bilinear(ph_inst* k, const void* u, const void* x, int64_t R, double* out, void* stream);
+
 /* Inspection (tests): copy the instantiated near block of canonical near index b for
  * slot t (n_s x n_t column-major, as double) or the coupling matrix of class c
  * (P x P column-major, as double) to host memory.  Synchronises the device. */
@@ -246,7 +256,8 @@ enum {
   PH_STAGE_PERM_OUT = 9,
   PH_STAGE_ZERO = 10,         /* reduction of split coupling partial sums */
   PH_STAGE_LEAF_DOWN = 11,    /* FastBackward, leaves */
-  PH_NUM_STAGES = 12
+  PH_STAGE_BILINEAR = 12,     /* reduction of ph_bilinear */
+  PH_NUM_STAGES = 13
 };
 typedef struct {
   double ms[16];

@@ -43,7 +43,7 @@ class TraceStats(C.Structure):
 
 
 STAGES = ["theta", "far_inst", "near_inst", "perm_in", "leaf_up", "transfer_up", "coupling",
-          "transfer_down", "near_mvm", "perm_out", "coupling_reduce", "leaf_down"]
+          "transfer_down", "near_mvm", "perm_out", "coupling_reduce", "leaf_down", "bilinear"]
 
 _P = C.c_void_p
 _I32P = C.POINTER(C.c_int32)
@@ -68,6 +68,7 @@ SIGNATURES = {
     "ph_instantiate": ([_P, _DP, C.c_int, C.c_int, _P, C.POINTER(_P)], C.c_int),
     "ph_instantiate_grad": ([_P, _DP, C.c_int, C.c_int, C.c_int, _P, C.POINTER(_P)], C.c_int),
     "ph_matvec": ([_P, _P, _P, C.c_int64, C.c_double, C.c_double, C.c_double, _P], C.c_int),
+    "ph_bilinear": ([_P, _P, _P, C.c_int64, _P, _P], C.c_int),
     "ph_inst_near_block": ([_P, C.c_int, C.c_int64, _DP], C.c_int),
     "ph_inst_coupling": ([_P, C.c_int, C.c_int64, _DP], C.c_int),
     "ph_inst_free": ([_P], None),

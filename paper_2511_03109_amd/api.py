@@ -179,6 +179,24 @@ class Instance:
         L.check(code, "ph_matvec")
         return y
 
+    def bilinear(self, u, x, *, stream=None):
+        """out[t] = sum_r u_t[r] . K~_t x_t[r] as a device float64 tensor of length T (ph_bilinear)."""
+        import torch
+        want = torch.float64 if self.dtype == "f64" else torch.float32
+        for a in (u, x):
+            if a.dtype != want or not a.is_cuda:
+                raise TypeError(f"u and x must be {want} device tensors")
+        if u.shape != x.shape:
+            raise ValueError("u and x must have the same shape")
+        u = u.contiguous()
+        x = x.contiguous()
+        R = 1 if x.dim() == 1 else x.shape[-2]
+        out = torch.empty(self.T, dtype=torch.float64, device=x.device)
+        code = L.lib().ph_bilinear(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(x.data_ptr()), R,
+                                   C.c_void_p(out.data_ptr()), _stream(stream))
+        L.check(code, "ph_bilinear")
+        return out
+
     def near_block(self, b, t=0):
         near, _, _ = self.model.tree.blocks()
         nodes = self.model.tree.nodes()
@@ -199,3 +217,64 @@ class Instance:
         if getattr(self, "_h", None):
             L.lib().ph_inst_free(self._h)
             self._h = None
+
+
+def _autograd_function():
+    import torch
+
+    class KThetaMatvec(torch.autograd.Function):
+        """y = (K~(theta) + nugget I) x with gradients for theta and x.
+
+        theta: (d_theta,) with x of shape (n,) or (R, n), or (T, d_theta) with x of shape
+        (T, R, n).  Backward: dL/dx = (K~ + nugget I) g (K~ is symmetric by construction)
+        and dL/dtheta_i = sum_r g_r . (dK~/dtheta_i) x_r, the bilinear form of the
+        instance of ph_instantiate_grad, both computed by the library.
+        """
+
+        @staticmethod
+        def forward(ctx, theta, x, model, nugget=0.0):
+            th = theta.detach().to("cpu", torch.float64).numpy().reshape(-1, model.d_theta)
+            dtype = "f64" if x.dtype == torch.float64 else "f32"
+            inst = Instance(model, th, dtype=dtype)
+            y = inst.matvec(x, nugget=nugget)
+            ctx.save_for_backward(x)
+            ctx.inst, ctx.model, ctx.nugget, ctx.th, ctx.theta_meta = inst, model, nugget, th, theta
+            return y
+
+        @staticmethod
+        def backward(ctx, g):
+            (x,) = ctx.saved_tensors
+            g = g.contiguous()
+            gtheta = gx = None
+            if ctx.needs_input_grad[1]:
+                gx = ctx.inst.matvec(g, nugget=ctx.nugget)
+            if ctx.needs_input_grad[0]:
+                cols = []
+                for i in range(ctx.model.d_theta):
+                    gi = Instance(ctx.model, ctx.th, dtype=ctx.inst.dtype, grad_dim=i)
+                    cols.append(gi.bilinear(g, x))
+                meta = ctx.theta_meta
+                gtheta = torch.stack(cols, dim=-1).reshape(meta.shape).to(meta.dtype).to(meta.device)
+            return gtheta, gx, None, None
+
+    return KThetaMatvec
+
+
+_KTM = None
+
+
+def k_theta_matvec(model, theta, x, nugget=0.0):
+    """Differentiable y = (K~(theta) + nugget I) x (see KThetaMatvec)."""
+    global _KTM
+    if _KTM is None:
+        _KTM = _autograd_function()
+    return _KTM.apply(theta, x, model, nugget)
+
+
+def __getattr__(name):
+    if name == "KThetaMatvec":
+        global _KTM
+        if _KTM is None:
+            _KTM = _autograd_function()
+        return _KTM
+    raise AttributeError(name)

@@ -598,16 +598,20 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
   launch(PH_STAGE_PERM_IN, k_perm_in<S>, dim3((unsigned)grid_for(total_in)), dim3(NT), st, x, xt,
          (const int64_t*)m.perm.p, m.n, R, Rs, total_in);
   // The near field (HBM-bound) runs on the instance's second stream, concurrently with
-  // the far-field chain (matrix-core bound) on the caller's stream.
-  if (!serial) {
-    PH_HIP(hipEventRecord(in.ev_fork, st));
-    PH_HIP(hipStreamWaitEvent(in.aux, in.ev_fork, 0));
-  }
-  launch(PH_STAGE_NEAR_MVM, k_near_mvm<S>, dim3((unsigned)m.n_leaves, (unsigned)nrc, (unsigned)T), dim3(NT),
-         nst, (const S*)xt, yt, (const S*)in.D.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
-         (const int64_t*)m.near_rowptr.p, (const int64_t*)m.near_tb.p, (const int32_t*)m.near_nt.p,
-         (const int64_t*)m.near_D.p, leaf0, m.n, Rs, m.N_nf_pad);
-  if (!serial) PH_HIP(hipEventRecord(in.ev_join, in.aux));
+  // the coupling (matrix-core bound) on the caller's stream.  It is forked after the
+  // upward pass, whose few small launches would otherwise wait for CUs behind it.
+  auto near_field = [&] {
+    if (!serial) {
+      PH_HIP(hipEventRecord(in.ev_fork, st));
+      PH_HIP(hipStreamWaitEvent(in.aux, in.ev_fork, 0));
+    }
+    launch(PH_STAGE_NEAR_MVM, k_near_mvm<S>, dim3((unsigned)m.n_leaves, (unsigned)nrc, (unsigned)T), dim3(NT),
+           nst, (const S*)xt, yt, (const S*)in.D.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
+           (const int64_t*)m.near_rowptr.p, (const int64_t*)m.near_tb.p, (const int32_t*)m.near_nt.p,
+           (const int64_t*)m.near_D.p, leaf0, m.n, Rs, m.N_nf_pad);
+    if (!serial) PH_HIP(hipEventRecord(in.ev_join, in.aux));
+  };
+  if (!use_far) near_field();
   if (use_far) {
     launch(PH_STAGE_LEAF_UP, k_leaf_up<S>, dim3((unsigned)m.n_leaves, (unsigned)nrc, (unsigned)T), dim3(NT),
            st, (const S*)xt, xh, (const double*)m.U.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
@@ -618,6 +622,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
              dim3(NT), st, xh, (const double*)m.E.p, (const int32_t*)m.first_child.p,
              (const int32_t*)m.nchild.p, (const int32_t*)m.cid.p, a, m.d, m.p_s, m.P, m.Pp, m.n_nodes, Rs);
     }
+    near_field();
     const int64_t part_stride = T * m.n_nodes * m.Pp * Rs;
     S* cout = G > 1 ? (S*)in.part.p : yh;
     dim3 cg((unsigned)G, (unsigned)(m.n_groups * nrc), (unsigned)T);
@@ -669,6 +674,60 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
   launch(PH_STAGE_PERM_OUT, k_perm_out<S>, dim3((unsigned)grid_for(total_out)), dim3(NT), st, y, (const S*)yt,
          (const S*)xt, (const int64_t*)m.perm.p, m.n, R, Rs, total_out, alpha, beta, nugget);
 }
+
+// Bilinear form, first pass: part[t][b] = sum over the elements e = b, b + NB, ... of
+// slot t of u[e] v[e] (FP64), then a fixed-order workgroup tree reduction.
+constexpr int BIL_BLOCKS = 256;
+template <typename S>
+__global__ void __launch_bounds__(NT) k_dot_partial(const S* __restrict__ u, const S* __restrict__ v,
+                                                    double* __restrict__ part, int64_t per_slot) {
+  __shared__ double red[NT];
+  const int64_t t = blockIdx.y;
+  const S* us = u + t * per_slot;
+  const S* vs = v + t * per_slot;
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < per_slot; e += (int64_t)BIL_BLOCKS * NT)
+    acc += (double)us[e] * (double)vs[e];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = NT / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[t * BIL_BLOCKS + blockIdx.x] = red[0];
+}
+
+// Second pass: out[t] = sum_b part[t][b] (one workgroup per slot, same fixed order).
+__global__ void __launch_bounds__(NT) k_dot_final(const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double red[NT];
+  const int64_t t = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < BIL_BLOCKS; b += NT) acc += part[t * BIL_BLOCKS + b];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = NT / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[t] = red[0];
+}
+
+template <typename S>
+void bilinear_impl(InstData& in, const S* u, const S* x, int64_t R, double* out, hipStream_t st) {
+  const DeviceModel& m = *in.m;
+  const int64_t per_slot = m.n * R;
+  const size_t need_bytes = (size_t)in.T * per_slot * sizeof(S);
+  if (in.bil.bytes() < need_bytes) in.bil.alloc(need_bytes);
+  if (in.bil_part.n < (size_t)in.T * BIL_BLOCKS) in.bil_part.alloc((size_t)in.T * BIL_BLOCKS);
+  S* v = (S*)in.bil.p;
+  matvec_impl<S>(in, x, v, R, 1.0, 0.0, 0.0, st);
+  launch(PH_STAGE_BILINEAR, k_dot_partial<S>, dim3(BIL_BLOCKS, (unsigned)in.T), dim3(NT), st, u, (const S*)v,
+         in.bil_part.p, per_slot);
+  launch(PH_STAGE_BILINEAR, k_dot_final, dim3((unsigned)in.T), dim3(NT), st, (const double*)in.bil_part.p, out);
+}
+
+template void bilinear_impl<double>(InstData&, const double*, const double*, int64_t, double*, hipStream_t);
+template void bilinear_impl<float>(InstData&, const float*, const float*, int64_t, double*, hipStream_t);
 
 template void matvec_impl<double>(InstData&, const double*, double*, int64_t, double, double, double,
                                   hipStream_t);

@@ -473,6 +473,20 @@ int ph_matvec(ph_inst* k, const void* x, void* y, int64_t R, double alpha, doubl
   });
 }
 
+int ph_bilinear(ph_inst* k, const void* u, const void* x, int64_t R, double* out, void* stream) {
+  return guarded([&] {
+    need(k && k->p, "instance is NULL");
+    need(u && x && out, "u, x or out is NULL");
+    need(R >= 1, "R must be >= 1");
+    ph::InstData& in = *k->p;
+    hipStream_t st = (hipStream_t)stream;
+    if (in.dt == PH_F64)
+      ph::bilinear_impl<double>(in, (const double*)u, (const double*)x, R, out, st);
+    else
+      ph::bilinear_impl<float>(in, (const float*)u, (const float*)x, R, out, st);
+  });
+}
+
 int ph_inst_near_block(const ph_inst* k, int t, int64_t b, double* host_out) {
   return guarded([&] {
     need(k && k->p && host_out, "NULL argument");

@@ -122,6 +122,8 @@ struct InstData {
   int64_t Rcap = 0;
   int Gcap = 0;
   DevArr<char> xt, yt, xh, yh, part;
+  DevArr<char> bil;                   // ph_bilinear: K~ x
+  DevArr<double> bil_part;            // ph_bilinear: per-block partial sums
   hipStream_t aux = nullptr;          // second stream: near field concurrent with the far chain
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ~InstData() {
@@ -136,6 +138,8 @@ void instantiate_impl(InstData& in, const double* theta, hipStream_t st);
 template <typename S>
 void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double beta, double nugget,
                  hipStream_t st);
+template <typename S>
+void bilinear_impl(InstData& in, const S* u, const S* x, int64_t R, double* out, hipStream_t st);
 
 // ---- per-kernel timing with HIP events
 struct TraceRec {

@@ -225,3 +225,76 @@ def test_workload2_full_size_sampled_rows():
     for t in (0, 5):
         ref = om.matvec_rows(thetas[t], x[t].T, rows)
         _close(y[t][:, rows].T, ref)
+
+
+def test_autograd_function_theta_and_x():
+    """torch.autograd.Function y = K~(theta) x: dL/dtheta and dL/dx of L = u . y against the
+    oracle's analytic derivative (Lagrange derivative in the parametric vector) and K~ u,
+    and dL/dtheta against a central difference of the library's own forward."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    n = 2000
+    X = inputs.points_for(4, n)
+    lt, lm, om = _setup(X, "gaussian", [0.05], [0.5], 6, 9, 1e-8, 3, (2, 1))
+    R = 3
+    u = inputs.normal_vectors(n, R, 4, inputs.STREAM_U)
+    x = inputs.normal_vectors(n, R, 4)
+    l0 = 0.23
+    theta = torch.tensor([l0], dtype=torch.float64, requires_grad=True)
+    xd = torch.tensor(np.ascontiguousarray(x.T), device="cuda", requires_grad=True)
+    ud = torch.tensor(np.ascontiguousarray(u.T), device="cuda")
+    y = api.k_theta_matvec(lm, theta, xd)
+    (y * ud).sum().backward()
+    gth = theta.grad.numpy()
+    gx = xd.grad.cpu().numpy().T
+    dth_o = np.sum(u * om.matvec(om.instantiate(l0, deriv_dim=0), x))
+    _close(gth, [dth_o], what="dL/dtheta")
+    _close(gx, om.matvec(om.instantiate(l0), u), what="dL/dx")
+    h = 1e-5
+    Lp = float((api.Instance(lm, [l0 + h]).matvec(xd.detach()) * ud).sum())
+    Lm = float((api.Instance(lm, [l0 - h]).matvec(xd.detach()) * ud).sum())
+    fd = (Lp - Lm) / (2 * h)
+    print(f"[parity] dL/dtheta vs central difference: {abs(gth[0] - fd) / abs(fd):.3e}", flush=True)
+    assert abs(gth[0] - fd) <= 1e-7 * abs(fd)
+
+
+def test_autograd_two_parameters_and_slots():
+    """Anisotropic Gaussian, theta of shape (T, 2) with T = 2 slots: the gradient of
+    L = sum_t u_t . K~(theta_t) x_t for both length scales of both slots."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    n = 1500
+    X = inputs.points_for(3, n)
+    lt, lm, om = _setup(X, "aniso_gaussian", [0.05, 0.05], [0.5, 0.5], 5, 7, 1e-8, 3, (2, 1))
+    th = np.array([[0.21, 0.09], [0.33, 0.41]])
+    R = 2
+    u = inputs.normal_vectors(n, 2 * R, 3, inputs.STREAM_U).T.reshape(2, R, n)
+    x = inputs.normal_vectors(n, 2 * R, 3).T.reshape(2, R, n)
+    theta = torch.tensor(th, requires_grad=True)
+    xd = torch.tensor(np.ascontiguousarray(x), device="cuda", requires_grad=True)
+    ud = torch.tensor(np.ascontiguousarray(u), device="cuda")
+    (api.k_theta_matvec(lm, theta, xd) * ud).sum().backward()
+    ref = np.empty((2, 2))
+    for t in range(2):
+        for i in range(2):
+            ref[t, i] = np.sum(u[t].T * om.matvec(om.instantiate(th[t], deriv_dim=i), x[t].T))
+    _close(theta.grad.numpy(), ref, what="dL/dtheta (T=2, d_theta=2)")
+    gx_ref = np.stack([om.matvec(om.instantiate(th[t]), u[t].T).T for t in range(2)])
+    _close(xd.grad.cpu().numpy(), gx_ref, what="dL/dx (T=2)")
+
+
+def test_bilinear_is_deterministic():
+    """ph_bilinear's fixed-order reduction gives bit-identical results on repeated calls."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    n = 3000
+    X = inputs.points_for(1, n)
+    lt, lm, om = _setup(X, "gaussian", [0.1], [0.5], 6, 9, 1e-8, 3, (1, 1))
+    inst = api.Instance(lm, [0.25])
+    u = torch.tensor(inputs.normal_vectors(n, 2, 1, inputs.STREAM_U).T.copy(), device="cuda")
+    x = torch.tensor(inputs.normal_vectors(n, 2, 1).T.copy(), device="cuda")
+    a = inst.bilinear(u, x).cpu().numpy()
+    b = inst.bilinear(u, x).cpu().numpy()
+    assert np.array_equal(a, b)
+    ref = np.sum(u.cpu().numpy().T * om.matvec(om.instantiate(0.25), x.cpu().numpy().T))
+    _close(a, [ref], what="bilinear")
