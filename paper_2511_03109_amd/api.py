@@ -75,9 +75,10 @@ class Tree:
         return lev, off
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            L.lib().ph_tree_free(self._h)
-            self._h = None
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h and L is not None and L._lib is not None:   # (skip at interpreter shutdown)
+            L._lib.ph_tree_free(h)
 
 
 class Model:
@@ -117,9 +118,10 @@ class Model:
         return out
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            L.lib().ph_model_free(self._h)
-            self._h = None
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h and L is not None and L._lib is not None:   # (skip at interpreter shutdown)
+            L._lib.ph_model_free(h)
 
 
 class Instance:
@@ -214,9 +216,10 @@ class Instance:
         return out.reshape(P, P).T
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            L.lib().ph_inst_free(self._h)
-            self._h = None
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h and L is not None and L._lib is not None:   # (skip at interpreter shutdown)
+            L._lib.ph_inst_free(h)
 
 
 def _autograd_function():

@@ -598,8 +598,8 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
   launch(PH_STAGE_PERM_IN, k_perm_in<S>, dim3((unsigned)grid_for(total_in)), dim3(NT), st, x, xt,
          (const int64_t*)m.perm.p, m.n, R, Rs, total_in);
   // The near field (HBM-bound) runs on the instance's second stream, concurrently with
-  // the coupling (matrix-core bound) on the caller's stream.  It is forked after the
-  // upward pass, whose few small launches would otherwise wait for CUs behind it.
+  // the far-field chain (matrix-core bound) on the caller's stream.  (Forking it after
+  // the upward pass instead measured slower: it then overlaps the coupling throughout.)
   auto near_field = [&] {
     if (!serial) {
       PH_HIP(hipEventRecord(in.ev_fork, st));
@@ -611,7 +611,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
            (const int64_t*)m.near_D.p, leaf0, m.n, Rs, m.N_nf_pad);
     if (!serial) PH_HIP(hipEventRecord(in.ev_join, in.aux));
   };
-  if (!use_far) near_field();
+  near_field();
   if (use_far) {
     launch(PH_STAGE_LEAF_UP, k_leaf_up<S>, dim3((unsigned)m.n_leaves, (unsigned)nrc, (unsigned)T), dim3(NT),
            st, (const S*)xt, xh, (const double*)m.U.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
@@ -622,7 +622,6 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
              dim3(NT), st, xh, (const double*)m.E.p, (const int32_t*)m.first_child.p,
              (const int32_t*)m.nchild.p, (const int32_t*)m.cid.p, a, m.d, m.p_s, m.P, m.Pp, m.n_nodes, Rs);
     }
-    near_field();
     const int64_t part_stride = T * m.n_nodes * m.Pp * Rs;
     S* cout = G > 1 ? (S*)in.part.p : yh;
     dim3 cg((unsigned)G, (unsigned)(m.n_groups * nrc), (unsigned)T);
