@@ -63,8 +63,12 @@ typedef enum {
 } ph_kernel;
 
 /* Arithmetic of an instance.  PH_F64: FP64 storage and arithmetic, I/O in double.
- * PH_F32: FP32 storage of the instantiated blocks, FP32 arithmetic, I/O in float. */
-typedef enum { PH_F64 = 0, PH_F32 = 1 } ph_dtype;
+ * PH_F32: FP32 storage of the instantiated blocks, FP32 arithmetic (matrix cores with
+ * FP32 accumulation), I/O in float.  PH_BF16: as PH_F32, but the near-field blocks D_b
+ * (the dominant stream) are stored in BF16, rounded to nearest from the FP64
+ * instantiation, and widened to FP32 on load.  The instantiation itself is FP64 in all
+ * three. */
+typedef enum { PH_F64 = 0, PH_F32 = 1, PH_BF16 = 2 } ph_dtype;
 
 typedef struct ph_tree ph_tree;
 typedef struct ph_model ph_model;
@@ -194,7 +198,7 @@ void ph_model_free(ph_model* m);
  *
  * theta: host, T x d_theta row-major.  T >= 1 instantiates T independent parameter
  * values into one instance (slot t holds theta[t]).  dt selects the storage and
- * arithmetic (PH_F64 or PH_F32).
+ * arithmetic (PH_F64, PH_F32 or PH_BF16).
  * *inout: NULL -> a new instance is allocated and returned (owned by the caller,
  * ph_inst_free).  Non-NULL -> that instance is re-instantiated in place; it must come
  * from the same model with the same T and dt (else PH_EINVAL), and no allocation
@@ -213,7 +217,8 @@ int ph_instantiate_grad(const ph_model* m, const double* theta, int T, int dim, 
  * blocks, near-field products, FastBackward), for every slot t:
  *   y_t = alpha * (K~(theta_t) + nugget I) x_t + beta * y_t.
  * x, y: device, slot-major [T][R][n] with each slot column-major n x R (leading
- * dimension n) in the ORIGINAL point order; double for PH_F64, float for PH_F32.
+ * dimension n) in the ORIGINAL point order; double for PH_F64, float for PH_F32 and
+ * PH_BF16.
  * x and y must not overlap.  R = 0 is a no-op.  With beta == 0, y is not read.
  * Scratch for R right-hand sides is allocated on the first call with a larger R and
  * kept in the instance. */
@@ -229,6 +234,29 @@ int ph_matvec(ph_inst* k, const void* x, void* y, int64_t R, double alpha, doubl
  * with a larger R); the sum over points and right-hand sides is a fixed-order two-pass
  * reduction in FP64, so repeated calls give identical results.  Stream-ordered. */
 int ph_bilinear(ph_inst* k, const void* u, const void* x, int64_t R, double* out, void* stream);
+
+/* Solve (K~(theta) + nugget I) a = y by conjugate gradients (K~ is symmetric by
+ * construction; it is positive definite up to the approximation error, which the nugget
+ * of a regularised system covers).
+ *   hi: PH_F64 instance with T = 1.  y, a: device, n doubles, original point order;
+ *   a is overwritten (the initial guess is 0).
+ *   lo == NULL: plain FP64 CG; max_iter bounds the total CG iterations.
+ *   lo != NULL: FP64 iterative refinement.  lo is a PH_F32 or PH_BF16 instance of the
+ *     same model and the same theta (else PH_EINVAL); each step forms the residual
+ *     r = y - (K~ + nugget I) a with hi in FP64 and adds the correction from an inner
+ *     CG on lo (to relative residual inner_tol or inner_max iterations, FP32 vectors);
+ *     max_iter bounds the refinement steps, and refinement stops early once the FP64
+ *     residual no longer decreases.
+ * Stops when ||y - (K~ + nugget I) a|| <= tol ||y|| with the FP64 instance.  Synchronous:
+ * it reads inner products back to the host each iteration.  stats may be NULL. */
+typedef struct {
+  int outer_steps;        /* refinement steps (plain CG: restarts from the true residual) */
+  int inner_iterations;   /* CG iterations in total */
+  double rel_residual;    /* final FP64 relative residual */
+  int converged;          /* rel_residual <= tol */
+} ph_cg_stats;
+int ph_cg_solve(ph_inst* hi, ph_inst* lo, const double* y, double* a, double nugget, double tol, int max_iter,
+                int inner_max, double inner_tol, ph_cg_stats* stats, void* stream);
 
 /* Inspection (tests): copy the instantiated near block of canonical near index b for
  * slot t (n_s x n_t column-major, as double) or the coupling matrix of class c
@@ -257,7 +285,8 @@ enum {
   PH_STAGE_ZERO = 10,         /* reduction of split coupling partial sums */
   PH_STAGE_LEAF_DOWN = 11,    /* FastBackward, leaves */
   PH_STAGE_BILINEAR = 12,     /* reduction of ph_bilinear */
-  PH_NUM_STAGES = 13
+  PH_STAGE_SOLVE = 13,        /* vector updates and inner products of ph_cg_solve */
+  PH_NUM_STAGES = 14
 };
 typedef struct {
   double ms[16];

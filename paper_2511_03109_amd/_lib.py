@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(_HERE, "libph.so")
 PH_OK, PH_EINVAL, PH_EDOMAIN, PH_ENOMEM, PH_EHIP, PH_ESTATE, PH_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 KERNELS = {"gaussian": 0, "matern32": 1, "matern12": 2, "aniso_gaussian": 3, "poly_test": 4,
            "poly2_test": 5}
-DTYPES = {"f64": 0, "f32": 1}
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2}
 
 
 class TreeOpts(C.Structure):
@@ -29,6 +29,11 @@ class OfflineOpts(C.Structure):
                 ("tol", C.c_double), ("num_threads", C.c_int)]
 
 
+class CgStats(C.Structure):
+    _fields_ = [("outer_steps", C.c_int), ("inner_iterations", C.c_int), ("rel_residual", C.c_double),
+                ("converged", C.c_int)]
+
+
 class ModelInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_near_stored", C.c_int64), ("n_classes_stored", C.c_int64),
                 ("near_entries", C.c_int64), ("near_factor_entries", C.c_int64),
@@ -43,7 +48,8 @@ class TraceStats(C.Structure):
 
 
 STAGES = ["theta", "far_inst", "near_inst", "perm_in", "leaf_up", "transfer_up", "coupling",
-          "transfer_down", "near_mvm", "perm_out", "coupling_reduce", "leaf_down", "bilinear"]
+          "transfer_down", "near_mvm", "perm_out", "coupling_reduce", "leaf_down", "bilinear",
+          "solve"]
 
 _P = C.c_void_p
 _I32P = C.POINTER(C.c_int32)
@@ -69,6 +75,8 @@ SIGNATURES = {
     "ph_instantiate_grad": ([_P, _DP, C.c_int, C.c_int, C.c_int, _P, C.POINTER(_P)], C.c_int),
     "ph_matvec": ([_P, _P, _P, C.c_int64, C.c_double, C.c_double, C.c_double, _P], C.c_int),
     "ph_bilinear": ([_P, _P, _P, C.c_int64, _P, _P], C.c_int),
+    "ph_cg_solve": ([_P, _P, _P, _P, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
+                     C.POINTER(CgStats), _P], C.c_int),
     "ph_inst_near_block": ([_P, C.c_int, C.c_int64, _DP], C.c_int),
     "ph_inst_coupling": ([_P, C.c_int, C.c_int64, _DP], C.c_int),
     "ph_inst_free": ([_P], None),

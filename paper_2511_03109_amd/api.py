@@ -222,6 +222,24 @@ class Instance:
             L._lib.ph_inst_free(h)
 
 
+def cg_solve(inst64, y, *, nugget, tol=1e-6, lo=None, max_iter=100000, inner_max=1000, inner_tol=1e-4,
+             stream=None):
+    """Solve (K~ + nugget I) a = y (ph_cg_solve).  inst64: FP64 instance with T = 1; y: device
+    float64 tensor of length n; lo: optional FP32/BF16 instance of the same theta for FP64
+    iterative refinement.  Returns (a, stats dict)."""
+    import torch
+    if y.dtype != torch.float64 or not y.is_cuda or y.dim() != 1:
+        raise TypeError("y must be a 1-D float64 device tensor")
+    y = y.contiguous()
+    a = torch.empty_like(y)
+    st = L.CgStats()
+    code = L.lib().ph_cg_solve(inst64._h, lo._h if lo is not None else None, C.c_void_p(y.data_ptr()),
+                               C.c_void_p(a.data_ptr()), nugget, tol, max_iter, inner_max, inner_tol,
+                               C.byref(st), _stream(stream))
+    L.check(code, "ph_cg_solve")
+    return a, {k: getattr(st, k) for k, _ in L.CgStats._fields_}
+
+
 def _autograd_function():
     import torch
 

@@ -137,11 +137,11 @@ __global__ void __launch_bounds__(NT) k_far_instantiate(
 //   c_t = core x_theta (Theta_k^T v_k(theta_t));  D_t[i + j n_s] = sum_k P[k][i + j n_s] c_t[k]
 // Each factor entry is read from HBM once for up to TC slots; D_t is written to the
 // (s, t) block and, through an LDS transpose, to the (t, s) block.
-template <typename S>
+template <typename DT>
 __global__ void __launch_bounds__(NT) k_near_instantiate(
     const NearDev* __restrict__ blocks, const int32_t* __restrict__ tiles,
     const double* __restrict__ Pf, const double* __restrict__ core, const double* __restrict__ th,
-    const double* __restrict__ v, S* __restrict__ D, int64_t D_per_slot, int T, int p, int dth) {
+    const double* __restrict__ v, DT* __restrict__ D, int64_t D_per_slot, int T, int p, int dth) {
   __shared__ double w1[TC][16], w2[TC][16], cc[TC][256];
   __shared__ double tile[TILE][TILE + 1];
   const int32_t bi = tiles[3 * blockIdx.x], i0 = tiles[3 * blockIdx.x + 1], j0 = tiles[3 * blockIdx.x + 2];
@@ -205,9 +205,9 @@ __global__ void __launch_bounds__(NT) k_near_instantiate(
 #pragma unroll
     for (int tt = 0; tt < TC; ++tt) {
       if (tt >= tc) break;
-      S* Dt = D + (size_t)(t0 + tt) * D_per_slot;
+      DT* Dt = D + (size_t)(t0 + tt) * D_per_slot;
       for (int q = 0; q < NQ; ++q)
-        if (ok[q]) Dt[b.D_st + ed[q]] = (S)acc[tt][q];
+        if (ok[q]) Dt[b.D_st + ed[q]] = to_store<DT>(acc[tt][q]);
       if (b.D_ts >= 0) {
         __syncthreads();
         for (int q = 0; q < NQ; ++q) tile[tj0 + q * (NT / TILE)][ti] = acc[tt][q];
@@ -216,14 +216,14 @@ __global__ void __launch_bounds__(NT) k_near_instantiate(
         const int jj = j0 + ti;
         for (int q = 0; q < NQ; ++q) {
           const int ii = i0 + tj0 + q * (NT / TILE);
-          if (ii < b.ns && jj < b.nt) Dt[b.D_ts + jj + (int64_t)ii * b.ldt] = (S)tile[ti][tj0 + q * (NT / TILE)];
+          if (ii < b.ns && jj < b.nt) Dt[b.D_ts + jj + (int64_t)ii * b.ldt] = to_store<DT>(tile[ti][tj0 + q * (NT / TILE)]);
         }
       }
     }
   }
 }
 
-template <typename S>
+template <typename S, typename DT>
 void instantiate_impl(InstData& in, const double* theta, hipStream_t st) {
   const DeviceModel& m = *in.m;
   for (int t0 = 0; t0 < in.T; t0 += MAXT) {
@@ -245,13 +245,14 @@ void instantiate_impl(InstData& in, const double* theta, hipStream_t st) {
          (const ClassDev*)m.cstore.p, (const double*)m.ff_L.p, (const double*)m.ff_R.p,
          (const double*)m.ff_core.p, (const double*)m.ff_theta.p, (const double*)in.v.p, in.ffs.p,
          m.ff_scratch, (S*)in.C.p, Cps, m.P, m.Pp, m.p_theta, m.d_theta);
-  launch(PH_STAGE_NEAR_INST, k_near_instantiate<S>, dim3((unsigned)m.n_tiles), dim3(NT), st,
+  launch(PH_STAGE_NEAR_INST, k_near_instantiate<DT>, dim3((unsigned)m.n_tiles), dim3(NT), st,
          (const NearDev*)m.nstore.p, (const int32_t*)m.tiles.p, (const double*)m.nf_P.p,
-         (const double*)m.nf_core.p, (const double*)m.nf_theta.p, (const double*)in.v.p, (S*)in.D.p,
+         (const double*)m.nf_core.p, (const double*)m.nf_theta.p, (const double*)in.v.p, (DT*)in.D.p,
          m.N_nf_pad, in.T, m.p_theta, m.d_theta);
 }
 
-template void instantiate_impl<double>(InstData&, const double*, hipStream_t);
-template void instantiate_impl<float>(InstData&, const double*, hipStream_t);
+template void instantiate_impl<double, double>(InstData&, const double*, hipStream_t);
+template void instantiate_impl<float, float>(InstData&, const double*, hipStream_t);
+template void instantiate_impl<float, bf16>(InstData&, const double*, hipStream_t);
 
 }  // namespace ph

@@ -409,9 +409,9 @@ __global__ void k_coupling_reduce(S* __restrict__ yh, const S* __restrict__ part
 // D (one aligned 128-byte line).  The (block, 16-column group) sequence is software
 // pipelined: the next group's D and x values are loaded while the current one feeds
 // the MFMAs.
-template <typename S>
+template <typename S, typename DT>
 __global__ void __launch_bounds__(NT) k_near_mvm(
-    const S* __restrict__ xt, S* __restrict__ yt, const S* __restrict__ D, const int64_t* __restrict__ nbegin,
+    const S* __restrict__ xt, S* __restrict__ yt, const DT* __restrict__ D, const int64_t* __restrict__ nbegin,
     const int64_t* __restrict__ nend, const int64_t* __restrict__ rowptr, const int64_t* __restrict__ ntb,
     const int32_t* __restrict__ nnt, const int64_t* __restrict__ nD, int32_t leaf0, int64_t n, int64_t R,
     int64_t N_nf) {
@@ -428,7 +428,7 @@ __global__ void __launch_bounds__(NT) k_near_mvm(
   const int64_t ld = (ns + 15) / 16 * 16;   // leading dimension of this leaf's row blocks
   const bool colok = r0 + m16 < R;
   const S* xs = xt + slot * n * R;
-  const S* Ds = D + slot * N_nf;
+  const DT* Ds = D + slot * N_nf;
   const int64_t bb0 = rowptr[li], bb1 = rowptr[li + 1];
   for (int64_t c0 = 0; c0 < ns; c0 += CH) {
     const int cn = (int)min<int64_t>(CH, ns - c0);
@@ -441,7 +441,7 @@ __global__ void __launch_bounds__(NT) k_near_mvm(
     int kb = 0;
     S a0n[4], a1n[4], bn[4];
     auto fetch = [&](int64_t fb, int fk) {
-      const S* Db = Ds + nD[fb] + c0;
+      const DT* Db = Ds + nD[fb] + c0;
       const int64_t tb = ntb[fb];
       const int nt = nnt[fb];
 #pragma unroll
@@ -449,8 +449,8 @@ __global__ void __launch_bounds__(NT) k_near_mvm(
         const int j = fk * 16 + u * 4 + kq;
         const bool jok = j < nt;
         bn[u] = (jok && colok) ? xs[(tb + j) * R + r0 + m16] : (S)0;
-        a0n[u] = (jok && r0ok) ? Db[i0 + (int64_t)j * ld] : (S)0;
-        a1n[u] = (jok && r1ok) ? Db[i1 + (int64_t)j * ld] : (S)0;
+        a0n[u] = (jok && r0ok) ? widen<S, DT>(Db[i0 + (int64_t)j * ld]) : (S)0;
+        a1n[u] = (jok && r1ok) ? widen<S, DT>(Db[i1 + (int64_t)j * ld]) : (S)0;
       }
     };
     if (bb < bb1) fetch(bb, kb);
@@ -554,7 +554,7 @@ __global__ void __launch_bounds__(NT) k_leaf_down(S* __restrict__ yt, const S* _
   }
 }
 
-template <typename S>
+template <typename S, typename DT>
 void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double beta, double nugget,
                  hipStream_t st) {
   const DeviceModel& m = *in.m;
@@ -605,8 +605,8 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
       PH_HIP(hipEventRecord(in.ev_fork, st));
       PH_HIP(hipStreamWaitEvent(in.aux, in.ev_fork, 0));
     }
-    launch(PH_STAGE_NEAR_MVM, k_near_mvm<S>, dim3((unsigned)m.n_leaves, (unsigned)nrc, (unsigned)T), dim3(NT),
-           nst, (const S*)xt, yt, (const S*)in.D.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
+    launch(PH_STAGE_NEAR_MVM, k_near_mvm<S, DT>, dim3((unsigned)m.n_leaves, (unsigned)nrc, (unsigned)T), dim3(NT),
+           nst, (const S*)xt, yt, (const DT*)in.D.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
            (const int64_t*)m.near_rowptr.p, (const int64_t*)m.near_tb.p, (const int32_t*)m.near_nt.p,
            (const int64_t*)m.near_D.p, leaf0, m.n, Rs, m.N_nf_pad);
     if (!serial) PH_HIP(hipEventRecord(in.ev_join, in.aux));
@@ -711,7 +711,7 @@ __global__ void __launch_bounds__(NT) k_dot_final(const double* __restrict__ par
   if (threadIdx.x == 0) out[t] = red[0];
 }
 
-template <typename S>
+template <typename S, typename DT>
 void bilinear_impl(InstData& in, const S* u, const S* x, int64_t R, double* out, hipStream_t st) {
   const DeviceModel& m = *in.m;
   const int64_t per_slot = m.n * R;
@@ -719,18 +719,21 @@ void bilinear_impl(InstData& in, const S* u, const S* x, int64_t R, double* out,
   if (in.bil.bytes() < need_bytes) in.bil.alloc(need_bytes);
   if (in.bil_part.n < (size_t)in.T * BIL_BLOCKS) in.bil_part.alloc((size_t)in.T * BIL_BLOCKS);
   S* v = (S*)in.bil.p;
-  matvec_impl<S>(in, x, v, R, 1.0, 0.0, 0.0, st);
+  matvec_impl<S, DT>(in, x, v, R, 1.0, 0.0, 0.0, st);
   launch(PH_STAGE_BILINEAR, k_dot_partial<S>, dim3(BIL_BLOCKS, (unsigned)in.T), dim3(NT), st, u, (const S*)v,
          in.bil_part.p, per_slot);
   launch(PH_STAGE_BILINEAR, k_dot_final, dim3((unsigned)in.T), dim3(NT), st, (const double*)in.bil_part.p, out);
 }
 
-template void bilinear_impl<double>(InstData&, const double*, const double*, int64_t, double*, hipStream_t);
-template void bilinear_impl<float>(InstData&, const float*, const float*, int64_t, double*, hipStream_t);
+template void bilinear_impl<double, double>(InstData&, const double*, const double*, int64_t, double*, hipStream_t);
+template void bilinear_impl<float, float>(InstData&, const float*, const float*, int64_t, double*, hipStream_t);
+template void bilinear_impl<float, bf16>(InstData&, const float*, const float*, int64_t, double*, hipStream_t);
 
-template void matvec_impl<double>(InstData&, const double*, double*, int64_t, double, double, double,
-                                  hipStream_t);
-template void matvec_impl<float>(InstData&, const float*, float*, int64_t, double, double, double,
-                                 hipStream_t);
+template void matvec_impl<double, double>(InstData&, const double*, double*, int64_t, double, double, double,
+                                          hipStream_t);
+template void matvec_impl<float, float>(InstData&, const float*, float*, int64_t, double, double, double,
+                                        hipStream_t);
+template void matvec_impl<float, bf16>(InstData&, const float*, float*, int64_t, double, double, double,
+                                       hipStream_t);
 
 }  // namespace ph

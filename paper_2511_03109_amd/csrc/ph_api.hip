@@ -285,7 +285,7 @@ int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype
     need(theta != nullptr, "theta is NULL");
     need(inout != nullptr, "inout is NULL");
     need(T >= 1, "T must be >= 1");
-    need(dt == PH_F64 || dt == PH_F32, "dtype must be PH_F64 or PH_F32");
+    need(dt == PH_F64 || dt == PH_F32 || dt == PH_BF16, "dtype must be PH_F64, PH_F32 or PH_BF16");
     const ph::DeviceModel& md = *m->p;
     if (dim >= 0) need(dim < md.d_theta, "gradient dimension out of range");
     for (int t = 0; t < T; ++t)
@@ -308,7 +308,8 @@ int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype
       in->dt = dt;
       in->grad_dim = dim;
       in->esize = dt == PH_F64 ? sizeof(double) : sizeof(float);
-      in->D.alloc((size_t)T * md.N_nf_pad * in->esize);
+      in->d_esize = dt == PH_F64 ? sizeof(double) : dt == PH_F32 ? sizeof(float) : sizeof(ph::bf16);
+      in->D.alloc((size_t)T * md.N_nf_pad * in->d_esize);
       in->C.alloc((size_t)T * md.n_classes * md.Pp * md.Pp * in->esize);
       in->v.alloc((size_t)T * md.d_theta * md.p_theta);
       in->ffs.alloc((size_t)T * std::max<int64_t>(md.ff_scratch, 1));
@@ -316,8 +317,10 @@ int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype
       PH_HIP(hipEventCreateWithFlags(&in->ev_fork, hipEventDisableTiming));
       PH_HIP(hipEventCreateWithFlags(&in->ev_join, hipEventDisableTiming));
     }
-    if (dt == PH_F64) ph::instantiate_impl<double>(*in, theta, st);
-    else ph::instantiate_impl<float>(*in, theta, st);
+    in->theta.assign(theta, theta + (size_t)T * md.d_theta);
+    if (dt == PH_F64) ph::instantiate_impl<double, double>(*in, theta, st);
+    else if (dt == PH_F32) ph::instantiate_impl<float, float>(*in, theta, st);
+    else ph::instantiate_impl<float, ph::bf16>(*in, theta, st);
     if (!*inout) *inout = new ph_inst{in};
   });
 }
@@ -467,9 +470,11 @@ int ph_matvec(ph_inst* k, const void* x, void* y, int64_t R, double alpha, doubl
     ph::InstData& in = *k->p;
     hipStream_t st = (hipStream_t)stream;
     if (in.dt == PH_F64)
-      ph::matvec_impl<double>(in, (const double*)x, (double*)y, R, alpha, beta, nugget, st);
+      ph::matvec_impl<double, double>(in, (const double*)x, (double*)y, R, alpha, beta, nugget, st);
+    else if (in.dt == PH_F32)
+      ph::matvec_impl<float, float>(in, (const float*)x, (float*)y, R, alpha, beta, nugget, st);
     else
-      ph::matvec_impl<float>(in, (const float*)x, (float*)y, R, alpha, beta, nugget, st);
+      ph::matvec_impl<float, ph::bf16>(in, (const float*)x, (float*)y, R, alpha, beta, nugget, st);
   });
 }
 
@@ -481,9 +486,34 @@ int ph_bilinear(ph_inst* k, const void* u, const void* x, int64_t R, double* out
     ph::InstData& in = *k->p;
     hipStream_t st = (hipStream_t)stream;
     if (in.dt == PH_F64)
-      ph::bilinear_impl<double>(in, (const double*)u, (const double*)x, R, out, st);
+      ph::bilinear_impl<double, double>(in, (const double*)u, (const double*)x, R, out, st);
+    else if (in.dt == PH_F32)
+      ph::bilinear_impl<float, float>(in, (const float*)u, (const float*)x, R, out, st);
     else
-      ph::bilinear_impl<float>(in, (const float*)u, (const float*)x, R, out, st);
+      ph::bilinear_impl<float, ph::bf16>(in, (const float*)u, (const float*)x, R, out, st);
+  });
+}
+
+int ph_cg_solve(ph_inst* hi, ph_inst* lo, const double* y, double* a, double nugget, double tol, int max_iter,
+                int inner_max, double inner_tol, ph_cg_stats* stats, void* stream) {
+  return guarded([&] {
+    need(hi && hi->p, "FP64 instance is NULL");
+    need(y && a, "y or a is NULL");
+    ph::InstData& h = *hi->p;
+    need(h.dt == PH_F64 && h.T == 1, "hi must be a PH_F64 instance with T = 1");
+    need(h.grad_dim < 0, "hi must not be a gradient instance");
+    need(tol > 0 && max_iter >= 1, "tol must be > 0 and max_iter >= 1");
+    need(nugget >= 0, "nugget must be >= 0");
+    ph::InstData* l = nullptr;
+    if (lo) {
+      need(lo->p != nullptr, "low-precision instance is empty");
+      l = lo->p.get();
+      need(l->dt == PH_F32 || l->dt == PH_BF16, "lo must be a PH_F32 or PH_BF16 instance");
+      need(l->m == h.m && l->T == 1 && l->grad_dim < 0 && l->theta == h.theta,
+           "lo must instantiate the same model at the same theta");
+      need(inner_max >= 1 && inner_tol > 0, "inner_max must be >= 1 and inner_tol > 0");
+    }
+    ph::cg_solve_impl(h, l, y, a, nugget, tol, max_iter, inner_max, inner_tol, stats, (hipStream_t)stream);
   });
 }
 
@@ -498,13 +528,15 @@ int ph_inst_near_block(const ph_inst* k, int t, int64_t b, double* host_out) {
     const ph::TreeData& tr = *m.tree;
     const int64_t ns = tr.size(tr.near[2 * b]), nt = tr.size(tr.near[2 * b + 1]), ld = (ns + 15) / 16 * 16;
     PH_HIP(hipDeviceSynchronize());
-    std::vector<char> buf(cnt * in.esize);
-    PH_HIP(hipMemcpy(buf.data(), in.D.p + ((size_t)t * m.N_nf_pad + off) * in.esize, buf.size(),
+    std::vector<char> buf(cnt * in.d_esize);
+    PH_HIP(hipMemcpy(buf.data(), in.D.p + ((size_t)t * m.N_nf_pad + off) * in.d_esize, buf.size(),
                      hipMemcpyDeviceToHost));
     for (int64_t j = 0; j < nt; ++j)
       for (int64_t i = 0; i < ns; ++i) {
         const int64_t src = i + j * ld;
-        host_out[i + j * ns] = in.dt == PH_F64 ? ((double*)buf.data())[src] : (double)((float*)buf.data())[src];
+        host_out[i + j * ns] = in.dt == PH_F64   ? ((double*)buf.data())[src]
+                               : in.dt == PH_F32 ? (double)((float*)buf.data())[src]
+                                                 : (double)ph::from_bf16(((ph::bf16*)buf.data())[src]);
       }
   });
 }

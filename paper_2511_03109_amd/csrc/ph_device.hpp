@@ -52,6 +52,34 @@ struct DevArr {
   size_t bytes() const { return n * sizeof(T); }
 };
 
+// BF16 storage (1 sign, 8 exponent, 7 fraction bits): the upper half of an FP32 value.
+// Conversion rounds to nearest, ties to even (NaN stays NaN); widening is exact.
+struct bf16 {
+  uint16_t bits;
+};
+__host__ __device__ inline bf16 to_bf16(float f) {
+  uint32_t u;
+  __builtin_memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return bf16{(uint16_t)((u >> 16) | 0x40)};   // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return bf16{(uint16_t)(u >> 16)};
+}
+__host__ __device__ inline float from_bf16(bf16 h) {
+  const uint32_t u = (uint32_t)h.bits << 16;
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return f;
+}
+// storage of a computed value (double accumulator) and its widening for arithmetic
+template <typename DT>
+__host__ __device__ inline DT to_store(double x) { return (DT)x; }
+template <>
+__host__ __device__ inline bf16 to_store<bf16>(double x) { return to_bf16((float)x); }
+template <typename S, typename DT>
+__host__ __device__ inline S widen(DT x) { return (S)x; }
+template <>
+__host__ __device__ inline float widen<float, bf16>(bf16 x) { return from_bf16(x); }
+
 // per stored near block (s <= t)
 // (leading dimensions: ldp of the stored factor columns, lds / ldt of the instantiated
 // (s, t) / (t, s) blocks; all are the row counts rounded up to a multiple of 16)
@@ -116,7 +144,9 @@ struct InstData {
   int T = 1;
   ph_dtype dt = PH_F64;
   int grad_dim = -1;
-  size_t esize = 8;
+  std::vector<double> theta;          // T x d_theta, as last instantiated
+  size_t esize = 8;                   // element size of C, x_hat, y_hat, I/O (compute type)
+  size_t d_esize = 8;                 // element size of the near blocks D (storage type)
   DevArr<char> D, C;
   DevArr<double> v, ffs;
   int64_t Rcap = 0;
@@ -133,13 +163,16 @@ struct InstData {
   }
 };
 
-template <typename S>
+// S: compute type (C, x_hat, I/O); DT: storage type of the near blocks D
+template <typename S, typename DT>
 void instantiate_impl(InstData& in, const double* theta, hipStream_t st);
-template <typename S>
+template <typename S, typename DT>
 void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double beta, double nugget,
                  hipStream_t st);
-template <typename S>
+template <typename S, typename DT>
 void bilinear_impl(InstData& in, const S* u, const S* x, int64_t R, double* out, hipStream_t st);
+void cg_solve_impl(InstData& hi, InstData* lo, const double* y, double* a, double nugget, double tol,
+                   int max_iter, int inner_max, double inner_tol, ph_cg_stats* stats, hipStream_t st);
 
 // ---- per-kernel timing with HIP events
 struct TraceRec {

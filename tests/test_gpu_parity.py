@@ -304,3 +304,87 @@ def test_bilinear_is_deterministic():
     assert np.array_equal(a, b)
     ref = np.sum(u.cpu().numpy().T * om.matvec(om.instantiate(0.25), x.cpu().numpy().T))
     _close(a, [ref], what="bilinear")
+
+
+def _bf16_round(a):
+    """Round float64 values to BF16 (via FP32, both to nearest-even), returned as float64."""
+    f = np.asarray(a, dtype=np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def test_bf16_near_blocks_are_rounded_fp64_blocks():
+    """A PH_BF16 instance stores each near-block entry of the FP64 instantiation rounded to
+    nearest-even BF16: bit-exact against the FP64 instance's blocks rounded on the host."""
+    _torch()
+    from paper_2511_03109_amd import api
+    X = inputs.points_for(2, 4096)
+    lt, lm, om = _setup(X, "matern32", [0.05], [0.5], 5, 11, 1e-8, 2, (3, 1))
+    i64 = api.Instance(lm, [0.3])
+    i16 = api.Instance(lm, [0.3], dtype="bf16")
+    for b in range(0, lt.info["n_near"], 7):
+        assert np.array_equal(i16.near_block(b), _bf16_round(i64.near_block(b))), f"block {b}"
+
+
+def test_bf16_mvm_error_bound():
+    """BF16 near blocks: ||y - y_oracle|| <= 2^-8 || |D| |x| || (unit roundoff of BF16 times the
+    near field applied to magnitudes) + 2e-6 ||y_oracle|| (the FP32 arithmetic, as the FP32 test)."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    X = inputs.points_for(2, 4096)
+    lt, lm, om = _setup(X, "matern32", [0.05], [0.5], 5, 11, 1e-8, 2, (3, 1))
+    x = inputs.normal_vectors(4096, 4, 9)
+    y = api.Instance(lm, [0.3], dtype="bf16").matvec(
+        torch.tensor(np.ascontiguousarray(x.T), device="cuda", dtype=torch.float32)).cpu().numpy().T
+    oi = om.instantiate(0.3)
+    y_o = om.matvec(oi, x)
+    mag = om.matvec({"D": {b: np.abs(D) for b, D in oi["D"].items()},
+                     "C": {k: np.zeros_like(C) for k, C in oi["C"].items()}}, np.abs(x))
+    err = np.linalg.norm(y - y_o)
+    bound = 2.0 ** -8 * np.linalg.norm(mag) + 2e-6 * np.linalg.norm(y_o)
+    print(f"[parity] bf16 mvm: relative error {err / np.linalg.norm(y_o):.3e}, bound {bound / np.linalg.norm(y_o):.3e}",
+          flush=True)
+    assert err <= bound
+
+
+def _solve_case(kernel, theta, nugget, dtype_lo, tol):
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    n = 4096
+    X = inputs.points_for(5, n)
+    lt, lm, om = _setup(X, kernel, [0.05], [0.5], 6, 9, 1e-8, 3, (2, 1))
+    y = inputs.normal_vectors(n, 1, 5, inputs.STREAM_Y)[:, 0]
+    hi = api.Instance(lm, [theta])
+    lo = api.Instance(lm, [theta], dtype=dtype_lo) if dtype_lo else None
+    a, st = api.cg_solve(hi, torch.tensor(y, device="cuda"), nugget=nugget, tol=tol, lo=lo,
+                         max_iter=20000 if lo is None else 200, inner_max=2000, inner_tol=1e-3)
+    a = a.cpu().numpy()
+    # residual of the library's solution under the oracle's operator; the two operators
+    # differ by ~1e-14 relative, which moves the residual by at most 1e-12 ||K~ a|| / ||y||
+    Ka = om.matvec(om.instantiate(theta), a)
+    res = np.linalg.norm(y - Ka - nugget * a) / np.linalg.norm(y)
+    slack = 1e-12 * np.linalg.norm(Ka) / np.linalg.norm(y)
+    print(f"[parity] cg ({dtype_lo or 'f64'}): stats {st}, oracle residual {res:.3e} (tol {tol:.0e}, "
+          f"slack {slack:.1e})", flush=True)
+    assert st["converged"] == 1
+    assert abs(res - st["rel_residual"]) <= slack + 1e-3 * tol
+    assert res <= 1.001 * tol + slack
+    return st
+
+
+def test_cg_fp64():
+    """Plain FP64 CG on (K~ + 1e-2 I) a = y, Matern-1/2 at l = 0.1, checked with the oracle."""
+    _solve_case("matern12", 0.1, 1e-2, None, 1e-8)
+
+
+def test_cg_iterative_refinement_fp32():
+    """FP64 iterative refinement around FP32 inner CG reaches the same FP64 residual."""
+    st = _solve_case("matern12", 0.1, 1e-2, "f32", 1e-8)
+    assert st["outer_steps"] >= 2
+
+
+def test_cg_iterative_refinement_bf16_well_conditioned():
+    """BF16 near blocks as the inner operator: refinement contracts when the condition number
+    times the BF16 unit roundoff is below one (nugget 10 here)."""
+    _solve_case("matern12", 0.1, 10.0, "bf16", 1e-8)
