@@ -258,6 +258,37 @@ typedef struct {
 int ph_cg_solve(ph_inst* hi, ph_inst* lo, const double* y, double* a, double nugget, double tol, int max_iter,
                 int inner_max, double inner_tol, ph_cg_stats* stats, void* stream);
 
+/* ---- batched launches -----------------------------------------------------------------
+ * Launch configuration of ph_matvec picked by measurement (autotuner): for the instance's
+ * T slots and R right-hand sides, every combination of coupling class-list chunks
+ * (1, 2, 4, 8, 16, at most the longest class list of a target box), register prefetch
+ * depth of the coupling pipeline (1, 2) and near field overlapped on a second stream or
+ * not is timed (3 runs after a warm-up, HIP events on `stream`), and the fastest is kept
+ * in the instance for all later ph_matvec calls.  x, y: as ph_matvec (y is overwritten).
+ * Synchronises `stream`.  Must precede ph_graph_create. */
+typedef struct {
+  int chunks, prefetch, overlap;
+  double ms;              /* measured time of one ph_matvec with this configuration */
+} ph_tune_info;
+int ph_autotune(ph_inst* k, const void* x, void* y, int64_t R, void* stream, ph_tune_info* info);
+
+/* Record instantiation + MVM of instance k as one HIP graph: theta vectors, far and near
+ * instantiation of all T slots, then y = (K~ + nugget I) x for R right-hand sides (alpha
+ * 1, beta 0), with the near field on the instance's second stream.  x, y (device) are
+ * bound into the graph.  stream must not be the null stream.  Runs one MVM first to
+ * allocate all scratch; afterwards the instance's scratch is fixed (a ph_matvec that
+ * would need more fails with PH_ESTATE) until every graph of the instance is freed.
+ * *out is caller-owned (ph_graph_free). */
+typedef struct ph_graph ph_graph;
+int ph_graph_create(ph_inst* k, const void* x, void* y, int64_t R, double nugget, void* stream, ph_graph** out);
+
+/* Replay a recorded graph: with theta != NULL (host, T x d_theta, checked against Theta
+ * as ph_instantiate does) the instance is re-instantiated at these values, else at the
+ * last ones.  One graph launch on `stream`; asynchronous (the host waits only for the
+ * previous launch's read of its theta staging buffer). */
+int ph_graph_launch(ph_graph* g, const double* theta, void* stream);
+void ph_graph_free(ph_graph* g);
+
 /* Inspection (tests): copy the instantiated near block of canonical near index b for
  * slot t (n_s x n_t column-major, as double) or the coupling matrix of class c
  * (P x P column-major, as double) to host memory.  Synchronises the device. */

@@ -34,6 +34,10 @@ class CgStats(C.Structure):
                 ("converged", C.c_int)]
 
 
+class TuneInfo(C.Structure):
+    _fields_ = [("chunks", C.c_int), ("prefetch", C.c_int), ("overlap", C.c_int), ("ms", C.c_double)]
+
+
 class ModelInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_near_stored", C.c_int64), ("n_classes_stored", C.c_int64),
                 ("near_entries", C.c_int64), ("near_factor_entries", C.c_int64),
@@ -77,6 +81,10 @@ SIGNATURES = {
     "ph_bilinear": ([_P, _P, _P, C.c_int64, _P, _P], C.c_int),
     "ph_cg_solve": ([_P, _P, _P, _P, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
                      C.POINTER(CgStats), _P], C.c_int),
+    "ph_autotune": ([_P, _P, _P, C.c_int64, _P, C.POINTER(TuneInfo)], C.c_int),
+    "ph_graph_create": ([_P, _P, _P, C.c_int64, C.c_double, _P, C.POINTER(_P)], C.c_int),
+    "ph_graph_launch": ([_P, _DP, _P], C.c_int),
+    "ph_graph_free": ([_P], None),
     "ph_inst_near_block": ([_P, C.c_int, C.c_int64, _DP], C.c_int),
     "ph_inst_coupling": ([_P, C.c_int, C.c_int64, _DP], C.c_int),
     "ph_inst_free": ([_P], None),

@@ -199,6 +199,22 @@ class Instance:
         L.check(code, "ph_bilinear")
         return out
 
+    def autotune(self, x, y=None, *, stream=None):
+        """Pick the MVM launch configuration by measurement (ph_autotune); returns it as a dict."""
+        import torch
+        x = x.contiguous()
+        if y is None:
+            y = torch.empty_like(x)
+        R = 1 if x.dim() == 1 else x.shape[-2]
+        info = L.TuneInfo()
+        L.check(L.lib().ph_autotune(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), R,
+                                    _stream(stream), C.byref(info)), "ph_autotune")
+        return {k: getattr(info, k) for k, _ in L.TuneInfo._fields_}
+
+    def record(self, x, y, *, nugget=0.0, stream=None):
+        """Record instantiation + MVM (y = (K~ + nugget I) x) as one replayable graph (ph_graph_create)."""
+        return Graph(self, x, y, nugget, stream)
+
     def near_block(self, b, t=0):
         near, _, _ = self.model.tree.blocks()
         nodes = self.model.tree.nodes()
@@ -220,6 +236,39 @@ class Instance:
         self._h = None
         if h and L is not None and L._lib is not None:   # (skip at interpreter shutdown)
             L._lib.ph_inst_free(h)
+
+
+class Graph:
+    """A recorded instantiate + MVM launch of an instance; launch(theta) replays it."""
+
+    def __init__(self, inst, x, y, nugget, stream):
+        import torch
+        if stream is None:
+            raise ValueError("recording needs an explicit non-default torch.cuda.Stream")
+        if not (x.is_contiguous() and y.is_contiguous()) or x.shape != y.shape:
+            raise ValueError("x and y must be contiguous tensors of the same shape")
+        self.inst, self.x, self.y, self.stream = inst, x, y, stream   # keep the bound buffers alive
+        R = 1 if x.dim() == 1 else x.shape[-2]
+        h = C.c_void_p()
+        L.check(L.lib().ph_graph_create(inst._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), R, nugget,
+                                        _stream(stream), C.byref(h)), "ph_graph_create")
+        self._h = h
+
+    def launch(self, theta=None, *, stream=None):
+        th = None
+        if theta is not None:
+            th = self.inst._theta(theta)
+            if th.shape[0] != self.inst.T:
+                raise ValueError("theta must have T rows")
+        L.check(L.lib().ph_graph_launch(self._h, _dptr(th) if th is not None else None,
+                                        _stream(stream if stream is not None else self.stream)), "ph_graph_launch")
+        return self.y
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h and L is not None and L._lib is not None:   # (skip at interpreter shutdown)
+            L._lib.ph_graph_free(h)
 
 
 def cg_solve(inst64, y, *, nugget, tol=1e-6, lo=None, max_iter=100000, inner_max=1000, inner_tol=1e-4,

@@ -2,44 +2,46 @@
 // parametric vectors, far-field couplings C(theta) = L H(theta) R^T (Sec. 4.2) and
 // near-field blocks D_b(theta) = reshape(P_b c_b(theta), [n_s, n_t]) (Sec. 4.3).
 // No kernel evaluation happens here.
+#include <cstring>
+
 #include "ph_device.hpp"
 
 namespace ph {
 
-struct ThetaPack {
-  double th[MAXT * 2];
+struct ThetaBox {
   double lo[2], hi[2];
-  int count, dth, p, grad_dim;
 };
 
 // v[(t*dth + k)*p + i] = l_i(theta_{t,k}) on [lo_k, hi_k] with first-kind Chebyshev
-// nodes (product formula, Sec. 2.2); its derivative for k == grad_dim.
-__global__ void k_theta_vectors(ThetaPack tp, double* __restrict__ v, int t0) {
-  const int total = tp.count * tp.dth * tp.p;
-  for (int o = threadIdx.x; o < total; o += blockDim.x) {
-    const int i = o % tp.p;
-    const int k = (o / tp.p) % tp.dth;
-    const int t = o / (tp.p * tp.dth);
-    const double a = tp.lo[k], b = tp.hi[k], x = tp.th[t * 2 + k];
+// nodes (product formula, Sec. 2.2); its derivative for k == grad_dim.  theta is a
+// device array T x dth (so that a recorded graph can be replayed with new values).
+__global__ void k_theta_vectors(const double* __restrict__ theta, ThetaBox box, double* __restrict__ v, int T,
+                                int dth, int p, int grad_dim) {
+  const int total = T * dth * p;
+  for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < total; o += gridDim.x * blockDim.x) {
+    const int i = o % p;
+    const int k = (o / p) % dth;
+    const int t = o / (p * dth);
+    const double a = box.lo[k], b = box.hi[k], x = theta[t * dth + k];
     double nodes[16];
-    for (int q = 0; q < tp.p; ++q)
-      nodes[q] = (a + b) / 2.0 - (b - a) / 2.0 * cos((2.0 * (q + 1) - 1.0) * M_PI / (2.0 * tp.p));
+    for (int q = 0; q < p; ++q)
+      nodes[q] = (a + b) / 2.0 - (b - a) / 2.0 * cos((2.0 * (q + 1) - 1.0) * M_PI / (2.0 * p));
     double val;
-    if (k != tp.grad_dim) {
+    if (k != grad_dim) {
       val = 1.0;
-      for (int q = 0; q < tp.p; ++q)
+      for (int q = 0; q < p; ++q)
         if (q != i) val *= (x - nodes[q]) / (nodes[i] - nodes[q]);
     } else {
       val = 0.0;
-      for (int m = 0; m < tp.p; ++m) {
+      for (int m = 0; m < p; ++m) {
         if (m == i) continue;
         double term = 1.0 / (nodes[i] - nodes[m]);
-        for (int q = 0; q < tp.p; ++q)
+        for (int q = 0; q < p; ++q)
           if (q != i && q != m) term *= (x - nodes[q]) / (nodes[i] - nodes[q]);
         val += term;
       }
     }
-    v[((size_t)(t0 + t) * tp.dth + k) * tp.p + i] = val;
+    v[((size_t)t * dth + k) * p + i] = val;
   }
 }
 
@@ -226,20 +228,27 @@ __global__ void __launch_bounds__(NT) k_near_instantiate(
 template <typename S, typename DT>
 void instantiate_impl(InstData& in, const double* theta, hipStream_t st) {
   const DeviceModel& m = *in.m;
-  for (int t0 = 0; t0 < in.T; t0 += MAXT) {
-    ThetaPack tp{};
-    tp.count = std::min(MAXT, in.T - t0);
-    tp.dth = m.d_theta;
-    tp.p = m.p_theta;
-    tp.grad_dim = in.grad_dim;
-    for (int k = 0; k < 2; ++k) {
-      tp.lo[k] = m.th_lo[k];
-      tp.hi[k] = m.th_hi[k];
-    }
-    for (int t = 0; t < tp.count; ++t)
-      for (int k = 0; k < m.d_theta; ++k) tp.th[t * 2 + k] = theta[(size_t)(t0 + t) * m.d_theta + k];
-    launch(PH_STAGE_THETA, k_theta_vectors, dim3(1), dim3(NT), st, tp, in.v.p, t0);
+  // theta -> pinned staging -> device.  The staging buffer is rewritten only after the
+  // previous copy out of it has run (ev_theta); under graph capture the copy becomes a
+  // graph node that reads the staging buffer at replay time.
+  const size_t nth = (size_t)in.T * m.d_theta;
+  if (theta) {
+    if (in.theta_pending) PH_HIP(hipEventSynchronize(in.ev_theta));
+    std::memcpy(in.theta_pin, theta, nth * sizeof(double));
   }
+  PH_HIP(hipMemcpyAsync(in.theta_d.p, in.theta_pin, nth * sizeof(double), hipMemcpyHostToDevice, st));
+  if (!g_capturing) {
+    PH_HIP(hipEventRecord(in.ev_theta, st));
+    in.theta_pending = true;
+  }
+  ThetaBox box{};
+  for (int k = 0; k < 2; ++k) {
+    box.lo[k] = m.th_lo[k];
+    box.hi[k] = m.th_hi[k];
+  }
+  const int64_t nv = (int64_t)in.T * m.d_theta * m.p_theta;
+  launch(PH_STAGE_THETA, k_theta_vectors, dim3((unsigned)grid_for(nv)), dim3(NT), st, (const double*)in.theta_d.p,
+         box, in.v.p, in.T, m.d_theta, m.p_theta, in.grad_dim);
   const int64_t Cps = m.n_classes * m.Pp * m.Pp;
   launch(PH_STAGE_FAR_INST, k_far_instantiate<S>, dim3((unsigned)m.n_stored_cls, in.T), dim3(NT), st,
          (const ClassDev*)m.cstore.p, (const double*)m.ff_L.p, (const double*)m.ff_R.p,

@@ -565,16 +565,21 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
   const bool use_far = m.min_far >= 0;
   // class-list chunks per target box: 8 (one per XCD) unless the lists are too short;
   // PH_COUPLING_CHUNKS overrides (tuning)
+  // launch configuration: environment override (tuning sweeps), else ph_autotune's
+  // choice, else the heuristic (8 chunks, prefetch 1, near field overlapped)
   int G = 1;
   if (use_far && m.n_groups > 0) G = m.max_group_entries >= 16 ? 8 : (m.max_group_entries >= 4 ? 2 : 1);
+  if (in.tune_chunks > 0) G = std::min<int64_t>(in.tune_chunks, std::max<int64_t>(m.max_group_entries, 1));
   if (const char* env = std::getenv("PH_COUPLING_CHUNKS")) {
     const int g = std::atoi(env);
     if (g >= 1 && g <= 64 && g <= std::max<int64_t>(m.max_group_entries, 1)) G = g;
   }
   // PH_SERIAL_MVM=1 runs the near field on the caller's stream (no overlap; profiling)
-  const bool serial = std::getenv("PH_SERIAL_MVM") && std::atoi(std::getenv("PH_SERIAL_MVM")) != 0;
+  bool serial = in.tune_overlap == 0;
+  if (const char* env = std::getenv("PH_SERIAL_MVM")) serial = std::atoi(env) != 0;
   hipStream_t nst = serial ? st : in.aux;
   if (Rs > in.Rcap || G > in.Gcap) {
+    if (in.graphs > 0) fail(PH_ESTATE, "ph_matvec: the instance has recorded graphs, its scratch cannot grow");
     const int64_t Rc = std::max<int64_t>(Rs, in.Rcap);
     const int Gc = std::max(G, in.Gcap);
     in.xt.alloc((size_t)T * m.n * Rc * sizeof(S));
@@ -633,7 +638,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     };
     // 8 waves (4 row groups x 2 target halves) for Pp > 64, else 4 waves over the targets;
     // PH_COUPLING_PD selects the register prefetch depth (1 or 2)
-    int pd = 1;
+    int pd = in.tune_prefetch == 2 ? 2 : 1;
     if (const char* env = std::getenv("PH_COUPLING_PD")) pd = std::atoi(env) == 2 ? 2 : 1;
     const int nMt = m.Pp / 16;
     if (nMt == 8) {

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <memory>
 
 #include "ph_device.hpp"
 
@@ -13,6 +14,7 @@ static thread_local std::string g_last_error;
 
 std::mutex g_trace_mu;
 bool g_trace_on = false;
+thread_local bool g_capturing = false;
 std::vector<TraceRec> g_trace_recs;
 static std::vector<hipEvent_t> g_event_pool;
 
@@ -250,6 +252,16 @@ struct ph_model {
 struct ph_inst {
   std::shared_ptr<ph::InstData> p;
 };
+struct ph_graph {
+  std::shared_ptr<ph::InstData> in;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~ph_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (in) --in->graphs;
+  }
+};
 
 namespace {
 
@@ -312,6 +324,9 @@ int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype
       in->D.alloc((size_t)T * md.N_nf_pad * in->d_esize);
       in->C.alloc((size_t)T * md.n_classes * md.Pp * md.Pp * in->esize);
       in->v.alloc((size_t)T * md.d_theta * md.p_theta);
+      in->theta_d.alloc((size_t)T * md.d_theta);
+      PH_HIP(hipHostMalloc((void**)&in->theta_pin, (size_t)T * md.d_theta * sizeof(double), hipHostMallocDefault));
+      PH_HIP(hipEventCreateWithFlags(&in->ev_theta, hipEventDisableTiming));
       in->ffs.alloc((size_t)T * std::max<int64_t>(md.ff_scratch, 1));
       PH_HIP(hipStreamCreateWithFlags(&in->aux, hipStreamNonBlocking));
       PH_HIP(hipEventCreateWithFlags(&in->ev_fork, hipEventDisableTiming));
@@ -516,6 +531,131 @@ int ph_cg_solve(ph_inst* hi, ph_inst* lo, const double* y, double* a, double nug
     ph::cg_solve_impl(h, l, y, a, nugget, tol, max_iter, inner_max, inner_tol, stats, (hipStream_t)stream);
   });
 }
+
+int ph_autotune(ph_inst* k, const void* x, void* y, int64_t R, void* stream, ph_tune_info* info) {
+  return guarded([&] {
+    need(k && k->p, "instance is NULL");
+    need(x && y && R >= 1, "x, y must be non-NULL and R >= 1");
+    ph::InstData& in = *k->p;
+    need(in.graphs == 0, "instance has recorded graphs; tune before recording");
+    const ph::DeviceModel& m = *in.m;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t a, b;
+    PH_HIP(hipEventCreate(&a));
+    PH_HIP(hipEventCreate(&b));
+    auto run = [&] {
+      if (in.dt == PH_F64)
+        ph::matvec_impl<double, double>(in, (const double*)x, (double*)y, R, 1.0, 0.0, 0.0, st);
+      else if (in.dt == PH_F32)
+        ph::matvec_impl<float, float>(in, (const float*)x, (float*)y, R, 1.0, 0.0, 0.0, st);
+      else
+        ph::matvec_impl<float, ph::bf16>(in, (const float*)x, (float*)y, R, 1.0, 0.0, 0.0, st);
+    };
+    std::vector<int> chunks{1};
+    for (int g : {2, 4, 8, 16})
+      if (g <= m.max_group_entries) chunks.push_back(g);
+    const int reps = 3;
+    float best = 1e30f;
+    ph_tune_info bi{};
+    for (int ov : {1, 0})
+      for (int pd : {1, 2})
+        for (int g : chunks) {
+          in.tune_chunks = g;
+          in.tune_prefetch = pd;
+          in.tune_overlap = ov;
+          run();   // warm-up (allocates scratch for this configuration)
+          PH_HIP(hipEventRecord(a, st));
+          for (int r = 0; r < reps; ++r) run();
+          PH_HIP(hipEventRecord(b, st));
+          PH_HIP(hipEventSynchronize(b));
+          float ms = 0;
+          PH_HIP(hipEventElapsedTime(&ms, a, b));
+          ms /= reps;
+          if (ms < best) {
+            best = ms;
+            bi = ph_tune_info{g, pd, ov, (double)ms};
+          }
+        }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    in.tune_chunks = bi.chunks;
+    in.tune_prefetch = bi.prefetch;
+    in.tune_overlap = bi.overlap;
+    if (info) *info = bi;
+  });
+}
+
+int ph_graph_create(ph_inst* k, const void* x, void* y, int64_t R, double nugget, void* stream, ph_graph** out) {
+  return guarded([&] {
+    need(k && k->p && out, "NULL argument");
+    need(x && y && R >= 1, "x, y must be non-NULL and R >= 1");
+    ph::InstData& in = *k->p;
+    hipStream_t st = (hipStream_t)stream;
+    need(st != nullptr, "recording needs a non-default stream");
+    auto mv = [&] {
+      if (in.dt == PH_F64)
+        ph::matvec_impl<double, double>(in, (const double*)x, (double*)y, R, 1.0, 0.0, nugget, st);
+      else if (in.dt == PH_F32)
+        ph::matvec_impl<float, float>(in, (const float*)x, (float*)y, R, 1.0, 0.0, nugget, st);
+      else
+        ph::matvec_impl<float, ph::bf16>(in, (const float*)x, (float*)y, R, 1.0, 0.0, nugget, st);
+    };
+    auto inst = [&] {
+      if (in.dt == PH_F64) ph::instantiate_impl<double, double>(in, nullptr, st);
+      else if (in.dt == PH_F32) ph::instantiate_impl<float, float>(in, nullptr, st);
+      else ph::instantiate_impl<float, ph::bf16>(in, nullptr, st);
+    };
+    mv();   // allocates every scratch buffer the recorded launches use
+    PH_HIP(hipStreamSynchronize(st));
+    if (in.theta_pending) PH_HIP(hipEventSynchronize(in.ev_theta));
+    auto g = std::make_unique<ph_graph>();
+    g->in = k->p;
+    ph::g_capturing = true;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+      try {
+        inst();
+        mv();
+      } catch (...) {
+        hipGraph_t junk = nullptr;
+        (void)hipStreamEndCapture(st, &junk);
+        if (junk) (void)hipGraphDestroy(junk);
+        ph::g_capturing = false;
+        throw;
+      }
+      e = hipStreamEndCapture(st, &g->graph);
+    }
+    ph::g_capturing = false;
+    if (e != hipSuccess) ph::fail(PH_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    PH_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    ++in.graphs;
+    *out = g.release();
+  });
+}
+
+int ph_graph_launch(ph_graph* g, const double* theta, void* stream) {
+  return guarded([&] {
+    need(g && g->exec, "graph is NULL");
+    ph::InstData& in = *g->in;
+    const ph::DeviceModel& md = *in.m;
+    if (theta) {
+      for (int t = 0; t < in.T; ++t)
+        for (int k = 0; k < md.d_theta; ++k) {
+          const double v = theta[(size_t)t * md.d_theta + k];
+          if (!(v >= md.th_lo[k] && v <= md.th_hi[k])) ph::fail(PH_EDOMAIN, "theta outside the parameter box");
+        }
+      if (in.theta_pending) PH_HIP(hipEventSynchronize(in.ev_theta));
+      std::memcpy(in.theta_pin, theta, (size_t)in.T * md.d_theta * sizeof(double));
+      in.theta.assign(theta, theta + (size_t)in.T * md.d_theta);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    PH_HIP(hipGraphLaunch(g->exec, st));
+    PH_HIP(hipEventRecord(in.ev_theta, st));
+    in.theta_pending = true;
+  });
+}
+
+void ph_graph_free(ph_graph* g) { delete g; }
 
 int ph_inst_near_block(const ph_inst* k, int t, int64_t b, double* host_out) {
   return guarded([&] {

@@ -156,9 +156,18 @@ struct InstData {
   DevArr<double> bil_part;            // ph_bilinear: per-block partial sums
   hipStream_t aux = nullptr;          // second stream: near field concurrent with the far chain
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  DevArr<double> theta_d;             // T x d_theta on the device (read by the theta-vector kernel)
+  double* theta_pin = nullptr;        // pinned staging of theta
+  hipEvent_t ev_theta = nullptr;      // after the last use of theta_pin
+  bool theta_pending = false;
+  int graphs = 0;                     // live graphs recorded from this instance (scratch is fixed)
+  // launch configuration of the MVM chosen by ph_autotune (0 = default heuristics)
+  int tune_chunks = 0, tune_prefetch = 0, tune_overlap = -1;
   ~InstData() {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_theta) (void)hipEventDestroy(ev_theta);
+    if (theta_pin) (void)hipHostFree(theta_pin);
     if (aux) (void)hipStreamDestroy(aux);
   }
 };
@@ -181,6 +190,7 @@ struct TraceRec {
 };
 extern std::mutex g_trace_mu;
 extern bool g_trace_on;
+extern thread_local bool g_capturing;   // recording a graph on this thread: no tracing events
 extern std::vector<TraceRec> g_trace_recs;
 hipEvent_t pooled_event();  // caller holds g_trace_mu
 
@@ -189,7 +199,7 @@ template <typename K, typename... Args>
 inline void launch(int stage, K kernel, dim3 grid, dim3 block, hipStream_t st, Args... args) {
   if (grid.x == 0 || grid.y == 0 || grid.z == 0) return;
   hipEvent_t a = nullptr, b = nullptr;
-  const bool tr = g_trace_on;
+  const bool tr = g_trace_on && !g_capturing;
   if (tr) {
     std::lock_guard<std::mutex> lk(g_trace_mu);
     a = pooled_event();

@@ -388,3 +388,48 @@ def test_cg_iterative_refinement_bf16_well_conditioned():
     """BF16 near blocks as the inner operator: refinement contracts when the condition number
     times the BF16 unit roundoff is below one (nugget 10 here)."""
     _solve_case("matern12", 0.1, 10.0, "bf16", 1e-8)
+
+
+def test_autotune_and_graph_replays():
+    """Uneven mixture, two parameters, T = 4 slots, R = 3: the autotuned configuration is
+    valid and matches the oracle; a recorded instantiate + MVM graph replayed with new
+    theta, with eager work and synchronisations between replays, equals the eager result
+    of the same instance bit for bit on every replay, and matches the oracle."""
+    torch = _torch()
+    from paper_2511_03109_amd import api, _lib
+    n, T, R = 3000, 4, 3
+    X = inputs.points_for(3, n)
+    lt, lm, om = _setup(X, "aniso_gaussian", [0.05, 0.05], [0.5, 0.5], 5, 7, 1e-8, 4, (2, 1))
+    rng = np.random.default_rng(11)
+    th0 = rng.uniform(0.05, 0.5, (T, 2))
+    inst = api.Instance(lm, th0)
+    x = torch.tensor(np.ascontiguousarray(inputs.normal_vectors(n, T * R, 3).T.reshape(T, R, n)), device="cuda")
+    y = torch.empty_like(x)
+    cfg = inst.autotune(x, y)
+    print(f"[parity] autotune: {cfg}", flush=True)
+    assert cfg["chunks"] in (1, 2, 4, 8, 16) and cfg["prefetch"] in (1, 2) and cfg["overlap"] in (0, 1)
+    assert cfg["ms"] > 0
+    s = torch.cuda.Stream()
+    g = inst.record(x, y, stream=s)
+    ref = torch.empty_like(x)
+    for rep in range(3):
+        th = rng.uniform(0.05, 0.5, (T, 2))
+        g.launch(th)
+        s.synchronize()
+        got = y.clone()
+        inst.reinstantiate(th)
+        inst.matvec(x, ref)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), f"replay {rep}"
+        if rep == 1:
+            xs = x.cpu().numpy()
+            for t in range(T):
+                _close(got[t].cpu().numpy().T, om.matvec(om.instantiate(th[t]), xs[t].T), what=f"graph slot {t}")
+    # while the graph lives, scratch cannot grow
+    xb = torch.zeros(T, 40, n, dtype=torch.float64, device="cuda")
+    with pytest.raises(_lib.PHError) as e:
+        inst.matvec(xb)
+    assert e.value.code == _lib.PH_ESTATE
+    del g
+    inst.matvec(xb)
+    torch.cuda.synchronize()
