@@ -116,6 +116,173 @@ def cpu_baseline(w, X, l_max, thetas, x_host, sample_leaves=160):
     }
 
 
+# ---------------------------------------------------------------- secondary measurements
+def _model(wid, n=None):
+    from paper_2511_03109_amd import api, inputs
+    w = inputs.WORKLOADS[wid]
+    X = inputs.points_for(wid) if n is None else inputs.points_for(wid, n)
+    t0 = time.time()
+    tree = api.Tree(X, leaf_size=w["leaf"], l_max=-1, eta2=tuple(w["eta2"]))
+    model = api.Model(tree, w["kernel"], w["theta_lo"], w["theta_hi"], p_s=w["p_s"], p_theta=w["p_theta"],
+                      tol=w["tol"])
+    log(f"[bench] {w['name']}: offline stage {time.time() - t0:.1f} s; tree {tree.info}; model {model.info}")
+    return w, X, tree, model
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3
+
+
+def mode_precision(args):
+    """The benchmark step with FP64, FP32 and BF16 instances; error of each against the FP64
+    instance (which matches the oracle to 1e-12) on the full output."""
+    import torch
+    from paper_2511_03109_amd import api, inputs
+    w, X, tree, model = _model(2)
+    n, T, R = w["n"], w["T"], w["R"]
+    thetas = inputs.theta_samples(T, w["theta_lo"], w["theta_hi"], 2)
+    xh = np.ascontiguousarray(inputs.normal_vectors(n, T * R, 2).T.reshape(T, R, n))
+    res, y64 = {}, None
+    for dt in ("f64", "f32", "bf16"):
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        x = torch.tensor(xh, device="cuda", dtype=tdt)
+        y = torch.empty_like(x)
+        inst = api.Instance(model, thetas, dtype=dt)
+        ms_inst = _timed(lambda: inst.reinstantiate(thetas), args.steps, args.warmup)
+        ms_mvm = _timed(lambda: inst.matvec(x, y), args.steps, args.warmup)
+        ms_step = _timed(lambda: (inst.reinstantiate(thetas), inst.matvec(x, y)), args.steps, args.warmup)
+        yd = y.double()
+        if y64 is None:
+            y64 = yd.clone()
+        err = float(torch.linalg.vector_norm(yd - y64) / torch.linalg.vector_norm(y64))
+        res[dt] = {"ms_per_theta": ms_step / T, "ms_instantiate_per_theta": ms_inst / T,
+                   "ms_matvec_per_theta": ms_mvm / T, "rel_error_vs_fp64": err}
+        del inst
+        torch.cuda.empty_cache()
+    for dt in ("f32", "bf16"):
+        res[dt]["speedup_vs_fp64"] = res["f64"]["ms_per_theta"] / res[dt]["ms_per_theta"]
+    print(json.dumps({"metric": "ms per θ-instantiate + H-MVM by precision", "unit": "ms per theta",
+                      "higher_is_better": False, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "config": {"workload": w["name"], "T": T, "R": R}, "data": "synthetic", "results": res}))
+
+
+def mode_cg(args):
+    """(K~(l) + 1e-2 I) a = y at n = 262144 (Matern-1/2, l = 0.1) to relative residual 1e-6
+    in FP64: plain FP64 CG against FP64 refinement around FP32 and BF16 inner solves."""
+    import torch
+    from paper_2511_03109_amd import api, inputs
+    w, X, tree, model = _model(5)
+    n, nug, th = w["n"], w["nugget"], w["theta"][0]
+    y = torch.tensor(inputs.normal_vectors(n, 1, 5, inputs.STREAM_Y)[:, 0], device="cuda")
+    res = {}
+    for lo_dt in (None, "f32", "bf16"):
+        t0 = time.perf_counter()
+        hi = api.Instance(model, [th])
+        lo = api.Instance(model, [th], dtype=lo_dt) if lo_dt else None
+        torch.cuda.synchronize()
+        t_inst = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        # inner tolerance: FP32 solves the correction almost to the target (one or two FP64
+        # refinement steps); BF16 is asked for two digits per step
+        a, st = api.cg_solve(hi, y, nugget=nug, tol=1e-6, lo=lo, max_iter=20000 if lo is None else 60,
+                             inner_max=20000, inner_tol=1e-2 if lo_dt == "bf16" else 5e-7)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t0
+        mvm = _timed(lambda: (lo or hi).matvec(y if lo is None else y.float()), 5, 2)
+        res[lo_dt or "f64"] = {"solve_s": t_solve, "instantiate_s": t_inst, "stats": st,
+                               "ms_per_inner_matvec": mvm}
+        del hi, lo, a
+        torch.cuda.empty_cache()
+    for k in ("f32", "bf16"):
+        if res[k]["stats"]["converged"]:
+            res[k]["speedup_vs_fp64_cg"] = res["f64"]["solve_s"] / res[k]["solve_s"]
+    print(json.dumps({"metric": "solve time to relative residual 1e-6, FP64 CG vs FP64-refined FP32/BF16",
+                      "unit": "s", "higher_is_better": False, "n_gpus": 1,
+                      "config": {"workload": w["name"], "n": n, "theta": th, "nugget": nug}, "data": "synthetic",
+                      "results": res}))
+
+
+def mode_grad(args):
+    """Forward y = K~(l) x and backward of L = u . y (dL/dl, dL/dx) through the autograd
+    Function at n = 131072; the gradient against a central difference with h = 1e-5."""
+    import torch
+    from paper_2511_03109_amd import api, inputs
+    w, X, tree, model = _model(4)
+    n, th = w["n"], w["theta"][0]
+    u = torch.tensor(inputs.normal_vectors(n, 1, 4, inputs.STREAM_U)[:, 0], device="cuda")
+    xv = torch.tensor(inputs.normal_vectors(n, 1, 4)[:, 0], device="cuda")
+
+    def fwd_bwd():
+        theta = torch.tensor([th], dtype=torch.float64, requires_grad=True)
+        x = xv.clone().requires_grad_(True)
+        L = (api.k_theta_matvec(model, theta, x) * u).sum()
+        L.backward()
+        return theta.grad, x.grad, L
+
+    ms_fb = _timed(fwd_bwd, args.steps, args.warmup)
+
+    def fwd():
+        with torch.no_grad():
+            return (api.k_theta_matvec(model, torch.tensor([th], dtype=torch.float64), xv) * u).sum()
+
+    ms_f = _timed(fwd, args.steps, args.warmup)
+    g, gx, L = fwd_bwd()
+    h = 1e-5
+    Lp = float((api.Instance(model, [th + h]).matvec(xv) * u).sum())
+    Lm = float((api.Instance(model, [th - h]).matvec(xv) * u).sum())
+    fd = (Lp - Lm) / (2 * h)
+    print(json.dumps({"metric": "ms per forward + backward of y = K(l) x", "value": ms_fb, "unit": "ms",
+                      "higher_is_better": False, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "config": {"workload": w["name"], "n": n, "theta": th}, "data": "synthetic",
+                      "ms_forward": ms_f, "dL_dl": float(g[0]), "central_difference": fd,
+                      "rel_diff_vs_fd": abs(float(g[0]) - fd) / abs(fd)}))
+
+
+def mode_sweep(args):
+    """64 (l1, l2) of the anisotropic Gaussian on the 8-component mixture, 32 RHS each: one
+    instance of T = 64 slots, autotuned, instantiate + MVM recorded as one graph."""
+    import torch
+    from paper_2511_03109_amd import api, inputs
+    w, X, tree, model = _model(3)
+    n, T, R = w["n"], w["T"], w["R"]
+    thetas = inputs.theta_samples(T, w["theta_lo"], w["theta_hi"], 3)
+    x = torch.tensor(np.ascontiguousarray(inputs.normal_vectors(n, T * R, 3).T.reshape(T, R, n)), device="cuda")
+    y = torch.empty_like(x)
+    inst = api.Instance(model, thetas)
+    ms_eager_default = _timed(lambda: (inst.reinstantiate(thetas), inst.matvec(x, y)), args.steps, args.warmup)
+    cfg = inst.autotune(x, y)
+    ms_eager = _timed(lambda: (inst.reinstantiate(thetas), inst.matvec(x, y)), args.steps, args.warmup)
+    s = torch.cuda.Stream()
+    g = inst.record(x, y, stream=s)
+    rng = np.random.default_rng(3)
+    batches = [rng.uniform(w["theta_lo"], w["theta_hi"], (T, 2)) for _ in range(4)]
+    k = [0]
+
+    def replay():
+        g.launch(batches[k[0] % 4])
+        k[0] += 1
+
+    with torch.cuda.stream(s):
+        ms_graph = _timed(replay, args.steps, args.warmup)
+    print(json.dumps({"metric": "ms per θ-instantiate + H-MVM in a 64-θ sweep (recorded graph)",
+                      "value": ms_graph / T, "unit": "ms per theta (32 RHS)", "higher_is_better": False,
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "config": {"workload": w["name"], "n": n, "T": T, "R": R}, "data": "synthetic",
+                      "autotuned": cfg, "ms_per_theta_eager_default": ms_eager_default / T,
+                      "ms_per_theta_eager_tuned": ms_eager / T, "model": model.info}))
+
+
+MODES = {"precision": mode_precision, "cg": mode_cg, "grad": mode_grad, "sweep": mode_sweep}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +290,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-leaves", type=int, default=160)
+    ap.add_argument("--mode", default="step", choices=["step", "precision", "cg", "grad", "sweep"],
+                    help="step (default): the benchmark step; precision: FP64 / FP32 / BF16 instances of "
+                         "the same step; cg: (K + 1e-2 I) a = y at n = 262144 by FP64 CG and by FP64 "
+                         "refinement around FP32 / BF16; grad: forward + backward of y = K(l) x at "
+                         "n = 131072; sweep: 64 theta x 32 RHS on the mixture, one recorded graph")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (to scale "
                          "profiler byte counters) and exit")
@@ -141,6 +313,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(multi-GPU sharding is described in the design notes, not built)"}))
         sys.exit(2)
+    if args.mode != "step":
+        MODES[args.mode](args)
+        return
 
     import torch
 
