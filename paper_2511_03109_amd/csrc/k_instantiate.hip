@@ -45,92 +45,65 @@ __global__ void k_theta_vectors(const double* __restrict__ theta, ThetaBox box, 
   }
 }
 
-// Far field, one workgroup per (stored class, slot).
-//   w_k = Theta_k^T v_k;  H = core x_theta w  (r_L x r_R, global scratch);
-//   St = (H R^T)^T, i.e. St[j + Pp a] = sum_b R[j, b] H[a, b]     (MFMA, M = j, N = a, K = b);
-//   C[i + Pp j] = sum_a L[i, a] St[j + Pp a]                     (MFMA, M = i, N = j, K = a);
-// the mirrored class receives C^T.  All Pp x Pp entries are written (zero padding), in
-// fragment order (frag_index).
+// Far field, one workgroup per (16 x 16 tile of the Pp x Pp coupling, stored class), all
+// slots:  w_k = Theta_k^T v_k(theta_t);  C_t = sum_q w_1[k_1] w_2[k_2] Chat_q  (Sec. 4.2,
+// C = L H(theta) R^T with H linear in the weights, the panels L G_q R^T formed offline).
+// C is in fragment order, where a 16 x 16 tile is 256 contiguous entries, so thread p
+// reads and writes entry p of the tile; the mirrored class receives C^T (entry (k, m) of
+// the transposed tile).
 template <typename S>
-__global__ void __launch_bounds__(NT) k_far_instantiate(
-    const ClassDev* __restrict__ cls, const double* __restrict__ L, const double* __restrict__ R,
-    const double* __restrict__ core, const double* __restrict__ th, const double* __restrict__ v,
-    double* __restrict__ scratch, int64_t scratch_per_slot, S* __restrict__ C, int64_t C_per_slot,
-    int P, int Pp, int p, int dth) {
-  typedef Mfma<double> MF;
-  __shared__ double w1[16], w2[16];
-  const ClassDev c = cls[blockIdx.x];
-  const int t = blockIdx.y;
-  const int lane = threadIdx.x % WAVE;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-  const double* vt = v + (size_t)t * dth * p;
-  for (int a = threadIdx.x; a < c.r1; a += blockDim.x) {
-    double s = 0;
-    for (int q = 0; q < p; ++q) s += th[c.th1_off + q + (size_t)p * a] * vt[q];
-    w1[a] = s;
-  }
-  if (dth == 2) {
-    for (int a = threadIdx.x; a < c.r2; a += blockDim.x) {
+__global__ void __launch_bounds__(NT) k_far_instantiate(const ClassDev* __restrict__ cls,
+                                                        const double* __restrict__ chat,
+                                                        const double* __restrict__ th, const double* __restrict__ v,
+                                                        S* __restrict__ C, int64_t C_per_slot, int Pp, int T, int p,
+                                                        int dth) {
+  __shared__ double w1[TC][16], w2[TC][16];
+  const ClassDev c = cls[blockIdx.y];
+  const int nMt = Pp / 16;
+  const int mt = blockIdx.x % nMt, kc = blockIdx.x / nMt;
+  const int pos = threadIdx.x;                                   // entry of the tile
+  const int kl = pos >> 4, ml = (pos & 3) * 4 + ((pos & 15) >> 2);
+  const int m = mt * 16 + ml, k = kc * 16 + kl;
+  const int64_t at = (int64_t)kc * Pp * 16 + mt * 256 + pos;    // = frag_index(m, k)
+  const int64_t mirror_at = frag_index(k, m, Pp);
+  const int rq = c.r1 * c.r2;
+  const double* cp = chat + c.chat_off + at;
+  for (int t0 = 0; t0 < T; t0 += TC) {
+    const int tc = min(TC, T - t0);
+    __syncthreads();
+    for (int o = threadIdx.x; o < tc * c.r1; o += NT) {
+      const int tt = o / c.r1, a = o % c.r1;
+      const double* vt = v + (size_t)(t0 + tt) * dth * p;
       double s = 0;
-      for (int q = 0; q < p; ++q) s += th[c.th2_off + q + (size_t)p * a] * vt[p + q];
-      w2[a] = s;
+      for (int q = 0; q < p; ++q) s += th[c.th1_off + q + (size_t)p * a] * vt[q];
+      w1[tt][a] = s;
     }
-  } else if (threadIdx.x == 0) {
-    w2[0] = 1.0;
-  }
-  __syncthreads();
-  const int rL = c.rL, rR = c.rR;
-  const int rLp = (rL + 15) / 16 * 16;
-  double* H = scratch + (size_t)t * scratch_per_slot + c.S_off;
-  double* St = H + (size_t)rL * rR;
-  for (int o = threadIdx.x; o < rL * rR; o += blockDim.x) {
-    const int a = o % rL, b = o / rL;
-    double s = 0;
-    for (int k2 = 0; k2 < c.r2; ++k2)
-      for (int k1 = 0; k1 < c.r1; ++k1)
-        s += core[c.core_off + a + (size_t)rL * (k1 + (size_t)c.r1 * (k2 + (size_t)c.r2 * b))] * w1[k1] *
-             w2[k2];
-    H[o] = s;
-  }
-  __threadfence_block();
-  __syncthreads();
-  const int m16 = lane & 15, kq = lane >> 4;
-  // St (Pp x rLp): tiles (jt, at)
-  {
-    const int nj = Pp / 16, na = rLp / 16;
-    for (int tile = wave; tile < nj * na; tile += NT / WAVE) {
-      const int jt = tile % nj, at = tile / nj;
-      MF::acc_t acc = {0, 0, 0, 0};
-      const int j = jt * 16 + m16, a = at * 16 + m16;
-      for (int b0 = 0; b0 < rR; b0 += 4) {
-        const int b = b0 + kq;
-        const double av = (j < P && b < rR) ? R[c.R_off + j + (size_t)P * b] : 0.0;
-        const double bv = (a < rL && b < rR) ? H[a + (size_t)rL * b] : 0.0;
-        acc = MF::mac(av, bv, acc);
+    for (int o = threadIdx.x; o < tc * c.r2; o += NT) {
+      const int tt = o / c.r2, a = o % c.r2;
+      double s = 1.0;
+      if (dth == 2) {
+        const double* vt = v + (size_t)(t0 + tt) * dth * p;
+        s = 0;
+        for (int q = 0; q < p; ++q) s += th[c.th2_off + q + (size_t)p * a] * vt[p + q];
       }
-      for (int i = 0; i < 4; ++i) St[(jt * 16 + MF::row(lane, i)) + (size_t)Pp * (at * 16 + m16)] = acc[i];
+      w2[tt][a] = s;
     }
-  }
-  __threadfence_block();
-  __syncthreads();
-  S* Ct = C + (size_t)t * C_per_slot;
-  {
-    const int nt = Pp / 16;
-    for (int tile = wave; tile < nt * nt; tile += NT / WAVE) {
-      const int it = tile % nt, jt = tile / nt;
-      MF::acc_t acc = {0, 0, 0, 0};
-      const int i = it * 16 + m16, j = jt * 16 + m16;
-      for (int a0 = 0; a0 < rL; a0 += 4) {
-        const int a = a0 + kq;
-        const double av = (i < P && a < rL) ? L[c.L_off + i + (size_t)P * a] : 0.0;
-        const double bv = (a < rL) ? St[j + (size_t)Pp * a] : 0.0;
-        acc = MF::mac(av, bv, acc);
-      }
-      for (int q = 0; q < 4; ++q) {
-        const int row = it * 16 + MF::row(lane, q);
-        Ct[c.C_off + frag_index(row, j, Pp)] = (S)acc[q];
-        if (c.Cm_off >= 0) Ct[c.Cm_off + frag_index(j, row, Pp)] = (S)acc[q];
-      }
+    __syncthreads();
+    double acc[TC];
+#pragma unroll
+    for (int tt = 0; tt < TC; ++tt) acc[tt] = 0.0;
+    for (int q = 0; q < rq; ++q) {
+      const double pv = cp[(int64_t)q * Pp * Pp];
+      const int k1 = q % c.r1, k2 = q / c.r1;
+#pragma unroll
+      for (int tt = 0; tt < TC; ++tt) acc[tt] += pv * (w1[tt][k1] * w2[tt][k2]);
+    }
+#pragma unroll
+    for (int tt = 0; tt < TC; ++tt) {
+      if (tt >= tc) break;
+      S* Ct = C + (size_t)(t0 + tt) * C_per_slot;
+      Ct[c.C_off + at] = (S)acc[tt];
+      if (c.Cm_off >= 0) Ct[c.Cm_off + mirror_at] = (S)acc[tt];
     }
   }
 }
@@ -250,10 +223,10 @@ void instantiate_impl(InstData& in, const double* theta, hipStream_t st) {
   launch(PH_STAGE_THETA, k_theta_vectors, dim3((unsigned)grid_for(nv)), dim3(NT), st, (const double*)in.theta_d.p,
          box, in.v.p, in.T, m.d_theta, m.p_theta, in.grad_dim);
   const int64_t Cps = m.n_classes * m.Pp * m.Pp;
-  launch(PH_STAGE_FAR_INST, k_far_instantiate<S>, dim3((unsigned)m.n_stored_cls, in.T), dim3(NT), st,
-         (const ClassDev*)m.cstore.p, (const double*)m.ff_L.p, (const double*)m.ff_R.p,
-         (const double*)m.ff_core.p, (const double*)m.ff_theta.p, (const double*)in.v.p, in.ffs.p,
-         m.ff_scratch, (S*)in.C.p, Cps, m.P, m.Pp, m.p_theta, m.d_theta);
+  const int nMt = m.Pp / 16;
+  launch(PH_STAGE_FAR_INST, k_far_instantiate<S>, dim3((unsigned)(nMt * nMt), (unsigned)m.n_stored_cls), dim3(NT), st,
+         (const ClassDev*)m.cstore.p, (const double*)m.ff_chat.p, (const double*)m.ff_theta.p,
+         (const double*)in.v.p, (S*)in.C.p, Cps, m.Pp, in.T, m.p_theta, m.d_theta);
   launch(PH_STAGE_NEAR_INST, k_near_instantiate<DT>, dim3((unsigned)m.n_tiles), dim3(NT), st,
          (const NearDev*)m.nstore.p, (const int32_t*)m.tiles.p, (const double*)m.nf_P.p,
          (const double*)m.nf_core.p, (const double*)m.nf_theta.p, (const double*)in.v.p, (DT*)in.D.p,

@@ -468,6 +468,40 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
     cs.core_off = (int64_t)m->ff_core.size();
     m->ff_core.insert(m->ff_core.end(), tk.core.begin(), tk.core.end());
   }
+  // far-field panels Chat_q = L G_q R^T (the coupling is linear in the parametric weights,
+  // so C(theta) = L H(theta) R^T = sum_q w_q(theta) Chat_q; the online stage then streams
+  // these panels once for all parameter values)
+  {
+    int64_t tot = 0;
+    for (int64_t ci = 0; ci < nfc; ++ci) {
+      m->cstore[ci].chat_off = tot;
+      tot += (int64_t)m->cstore[ci].r1 * m->cstore[ci].r2 * P * P;
+    }
+    m->ff_chat.assign((size_t)tot, 0.0);
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
+    for (int64_t ci = 0; ci < nfc; ++ci) {
+      const ClassStored& cs = m->cstore[ci];
+      const Tucker& tk = ftuck[ci];
+      const double* L = tk.factors.front().data();   // P x rL
+      const double* Rf = tk.factors.back().data();   // P x rR
+      std::vector<double> T1((size_t)P * cs.rR);
+      for (int k2 = 0; k2 < cs.r2; ++k2)
+        for (int k1 = 0; k1 < cs.r1; ++k1) {
+          std::fill(T1.begin(), T1.end(), 0.0);
+          for (int b = 0; b < cs.rR; ++b)
+            for (int a = 0; a < cs.rL; ++a) {
+              const double g = tk.core[(size_t)a + (size_t)cs.rL * (k1 + (size_t)cs.r1 * (k2 + (size_t)cs.r2 * b))];
+              for (int i = 0; i < P; ++i) T1[(size_t)i + (size_t)P * b] += L[(size_t)i + (size_t)P * a] * g;
+            }
+          double* out = &m->ff_chat[(size_t)cs.chat_off + (size_t)(k1 + cs.r1 * k2) * P * P];
+          for (int b = 0; b < cs.rR; ++b)
+            for (int j = 0; j < P; ++j) {
+              const double r = Rf[(size_t)j + (size_t)P * b];
+              for (int i = 0; i < P; ++i) out[(size_t)i + (size_t)P * j] += T1[(size_t)i + (size_t)P * b] * r;
+            }
+        }
+    }
+  }
 
   // ---- near blocks (s <= t stored)
   const int64_t nn = t.n_near();

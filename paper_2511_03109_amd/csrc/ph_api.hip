@@ -81,22 +81,29 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   m->near_rank_mean = wsum > 0 ? rsum / wsum : 0;
   m->n_tiles = (int64_t)tiles.size() / 3;
 
-  // far classes
+  // far classes: panels Chat_q permuted into fragment order (zero padding to Pp)
   const int P = hm.P;
+  const int64_t Pp = m->Pp;
   std::vector<ClassDev> cd(hm.cstore.size());
-  int64_t soff = 0;
   double fr = 0;
+  int64_t chat_tot = 0;
+  for (const ClassStored& c : hm.cstore) chat_tot += (int64_t)c.r1 * c.r2 * Pp * Pp;
+  std::vector<double> chat((size_t)chat_tot, 0.0);
   m->class_ranks.assign(m->n_classes * (2 + hm.d_theta), 0);
+  int64_t coff = 0;
   for (size_t q = 0; q < hm.cstore.size(); ++q) {
     const ClassStored& c = hm.cstore[q];
     ClassDev& x = cd[q];
-    x.L_off = c.L_off; x.R_off = c.R_off; x.core_off = c.core_off;
     x.th1_off = c.th1_off; x.th2_off = c.th2_off;
-    const int64_t Pp = m->Pp;
     x.C_off = (int64_t)c.cls * Pp * Pp;
     x.Cm_off = c.mirror >= 0 ? (int64_t)c.mirror * Pp * Pp : -1;
-    x.S_off = soff;
-    soff += (int64_t)c.rL * c.rR + Pp * (int64_t)((c.rL + 15) / 16 * 16);
+    x.chat_off = coff;
+    for (int64_t r = 0; r < (int64_t)c.r1 * c.r2; ++r)
+      for (int j = 0; j < P; ++j)
+        for (int i = 0; i < P; ++i)
+          chat[(size_t)(coff + r * Pp * Pp + frag_index(i, j, (int)Pp))] =
+              hm.ff_chat[(size_t)(c.chat_off + r * P * P + i + (int64_t)P * j)];
+    coff += (int64_t)c.r1 * c.r2 * Pp * Pp;
     x.rL = c.rL; x.r1 = c.r1; x.r2 = c.r2; x.rR = c.rR;
     fr += 0.5 * (c.rL + c.rR);
     m->far_rank_max = std::max({m->far_rank_max, c.rL, c.rR});
@@ -108,7 +115,6 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
     }
   }
   m->far_rank_mean = cd.empty() ? 0 : fr / cd.size();
-  m->ff_scratch = soff;
 
   // CSR of near blocks by target leaf (canonical list is sorted by sigma)
   const int32_t leaf0 = t.leaves.empty() ? 0 : t.leaves.front();
@@ -217,9 +223,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   m->near_D.upload(nD.data(), nD.size(), st);
   m->near_nt.upload(nnt.data(), nnt.size(), st);
   m->cstore.upload(cd.data(), cd.size(), st);
-  m->ff_L.upload(hm.ff_L.data(), hm.ff_L.size(), st);
-  m->ff_R.upload(hm.ff_R.data(), hm.ff_R.size(), st);
-  m->ff_core.upload(hm.ff_core.data(), hm.ff_core.size(), st);
+  m->ff_chat.upload(chat.data(), chat.size(), st);
   m->ff_theta.upload(hm.ff_theta.data(), hm.ff_theta.size(), st);
   m->grp_targets.upload(gt.data(), gt.size(), st);
   m->grp_entry.upload(gptr.data(), gptr.size(), st);
@@ -233,8 +237,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
                               m->nstore.bytes() + m->nf_P.bytes() + m->nf_core.bytes() +
                               m->nf_theta.bytes() + m->tiles.bytes() + m->near_rowptr.bytes() +
                               m->near_tb.bytes() + m->near_D.bytes() + m->near_nt.bytes() +
-                              m->cstore.bytes() + m->ff_L.bytes() + m->ff_R.bytes() +
-                              m->ff_core.bytes() + m->ff_theta.bytes() + m->grp_targets.bytes() +
+                              m->cstore.bytes() + m->ff_chat.bytes() + m->ff_theta.bytes() + m->grp_targets.bytes() +
                               m->grp_entry.bytes() + m->ent_cls.bytes() + m->ent_tau.bytes() +
                               m->ent_wpre.bytes() + m->grp_w.bytes());
   return m;
@@ -327,7 +330,6 @@ int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype
       in->theta_d.alloc((size_t)T * md.d_theta);
       PH_HIP(hipHostMalloc((void**)&in->theta_pin, (size_t)T * md.d_theta * sizeof(double), hipHostMallocDefault));
       PH_HIP(hipEventCreateWithFlags(&in->ev_theta, hipEventDisableTiming));
-      in->ffs.alloc((size_t)T * std::max<int64_t>(md.ff_scratch, 1));
       PH_HIP(hipStreamCreateWithFlags(&in->aux, hipStreamNonBlocking));
       PH_HIP(hipEventCreateWithFlags(&in->ev_fork, hipEventDisableTiming));
       PH_HIP(hipEventCreateWithFlags(&in->ev_join, hipEventDisableTiming));

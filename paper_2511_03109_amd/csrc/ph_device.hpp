@@ -90,7 +90,7 @@ struct NearDev {
 
 // per stored far class (offset >= 0 lexicographically)
 struct ClassDev {
-  int64_t L_off, R_off, core_off, th1_off, th2_off, C_off, Cm_off, S_off;
+  int64_t chat_off, th1_off, th2_off, C_off, Cm_off;   // chat_off: panels in fragment order
   int32_t rL, r1, r2, rR;
 };
 
@@ -107,7 +107,7 @@ struct DeviceModel {
   int d = 0, p_s = 0, P = 0, Pp = 0, p_theta = 0, d_theta = 0, l_max = 0, min_far = -1;
   double th_lo[2] = {0, 0}, th_hi[2] = {0, 0};
   int64_t n = 0, n_nodes = 0, n_leaves = 0, n_near = 0, n_classes = 0, N_nf = 0, N_nf_pad = 0;
-  int64_t n_stored_near = 0, n_stored_cls = 0, n_tiles = 0, ff_scratch = 0;
+  int64_t n_stored_near = 0, n_stored_cls = 0, n_tiles = 0;
   int64_t n_groups = 0, n_entries = 0, max_group_entries = 0;
   int64_t near_factor_entries = 0, kernel_evals = 0;
   double near_rank_mean = 0, far_rank_mean = 0;
@@ -128,7 +128,7 @@ struct DeviceModel {
   DevArr<int64_t> near_tb, near_D;        // per canonical near block: tau begin, D offset
   DevArr<int32_t> near_nt;
   DevArr<ClassDev> cstore;
-  DevArr<double> ff_L, ff_R, ff_core, ff_theta;
+  DevArr<double> ff_chat, ff_theta;       // far panels (r1 r2 of Pp x Pp per class), theta factors
   // coupling work list: target boxes of NTG nodes of one level (see coupling_groups)
   DevArr<int32_t> grp_targets;            // n_groups x NTG node ids (-1 = absent)
   DevArr<int32_t> grp_entry;              // n_groups + 1
@@ -148,7 +148,7 @@ struct InstData {
   size_t esize = 8;                   // element size of C, x_hat, y_hat, I/O (compute type)
   size_t d_esize = 8;                 // element size of the near blocks D (storage type)
   DevArr<char> D, C;
-  DevArr<double> v, ffs;
+  DevArr<double> v;
   int64_t Rcap = 0;
   int Gcap = 0;
   DevArr<char> xt, yt, xh, yh, part;

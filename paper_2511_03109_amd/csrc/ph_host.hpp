@@ -60,6 +60,8 @@ std::shared_ptr<TreeData> build_tree(const double* pts, int64_t n, const ph_tree
 //  Theta factors (near and far) column-major p_theta x r: th[off + q + p_theta*a]
 //  far L, R  column-major P x r
 //  far core  core[off + a + r_L*(k_1 + r_1*(k_2 + r_2*b))]
+//  far panels  Chat[chat_off + q*P*P + i + P*j] = (L G_q R^T)[i, j], q = k_1 + r_1 k_2,
+//              G_q[a, b] = core[a, k_1, k_2, b]; C(theta) = sum_q w_1[k_1] w_2[k_2] Chat_q
 struct NearStored {
   int32_t s, t;             // node ids, s <= t
   int64_t s_begin, t_begin; // tree-order offsets
@@ -73,7 +75,7 @@ struct NearStored {
 struct ClassStored {
   int32_t cls, mirror;      // class index and its mirror (-1 if none)
   int32_t rL, r1, r2, rR;
-  int64_t L_off, R_off, core_off, th1_off, th2_off;
+  int64_t L_off, R_off, core_off, th1_off, th2_off, chat_off;
 };
 
 struct HostModel {
@@ -86,7 +88,7 @@ struct HostModel {
   std::vector<double> nf_P, nf_core, nf_theta;
   std::vector<int32_t> near_src, near_tr;   // per canonical near block
   std::vector<ClassStored> cstore;
-  std::vector<double> ff_L, ff_R, ff_core, ff_theta;
+  std::vector<double> ff_L, ff_R, ff_core, ff_theta, ff_chat;
   std::vector<int32_t> class_src, class_tr; // per class: stored index, transposed?
   int64_t kernel_evals = 0;
   int64_t near_factor_entries = 0;
