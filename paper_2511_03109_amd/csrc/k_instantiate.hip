@@ -108,23 +108,37 @@ __global__ void __launch_bounds__(NT) k_far_instantiate(const ClassDev* __restri
   }
 }
 
-// Near field, one workgroup per TILE x TILE tile of a stored block, all slots:
-//   c_t = core x_theta (Theta_k^T v_k(theta_t));  D_t[i + j n_s] = sum_k P[k][i + j n_s] c_t[k]
-// Each factor entry is read from HBM once for up to TC slots; D_t is written to the
-// (s, t) block and, through an LDS transpose, to the (t, s) block.
+// Near field, one workgroup per TILE x TILE_J tile of a stored block (s <= t), all slots:
+//   c_t = core x_theta (Theta_k^T v_k(theta_t));  D_t(i, j) = sum_k P[k][i + j n_s] c_t[k]
+// Each factor entry is read from HBM once for up to TC slots; the factor entries of KB
+// ranks are loaded before any is used (KB * NQ loads in flight per thread).  D_t goes to
+// the stored block in 16-row panels (panel_index), padding rows as zeros; the (t, s)
+// block is its transpose and is not written (the MVM reads the stored block transposed).
 template <typename DT>
 __global__ void __launch_bounds__(NT) k_near_instantiate(
     const NearDev* __restrict__ blocks, const int32_t* __restrict__ tiles,
     const double* __restrict__ Pf, const double* __restrict__ core, const double* __restrict__ th,
     const double* __restrict__ v, DT* __restrict__ D, int64_t D_per_slot, int T, int p, int dth) {
+  constexpr int RS = NT / TILE;                // 8 column steps of the thread grid
+  constexpr int NQ = TILE_J / RS;              // 2 entries per thread
+  constexpr int KB = 8;
   __shared__ double w1[TC][16], w2[TC][16], cc[TC][256];
-  __shared__ double tile[TILE][TILE + 1];
   const int32_t bi = tiles[3 * blockIdx.x], i0 = tiles[3 * blockIdx.x + 1], j0 = tiles[3 * blockIdx.x + 2];
   const NearDev b = blocks[bi];
   const int64_t Nep = (int64_t)b.ldp * b.nt;                     // padded factor column length
-  const int ti = threadIdx.x % TILE, tj0 = threadIdx.x / TILE;   // 8 rows of 32
+  const int ti = threadIdx.x % TILE, tj0 = threadIdx.x / TILE;
   const int i = i0 + ti;
-  constexpr int NQ = TILE / (NT / TILE);                          // 4 entries per thread
+  const int nsp = (b.ns + 15) / 16 * 16;
+  bool ok[NQ], wr[NQ];
+  int64_t e[NQ], ed[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int j = j0 + tj0 + q * RS;
+    ok[q] = i < b.ns && j < b.nt;
+    wr[q] = i < nsp && j < b.nt;                                  // rows ns..nsp-1 get 0
+    e[q] = ok[q] ? i + (int64_t)j * b.ldp : 0;
+    ed[q] = wr[q] ? panel_index(i, j, b.nt) : 0;
+  }
   for (int t0 = 0; t0 < T; t0 += TC) {
     const int tc = min(TC, T - t0);
     __syncthreads();
@@ -146,54 +160,48 @@ __global__ void __launch_bounds__(NT) k_near_instantiate(
       w2[tt][a] = s;
     }
     __syncthreads();
-    for (int o = threadIdx.x; o < tc * b.r_e; o += NT) {
+    for (int o = threadIdx.x; o < TC * b.r_e; o += NT) {
       const int tt = o / b.r_e, k = o % b.r_e;
       double s = 0;
-      for (int k2 = 0; k2 < b.r2; ++k2)
-        for (int k1 = 0; k1 < b.r1; ++k1)
-          s += core[b.core_off + k + (size_t)b.r_e * (k1 + (size_t)b.r1 * k2)] * w1[tt][k1] * w2[tt][k2];
+      if (tt < tc)
+        for (int k2 = 0; k2 < b.r2; ++k2)
+          for (int k1 = 0; k1 < b.r1; ++k1)
+            s += core[b.core_off + k + (size_t)b.r_e * (k1 + (size_t)b.r1 * k2)] * w1[tt][k1] * w2[tt][k2];
       cc[tt][k] = s;
     }
     __syncthreads();
     double acc[TC][NQ];
-    for (int tt = 0; tt < TC; ++tt)
-      for (int q = 0; q < NQ; ++q) acc[tt][q] = 0.0;
-    bool ok[NQ];
-    int64_t e[NQ], ed[NQ];
-    for (int q = 0; q < NQ; ++q) {
-      const int j = j0 + tj0 + q * (NT / TILE);
-      ok[q] = i < b.ns && j < b.nt;
-      e[q] = ok[q] ? i + (int64_t)j * b.ldp : 0;
-      ed[q] = ok[q] ? i + (int64_t)j * b.lds : 0;
-    }
-    const double* pb = Pf + b.P_off;
-    int k = 0;
-    for (; k < b.r_e; ++k) {
-      double pv[NQ];
-      for (int q = 0; q < NQ; ++q) pv[q] = ok[q] ? pb[(size_t)k * Nep + e[q]] : 0.0;
 #pragma unroll
-      for (int tt = 0; tt < TC; ++tt) {
-        const double cv = cc[tt][k];
-        for (int q = 0; q < NQ; ++q) acc[tt][q] += pv[q] * cv;
+    for (int tt = 0; tt < TC; ++tt)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc[tt][q] = 0.0;
+    const double* pb = Pf + b.P_off;
+    for (int k0 = 0; k0 < b.r_e; k0 += KB) {
+      double pv[KB][NQ];
+#pragma unroll
+      for (int kk = 0; kk < KB; ++kk) {
+        const bool kok = k0 + kk < b.r_e;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) pv[kk][q] = (kok && ok[q]) ? pb[(size_t)(k0 + kk) * Nep + e[q]] : 0.0;
+      }
+#pragma unroll
+      for (int kk = 0; kk < KB; ++kk) {
+        if (k0 + kk >= b.r_e) break;
+#pragma unroll
+        for (int tt = 0; tt < TC; ++tt) {
+          const double cv = cc[tt][k0 + kk];
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) acc[tt][q] += pv[kk][q] * cv;
+        }
       }
     }
 #pragma unroll
     for (int tt = 0; tt < TC; ++tt) {
       if (tt >= tc) break;
-      DT* Dt = D + (size_t)(t0 + tt) * D_per_slot;
+      DT* Dt = D + (size_t)(t0 + tt) * D_per_slot + b.D_st;
+#pragma unroll
       for (int q = 0; q < NQ; ++q)
-        if (ok[q]) Dt[b.D_st + ed[q]] = to_store<DT>(acc[tt][q]);
-      if (b.D_ts >= 0) {
-        __syncthreads();
-        for (int q = 0; q < NQ; ++q) tile[tj0 + q * (NT / TILE)][ti] = acc[tt][q];
-        __syncthreads();
-        // transposed block (t, s): element (j, i) at j + i n_t
-        const int jj = j0 + ti;
-        for (int q = 0; q < NQ; ++q) {
-          const int ii = i0 + tj0 + q * (NT / TILE);
-          if (ii < b.ns && jj < b.nt) Dt[b.D_ts + jj + (int64_t)ii * b.ldt] = to_store<DT>(tile[ti][tj0 + q * (NT / TILE)]);
-        }
-      }
+        if (wr[q]) Dt[ed[q]] = to_store<DT>(acc[tt][q]);
     }
   }
 }

@@ -325,9 +325,12 @@ __global__ void __launch_bounds__(NW * 64) k_coupling(
       for (int h = 0; h < BUT; ++h) reinterpret_cast<u4*>(Bs[buf][wave * TSW + q])[lane + 64 * h] = breg[rb][q][h];
   };
   // one stage: prefetch stage st + PD into ring slot RF, multiply from LDS buffer BUF,
-  // store stage st + 1 (ring slot RS) into the other LDS buffer
+  // store stage st + 1 (ring slot RS) into the other LDS buffer.  With PD = 2 the loads of
+  // stage st + 1 were issued a whole stage earlier, so it is stored first and its LDS
+  // writes overlap this stage's matrix-core work; with PD = 1 it is stored last.
   auto body = [&](int st, auto BUF, auto RF, auto RS) {
     constexpr int buf = decltype(BUF)::value;
+    if (PD == 2) stash(decltype(RS)::value, buf ^ 1);
     fetch(min(st + PD, nsteps - 1), decltype(RF)::value);
     const int e = ea + st / nk;
     bool use[NTW];
@@ -353,7 +356,7 @@ __global__ void __launch_bounds__(NW * 64) k_coupling(
           if (FULL || wr + WR * j < nMt) acc[s][j] = MF::mac(a[j], bv[s], acc[s][j]);
       }
     }
-    stash(decltype(RS)::value, buf ^ 1);
+    if (PD == 1) stash(decltype(RS)::value, buf ^ 1);
     __syncthreads();
   };
   typedef std::integral_constant<int, 0> I0;
@@ -405,16 +408,20 @@ __global__ void k_coupling_reduce(S* __restrict__ yh, const S* __restrict__ part
 // Near field on the matrix cores, one workgroup per (leaf s, RHS tile, slot):
 //   y_s = sum_{near t} D_st x_t        (writes y_s)
 // M = rows of the leaf (row tiles w, w + 4 per wave, in chunks of 128 rows), K = the
-// columns of each near block; each A fragment is 16 consecutive rows of one column of
-// D (one aligned 128-byte line).  The (block, 16-column group) sequence is software
-// pipelined: the next group's D and x values are loaded while the current one feeds
-// the MFMAs.
+// columns of each near block.  Only blocks with s <= t are stored (16-row panels,
+// panel_index); for t < s the kernel reads the stored (t, s) block transposed.  Either way
+// the 16 x 16 tile a wave needs for one group of 16 columns is one contiguous 2 KB chunk:
+// direct blocks are read with one 512-byte row of lanes per K-step, transposed ones with
+// 32 contiguous bytes per lane, the K index of the group relabelled (j = 4 kq + u instead
+// of 4 u + kq; the x operand follows the same relabelling).  The (block, column group)
+// sequence is software pipelined: the next group's D and x values are loaded while the
+// current one feeds the MFMAs.
 template <typename S, typename DT>
 __global__ void __launch_bounds__(NT) k_near_mvm(
     const S* __restrict__ xt, S* __restrict__ yt, const DT* __restrict__ D, const int64_t* __restrict__ nbegin,
     const int64_t* __restrict__ nend, const int64_t* __restrict__ rowptr, const int64_t* __restrict__ ntb,
-    const int32_t* __restrict__ nnt, const int64_t* __restrict__ nD, int32_t leaf0, int64_t n, int64_t R,
-    int64_t N_nf) {
+    const int32_t* __restrict__ nnt, const int32_t* __restrict__ ntr, const int64_t* __restrict__ nD,
+    int32_t leaf0, int64_t n, int64_t R, int64_t N_nf) {
   typedef Mfma<S> MF;
   constexpr int CH = 128;
   const int32_t li = blockIdx.x;
@@ -425,32 +432,46 @@ __global__ void __launch_bounds__(NT) k_near_mvm(
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int m16 = lane & 15, kq = lane >> 4;
   const int64_t b = nbegin[s], ns = nend[s] - b;
-  const int64_t ld = (ns + 15) / 16 * 16;   // leading dimension of this leaf's row blocks
   const bool colok = r0 + m16 < R;
   const S* xs = xt + slot * n * R;
   const DT* Ds = D + slot * N_nf;
   const int64_t bb0 = rowptr[li], bb1 = rowptr[li + 1];
   for (int64_t c0 = 0; c0 < ns; c0 += CH) {
     const int cn = (int)min<int64_t>(CH, ns - c0);
-    const int i0 = wave * 16 + m16, i1 = (wave + 4) * 16 + m16;   // rows within the chunk
+    const int64_t i0 = c0 + wave * 16 + m16, i1 = c0 + (wave + 4) * 16 + m16;   // rows of the leaf
     const bool t0ok = wave * 16 < cn, t1ok = (wave + 4) * 16 < cn;
-    const bool r0ok = i0 < cn, r1ok = i1 < cn;
+    const bool r0ok = i0 < c0 + cn, r1ok = i1 < c0 + cn;
     typename MF::acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
     // pipeline state: block bb, column group kb (16 columns = 4 MFMA K-steps)
     int64_t bb = bb0;
     int kb = 0;
     S a0n[4], a1n[4], bn[4];
     auto fetch = [&](int64_t fb, int fk) {
-      const DT* Db = Ds + nD[fb] + c0;
+      const DT* Db = Ds + nD[fb];
       const int64_t tb = ntb[fb];
       const int nt = nnt[fb];
+      if (ntr[fb] == 0) {
+        // stored (s, t): entry (i, j) at panel_index(i, j, nt)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int j = fk * 16 + u * 4 + kq;
-        const bool jok = j < nt;
-        bn[u] = (jok && colok) ? xs[(tb + j) * R + r0 + m16] : (S)0;
-        a0n[u] = (jok && r0ok) ? widen<S, DT>(Db[i0 + (int64_t)j * ld]) : (S)0;
-        a1n[u] = (jok && r1ok) ? widen<S, DT>(Db[i1 + (int64_t)j * ld]) : (S)0;
+        for (int u = 0; u < 4; ++u) {
+          const int j = fk * 16 + u * 4 + kq;
+          const bool jok = j < nt;
+          bn[u] = (jok && colok) ? xs[(tb + j) * R + r0 + m16] : (S)0;
+          a0n[u] = (jok && r0ok) ? widen<S, DT>(Db[panel_index(i0, j, nt)]) : (S)0;
+          a1n[u] = (jok && r1ok) ? widen<S, DT>(Db[panel_index(i1, j, nt)]) : (S)0;
+        }
+      } else {
+        // stored (t, s), n_t rows (zero-padded to 16) x n_s columns: entry (i, j) of D_st
+        // at panel_index(j, i, ns); this lane's four K-steps u are j = 16 fk + 4 kq + u
+        const int jq = fk * 16 + kq * 4;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          bn[u] = (jq + u < nt && colok) ? xs[(tb + jq + u) * R + r0 + m16] : (S)0;
+          a0n[u] = (S)0;
+          a1n[u] = (S)0;
+        }
+        if (r0ok) Load4<S, DT>::get(Db + panel_index(jq, i0, ns), a0n);
+        if (r1ok) Load4<S, DT>::get(Db + panel_index(jq, i1, ns), a1n);
       }
     };
     if (bb < bb1) fetch(bb, kb);
@@ -613,7 +634,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     launch(PH_STAGE_NEAR_MVM, k_near_mvm<S, DT>, dim3((unsigned)m.n_leaves, (unsigned)nrc, (unsigned)T), dim3(NT),
            nst, (const S*)xt, yt, (const DT*)in.D.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
            (const int64_t*)m.near_rowptr.p, (const int64_t*)m.near_tb.p, (const int32_t*)m.near_nt.p,
-           (const int64_t*)m.near_D.p, leaf0, m.n, Rs, m.N_nf_pad);
+           (const int32_t*)m.near_tr.p, (const int64_t*)m.near_D.p, leaf0, m.n, Rs, m.N_nf_pad);
     if (!serial) PH_HIP(hipEventRecord(in.ev_join, in.aux));
   };
   near_field();

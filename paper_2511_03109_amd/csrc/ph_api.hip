@@ -46,11 +46,17 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   m->kernel_evals = hm.kernel_evals;
   m->near_factor_entries = hm.near_factor_entries;
 
-  // canonical near D offsets
-  m->D_off_host.assign(m->n_near + 1, 0);
-  for (int64_t b = 0; b < m->n_near; ++b)
-    m->D_off_host[b + 1] = m->D_off_host[b] + (t.size(t.near[2 * b]) + 15) / 16 * 16 * t.size(t.near[2 * b + 1]);
-  m->N_nf_pad = m->D_off_host[m->n_near];
+  // stored near blocks (s <= t): offsets of the instantiated blocks (rows padded to 16)
+  std::vector<int64_t> doff(hm.nstore.size() + 1, 0);
+  for (size_t q = 0; q < hm.nstore.size(); ++q)
+    doff[q + 1] = doff[q] + (int64_t)(hm.nstore[q].ns + 15) / 16 * 16 * hm.nstore[q].nt;
+  m->N_nf_pad = doff.back();
+  m->D_off_host.assign(m->n_near, 0);
+  m->D_tr_host.assign(m->n_near, 0);
+  for (int64_t b = 0; b < m->n_near; ++b) {
+    m->D_off_host[b] = doff[hm.near_src[b]];
+    m->D_tr_host[b] = hm.near_tr[b];
+  }
 
   // near stored blocks and tiles
   std::vector<NearDev> nd(hm.nstore.size());
@@ -62,17 +68,16 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
     NearDev& x = nd[q];
     x.s_begin = s.s_begin; x.t_begin = s.t_begin;
     x.P_off = s.P_off; x.core_off = s.core_off; x.th1_off = s.th1_off; x.th2_off = s.th2_off;
-    x.D_st = m->D_off_host[s.b_st];
-    x.D_ts = s.b_ts >= 0 ? m->D_off_host[s.b_ts] : -1;
+    x.D_st = doff[q];
     x.ns = s.ns; x.nt = s.nt; x.r_e = s.r_e; x.r1 = s.r1; x.r2 = s.r2;
-    x.ldp = s.ldp; x.lds = (s.ns + 15) / 16 * 16; x.ldt = (s.nt + 15) / 16 * 16;
+    x.ldp = s.ldp;
     m->near_rank_canon[s.b_st] = s.r_e;
     const double w = (double)s.ns * s.nt * (s.b_ts >= 0 ? 2 : 1);
     wsum += w;
     rsum += w * s.r_e;
     m->near_rank_max = std::max(m->near_rank_max, s.r_e);
-    for (int32_t j0 = 0; j0 < s.nt; j0 += TILE)
-      for (int32_t i0 = 0; i0 < s.ns; i0 += TILE) {
+    for (int32_t j0 = 0; j0 < s.nt; j0 += TILE_J)
+      for (int32_t i0 = 0; i0 < (s.ns + 15) / 16 * 16; i0 += TILE) {   // padding rows are written (0)
         tiles.push_back((int32_t)q);
         tiles.push_back(i0);
         tiles.push_back(j0);
@@ -119,13 +124,14 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   // CSR of near blocks by target leaf (canonical list is sorted by sigma)
   const int32_t leaf0 = t.leaves.empty() ? 0 : t.leaves.front();
   std::vector<int64_t> nrow(m->n_leaves + 1, 0), ntb(m->n_near), nD(m->n_near);
-  std::vector<int32_t> nnt(m->n_near);
+  std::vector<int32_t> nnt(m->n_near), ntr(m->n_near);
   for (int64_t b = 0; b < m->n_near; ++b) {
     const int32_t s = t.near[2 * b], u = t.near[2 * b + 1];
     nrow[s - leaf0 + 1]++;
     ntb[b] = t.begin[u];
     nnt[b] = (int32_t)t.size(u);
     nD[b] = m->D_off_host[b];
+    ntr[b] = m->D_tr_host[b];
   }
   for (int64_t i = 0; i < m->n_leaves; ++i) nrow[i + 1] += nrow[i];
   // Coupling work list.  The nodes of every level >= min_far are cut into boxes of NTG = 16
@@ -222,6 +228,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   m->near_tb.upload(ntb.data(), ntb.size(), st);
   m->near_D.upload(nD.data(), nD.size(), st);
   m->near_nt.upload(nnt.data(), nnt.size(), st);
+  m->near_tr.upload(ntr.data(), ntr.size(), st);
   m->cstore.upload(cd.data(), cd.size(), st);
   m->ff_chat.upload(chat.data(), chat.size(), st);
   m->ff_theta.upload(hm.ff_theta.data(), hm.ff_theta.size(), st);
@@ -236,7 +243,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
                               m->nchild.bytes() + m->cid.bytes() + m->parent.bytes() + m->nbegin.bytes() + m->nend.bytes() +
                               m->nstore.bytes() + m->nf_P.bytes() + m->nf_core.bytes() +
                               m->nf_theta.bytes() + m->tiles.bytes() + m->near_rowptr.bytes() +
-                              m->near_tb.bytes() + m->near_D.bytes() + m->near_nt.bytes() +
+                              m->near_tb.bytes() + m->near_D.bytes() + m->near_nt.bytes() + m->near_tr.bytes() +
                               m->cstore.bytes() + m->ff_chat.bytes() + m->ff_theta.bytes() + m->grp_targets.bytes() +
                               m->grp_entry.bytes() + m->ent_cls.bytes() + m->ent_tau.bytes() +
                               m->ent_wpre.bytes() + m->grp_w.bytes());
@@ -666,20 +673,23 @@ int ph_inst_near_block(const ph_inst* k, int t, int64_t b, double* host_out) {
     const ph::DeviceModel& m = *in.m;
     need(t >= 0 && t < in.T, "slot out of range");
     need(b >= 0 && b < m.n_near, "near block index out of range");
-    const int64_t off = m.D_off_host[b], cnt = m.D_off_host[b + 1] - off;
     const ph::TreeData& tr = *m.tree;
-    const int64_t ns = tr.size(tr.near[2 * b]), nt = tr.size(tr.near[2 * b + 1]), ld = (ns + 15) / 16 * 16;
+    const int64_t ns = tr.size(tr.near[2 * b]), nt = tr.size(tr.near[2 * b + 1]);
+    const bool trn = m.D_tr_host[b] != 0;
+    const int64_t rows = trn ? nt : ns, cols = trn ? ns : nt;     // the stored block
+    const int64_t cnt = (rows + 15) / 16 * 16 * cols;
     PH_HIP(hipDeviceSynchronize());
     std::vector<char> buf(cnt * in.d_esize);
-    PH_HIP(hipMemcpy(buf.data(), in.D.p + ((size_t)t * m.N_nf_pad + off) * in.d_esize, buf.size(),
+    PH_HIP(hipMemcpy(buf.data(), in.D.p + ((size_t)t * m.N_nf_pad + m.D_off_host[b]) * in.d_esize, buf.size(),
                      hipMemcpyDeviceToHost));
+    auto val = [&](int64_t idx) {
+      return in.dt == PH_F64   ? ((double*)buf.data())[idx]
+             : in.dt == PH_F32 ? (double)((float*)buf.data())[idx]
+                               : (double)ph::from_bf16(((ph::bf16*)buf.data())[idx]);
+    };
     for (int64_t j = 0; j < nt; ++j)
-      for (int64_t i = 0; i < ns; ++i) {
-        const int64_t src = i + j * ld;
-        host_out[i + j * ns] = in.dt == PH_F64   ? ((double*)buf.data())[src]
-                               : in.dt == PH_F32 ? (double)((float*)buf.data())[src]
-                                                 : (double)ph::from_bf16(((ph::bf16*)buf.data())[src]);
-      }
+      for (int64_t i = 0; i < ns; ++i)
+        host_out[i + j * ns] = trn ? val(ph::panel_index(j, i, cols)) : val(ph::panel_index(i, j, cols));
   });
 }
 

@@ -80,12 +80,47 @@ __host__ __device__ inline S widen(DT x) { return (S)x; }
 template <>
 __host__ __device__ inline float widen<float, bf16>(bf16 x) { return from_bf16(x); }
 
-// per stored near block (s <= t)
-// (leading dimensions: ldp of the stored factor columns, lds / ldt of the instantiated
-// (s, t) / (t, s) blocks; all are the row counts rounded up to a multiple of 16)
+// Near-field blocks are stored once per pair (s <= t).  An instantiated block D (n_s x n_t)
+// is kept in 16-row panels: entry (i, j) at (i / 16) * 16 n_t + i % 16 + 16 j, rows
+// padded to a multiple of 16 with zeros, so every 16 x 16 tile is one contiguous 2 KB
+// chunk whichever way the MVM reads it (D_st x_t for s, D_st^T x_s for t).
+__host__ __device__ inline int64_t panel_index(int64_t i, int64_t j, int64_t ncols) {
+  return (i >> 4) * 16 * ncols + (i & 15) + 16 * j;
+}
+
+// Four consecutive stored values (aligned to 4 elements), widened to the compute type.
+template <typename S, typename DT>
+struct Load4;
+template <>
+struct Load4<double, double> {
+  static __device__ __forceinline__ void get(const double* p, double* o) {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    const v4 v = *reinterpret_cast<const v4*>(p);
+    o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+  }
+};
+template <>
+struct Load4<float, float> {
+  static __device__ __forceinline__ void get(const float* p, float* o) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const v4 v = *reinterpret_cast<const v4*>(p);
+    o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+  }
+};
+template <>
+struct Load4<float, bf16> {
+  static __device__ __forceinline__ void get(const bf16* p, float* o) {
+    typedef unsigned short v4 __attribute__((ext_vector_type(4)));
+    const v4 v = *reinterpret_cast<const v4*>(p);
+    o[0] = from_bf16(bf16{v[0]}); o[1] = from_bf16(bf16{v[1]});
+    o[2] = from_bf16(bf16{v[2]}); o[3] = from_bf16(bf16{v[3]});
+  }
+};
+
+// per stored near block (s <= t); ldp: leading dimension of the stored factor columns
 struct NearDev {
-  int64_t s_begin, t_begin, P_off, core_off, th1_off, th2_off, D_st, D_ts;
-  int32_t ns, nt, r_e, r1, r2, ldp, lds, ldt;
+  int64_t s_begin, t_begin, P_off, core_off, th1_off, th2_off, D_st;
+  int32_t ns, nt, r_e, r1, r2, ldp;
 };
 
 // per stored far class (offset >= 0 lexicographically)
@@ -96,7 +131,8 @@ struct ClassDev {
 
 constexpr int NT = 256;    // threads per workgroup (4 wavefronts of 64)
 constexpr int WAVE = 64;
-constexpr int TILE = 32;   // near-field instantiation tile edge
+constexpr int TILE = 32;   // near-field instantiation tile: rows
+constexpr int TILE_J = 16; // near-field instantiation tile: columns
 constexpr int TC = 8;      // parameter slots processed together by the near-field kernel
 constexpr int MAXT = 64;   // parameter values per theta-vector launch
 constexpr int RC = 16;     // right-hand sides per MFMA column tile
@@ -114,8 +150,8 @@ struct DeviceModel {
   int near_rank_max = 0, far_rank_max = 0;
   std::vector<int32_t> near_rank_canon;   // per canonical near block (-1 if transposed copy)
   std::vector<int32_t> class_ranks;       // per class, 2 + d_theta entries
-  std::vector<int64_t> D_off_host;        // per canonical near block, n_near + 1 (padded blocks:
-                                          // leading dimension = rows rounded up to 16)
+  std::vector<int64_t> D_off_host;        // per canonical near block: offset of its stored block
+  std::vector<int32_t> D_tr_host;         // per canonical near block: 1 if stored as its transpose
   // device arrays
   DevArr<double> U, E;
   DevArr<int64_t> perm;
@@ -125,8 +161,8 @@ struct DeviceModel {
   DevArr<double> nf_P, nf_core, nf_theta;
   DevArr<int32_t> tiles;                  // 3 per tile: stored block, i0, j0
   DevArr<int64_t> near_rowptr;            // per leaf index
-  DevArr<int64_t> near_tb, near_D;        // per canonical near block: tau begin, D offset
-  DevArr<int32_t> near_nt;
+  DevArr<int64_t> near_tb, near_D;        // per canonical near block: tau begin, stored D offset
+  DevArr<int32_t> near_nt, near_tr;       // per canonical near block: n_tau, stored transposed
   DevArr<ClassDev> cstore;
   DevArr<double> ff_chat, ff_theta;       // far panels (r1 r2 of Pp x Pp per class), theta factors
   // coupling work list: target boxes of NTG nodes of one level (see coupling_groups)
