@@ -378,11 +378,15 @@ def main():
     P = mi["P"]
     ncls = tree.info["n_classes"]
     nfar = tree.info["n_far"]
+    # near blocks are stored once per pair (s <= t): sum over s <= t of n_s n_t entries
+    nd = tree.nodes()
+    leaf_sizes = (nd["end"] - nd["begin"])[nd["level"] == tree.info["l_max"]]
+    stored = (mi["near_entries"] + float(np.sum(leaf_sizes.astype(np.float64) ** 2))) / 2.0
     kernels = {
-        # each stored factor entry P_b[k][e] read once, each near-block entry written once per slot
-        "k_near_instantiate": ("near_inst", "hbm", 8.0 * mi["near_factor_entries"] + 8.0 * T * mi["near_entries"]),
-        # D read once, x and y once per slot
-        "k_near_mvm": ("near_mvm", "hbm", 8.0 * T * (mi["near_entries"] + 2.0 * n * R)),
+        # each stored factor entry P_b[k][e] read once, each stored block entry written once per slot
+        "k_near_instantiate": ("near_inst", "hbm", 8.0 * mi["near_factor_entries"] + 8.0 * T * stored),
+        # each stored block entry read once per slot (it serves D_st and D_ts), x and y once
+        "k_near_mvm": ("near_mvm", "hbm", 8.0 * T * (stored + 2.0 * n * R)),
         # y_hat_s += C x_hat_t for every far block: 2 P^2 R flops per block and slot
         "k_coupling": ("coupling", "mfma", 2.0 * P * P * R * nfar * T),
     }
@@ -400,7 +404,7 @@ def main():
     dominant = max(roof, key=lambda k: roof[k]["ms_per_step"])
     # whole-step algorithmic bytes per theta (near factors once per step, D write + read,
     # couplings, vectors)
-    step_bytes = (8.0 * mi["near_factor_entries"] + T * 8.0 * (2 * mi["near_entries"]
+    step_bytes = (8.0 * mi["near_factor_entries"] + T * 8.0 * (2 * stored
                   + 2 * ncls * P * P + 4 * n * R + 2 * tree.info["n_nodes"] * P * R))
     out = {
         "metric": METRIC,

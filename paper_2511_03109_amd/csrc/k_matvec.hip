@@ -658,8 +658,8 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
              m.n_nodes, Rs, G, Cps, part_stride, (int)m.n_groups);
     };
     // 8 waves (4 row groups x 2 target halves) for Pp > 64, else 4 waves over the targets;
-    // PH_COUPLING_PD selects the register prefetch depth (1 or 2)
-    int pd = in.tune_prefetch == 2 ? 2 : 1;
+    // register prefetch depth 2 (PH_COUPLING_PD or the autotuner may select 1)
+    int pd = in.tune_prefetch == 1 ? 1 : 2;
     if (const char* env = std::getenv("PH_COUPLING_PD")) pd = std::atoi(env) == 2 ? 2 : 1;
     const int nMt = m.Pp / 16;
     if (nMt == 8) {
