@@ -2,6 +2,7 @@
 // parametric vectors, far-field couplings C(theta) = L H(theta) R^T (Sec. 4.2) and
 // near-field blocks D_b(theta) = reshape(P_b c_b(theta), [n_s, n_t]) (Sec. 4.3).
 // No kernel evaluation happens here.
+#include <cstdlib>
 #include <cstring>
 
 #include "ph_device.hpp"
@@ -209,6 +210,7 @@ __global__ void __launch_bounds__(NT) k_near_instantiate(
 template <typename S, typename DT>
 void instantiate_impl(InstData& in, const double* theta, hipStream_t st) {
   const DeviceModel& m = *in.m;
+  join_near(in, st);   // a previous near-field instantiation may still read the theta vectors
   // theta -> pinned staging -> device.  The staging buffer is rewritten only after the
   // previous copy out of it has run (ev_theta); under graph capture the copy becomes a
   // graph node that reads the staging buffer at replay time.
@@ -235,10 +237,25 @@ void instantiate_impl(InstData& in, const double* theta, hipStream_t st) {
   launch(PH_STAGE_FAR_INST, k_far_instantiate<S>, dim3((unsigned)(nMt * nMt), (unsigned)m.n_stored_cls), dim3(NT), st,
          (const ClassDev*)m.cstore.p, (const double*)m.ff_chat.p, (const double*)m.ff_theta.p,
          (const double*)in.v.p, (S*)in.C.p, Cps, m.Pp, in.T, m.p_theta, m.d_theta);
-  launch(PH_STAGE_NEAR_INST, k_near_instantiate<DT>, dim3((unsigned)m.n_tiles), dim3(NT), st,
+  // The near-field blocks (HBM-bound, the bulk of the instantiation) are written on the
+  // instance's second stream: they overlap the far-field panels here and, in a following
+  // ph_matvec, the upward pass and the coupling; the near-field MVM runs on the same
+  // stream after them, and every other reader of the instance joins it first (join_near).
+  const bool serial = std::getenv("PH_SERIAL_MVM") ? std::atoi(std::getenv("PH_SERIAL_MVM")) != 0
+                                                   : in.tune_overlap == 0;
+  hipStream_t nst = serial ? st : in.aux;
+  if (!serial) {
+    PH_HIP(hipEventRecord(in.ev_fork, st));          // theta vectors are ready
+    PH_HIP(hipStreamWaitEvent(in.aux, in.ev_fork, 0));
+  }
+  launch(PH_STAGE_NEAR_INST, k_near_instantiate<DT>, dim3((unsigned)m.n_tiles), dim3(NT), nst,
          (const NearDev*)m.nstore.p, (const int32_t*)m.tiles.p, (const double*)m.nf_P.p,
          (const double*)m.nf_core.p, (const double*)m.nf_theta.p, (const double*)in.v.p, (DT*)in.D.p,
          m.N_nf_pad, in.T, m.p_theta, m.d_theta);
+  if (!serial) {
+    PH_HIP(hipEventRecord(in.ev_near, in.aux));
+    in.near_pending = true;
+  }
 }
 
 template void instantiate_impl<double, double>(InstData&, const double*, hipStream_t);

@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(NW * 64) k_coupling(
     const S* __restrict__ xh, S* __restrict__ out, const S* __restrict__ C,
     const int32_t* __restrict__ grp_targets, const int32_t* __restrict__ grp_entry,
     const int32_t* __restrict__ ent_cls, const int32_t* __restrict__ ent_tau,
-    const int32_t* __restrict__ ent_wpre, const int32_t* __restrict__ grp_w, int Pp, int64_t nodes,
+    const int32_t* __restrict__ chunk_first, int Pp, int64_t nodes,
     int64_t Rs, int G, int64_t Cps, int64_t part_stride, int n_groups) {
   typedef Tile16<S> MF;
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
@@ -267,19 +267,8 @@ __global__ void __launch_bounds__(NW * 64) k_coupling(
   for (int s = 0; s < NTW; ++s)
 #pragma unroll
     for (int j = 0; j < TPW; ++j) acc[s][j] = (typename MF::acc_t){0, 0, 0, 0};
-  // chunk g = the entries whose work prefix lies in [W g / G, W (g + 1) / G)
-  const int e_begin = grp_entry[grp], e_end = grp_entry[grp + 1];
-  const int64_t W = grp_w[grp];
-  auto first_at = [&](int64_t lim) {   // first entry of the box with prefix >= lim
-    int lo = e_begin, hi = e_end;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (ent_wpre[mid] < lim) lo = mid + 1;
-      else hi = mid;
-    }
-    return lo;
-  };
-  const int ea = first_at((W * g + G - 1) / G), eb = first_at((W * (g + 1) + G - 1) / G);
+  // chunk g of this box (boundaries balanced by estimated work, computed on the host)
+  const int ea = chunk_first[grp * (G + 1) + g], eb = chunk_first[grp * (G + 1) + g + 1];
   // raw buffer views of this slot's x_hat and C: an offset past the end reads zeros
   // without touching memory (targets that do not use an entry's class)
   const __amdgpu_buffer_rsrc_t xrs = __builtin_amdgcn_make_buffer_rsrc(
@@ -575,6 +564,12 @@ __global__ void __launch_bounds__(NT) k_leaf_down(S* __restrict__ yt, const S* _
   }
 }
 
+static inline int ilog2(int g) {
+  int c = 0;
+  while ((1 << c) < g) ++c;
+  return c;
+}
+
 template <typename S, typename DT>
 void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double beta, double nugget,
                  hipStream_t st) {
@@ -588,12 +583,12 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
   // PH_COUPLING_CHUNKS overrides (tuning)
   // launch configuration: environment override (tuning sweeps), else ph_autotune's
   // choice, else the heuristic (8 chunks, prefetch 1, near field overlapped)
-  int G = 1;
+  int G = 1;   // a power of two <= 64
   if (use_far && m.n_groups > 0) G = m.max_group_entries >= 16 ? 8 : (m.max_group_entries >= 4 ? 2 : 1);
-  if (in.tune_chunks > 0) G = std::min<int64_t>(in.tune_chunks, std::max<int64_t>(m.max_group_entries, 1));
+  if (in.tune_chunks > 0) G = in.tune_chunks;
   if (const char* env = std::getenv("PH_COUPLING_CHUNKS")) {
     const int g = std::atoi(env);
-    if (g >= 1 && g <= 64 && g <= std::max<int64_t>(m.max_group_entries, 1)) G = g;
+    if (g >= 1 && g <= 64 && (g & (g - 1)) == 0) G = g;
   }
   // PH_SERIAL_MVM=1 runs the near field on the caller's stream (no overlap; profiling)
   bool serial = in.tune_overlap == 0;
@@ -628,8 +623,12 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
   // the upward pass instead measured slower: it then overlaps the coupling throughout.)
   auto near_field = [&] {
     if (!serial) {
+      // aux is already ordered after a pending near-field instantiation
       PH_HIP(hipEventRecord(in.ev_fork, st));
       PH_HIP(hipStreamWaitEvent(in.aux, in.ev_fork, 0));
+      in.near_pending = false;   // joined into st below (ev_join follows the near-field MVM)
+    } else {
+      join_near(in, st);
     }
     launch(PH_STAGE_NEAR_MVM, k_near_mvm<S, DT>, dim3((unsigned)m.n_leaves, (unsigned)nrc, (unsigned)T), dim3(NT),
            nst, (const S*)xt, yt, (const DT*)in.D.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
@@ -654,7 +653,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     auto run = [&](auto kern, int nw) {
       launch(PH_STAGE_COUPLING, kern, cg, dim3(64 * nw), st, (const S*)xh, cout, (const S*)in.C.p,
              (const int32_t*)m.grp_targets.p, (const int32_t*)m.grp_entry.p, (const int32_t*)m.ent_cls.p,
-             (const int32_t*)m.ent_tau.p, (const int32_t*)m.ent_wpre.p, (const int32_t*)m.grp_w.p, m.Pp,
+             (const int32_t*)m.ent_tau.p, (const int32_t*)m.chunk_first.p + m.chunk_off[ilog2(G)], m.Pp,
              m.n_nodes, Rs, G, Cps, part_stride, (int)m.n_groups);
     };
     // 8 waves (4 row groups x 2 target halves) for Pp > 64, else 4 waves over the targets;

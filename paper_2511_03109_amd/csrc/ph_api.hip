@@ -236,8 +236,24 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   m->grp_entry.upload(gptr.data(), gptr.size(), st);
   m->ent_cls.upload(ecls.data(), ecls.size(), st);
   m->ent_tau.upload(etau.data(), etau.size(), st);
-  m->ent_wpre.upload(ewpre.data(), ewpre.size(), st);
-  m->grp_w.upload(gw.data(), gw.size(), st);
+  // chunk boundaries: chunk g of G holds the entries whose work prefix lies in
+  // [ceil(W g / G), ceil(W (g + 1) / G))
+  std::vector<int32_t> cfirst;
+  for (int c = 0; c < 7; ++c) {
+    const int G = 1 << c;
+    m->chunk_off[c] = (int64_t)cfirst.size();
+    for (size_t b = 0; b + 1 < gptr.size(); ++b) {
+      const int32_t e0 = gptr[b], e1 = gptr[b + 1];
+      const int64_t W = gw[b];
+      for (int g = 0; g <= G; ++g) {
+        const int64_t lim = (W * g + G - 1) / G;
+        int32_t e = e0;
+        while (e < e1 && ewpre[e] < lim) ++e;
+        cfirst.push_back(e);
+      }
+    }
+  }
+  m->chunk_first.upload(cfirst.data(), cfirst.size(), st);
   PH_HIP(hipStreamSynchronize(st));  // host staging buffers die with this call
   m->device_bytes = (int64_t)(m->U.bytes() + m->E.bytes() + m->perm.bytes() + m->first_child.bytes() +
                               m->nchild.bytes() + m->cid.bytes() + m->parent.bytes() + m->nbegin.bytes() + m->nend.bytes() +
@@ -246,7 +262,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
                               m->near_tb.bytes() + m->near_D.bytes() + m->near_nt.bytes() + m->near_tr.bytes() +
                               m->cstore.bytes() + m->ff_chat.bytes() + m->ff_theta.bytes() + m->grp_targets.bytes() +
                               m->grp_entry.bytes() + m->ent_cls.bytes() + m->ent_tau.bytes() +
-                              m->ent_wpre.bytes() + m->grp_w.bytes());
+                              m->chunk_first.bytes());
   return m;
 }
 
@@ -340,6 +356,7 @@ int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype
       PH_HIP(hipStreamCreateWithFlags(&in->aux, hipStreamNonBlocking));
       PH_HIP(hipEventCreateWithFlags(&in->ev_fork, hipEventDisableTiming));
       PH_HIP(hipEventCreateWithFlags(&in->ev_join, hipEventDisableTiming));
+      PH_HIP(hipEventCreateWithFlags(&in->ev_near, hipEventDisableTiming));
     }
     in->theta.assign(theta, theta + (size_t)T * md.d_theta);
     if (dt == PH_F64) ph::instantiate_impl<double, double>(*in, theta, st);

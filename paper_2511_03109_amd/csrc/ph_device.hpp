@@ -170,8 +170,10 @@ struct DeviceModel {
   DevArr<int32_t> grp_entry;              // n_groups + 1
   DevArr<int32_t> ent_cls;                // per entry: class
   DevArr<int32_t> ent_tau;                // per entry: NTG source nodes (-1 = target unused)
-  DevArr<int32_t> ent_wpre;               // per entry: work of the box's earlier entries
-  DevArr<int32_t> grp_w;                  // per box: total work
+  // class-list chunks of equal estimated work: for G = 2^c (c = 0..6), box b's chunk g
+  // is entries [chunk_first[chunk_off[c] + b (G + 1) + g], ... + g + 1)
+  DevArr<int32_t> chunk_first;
+  int64_t chunk_off[7] = {0, 0, 0, 0, 0, 0, 0};
   int64_t device_bytes = 0;
 };
 
@@ -192,6 +194,8 @@ struct InstData {
   DevArr<double> bil_part;            // ph_bilinear: per-block partial sums
   hipStream_t aux = nullptr;          // second stream: near field concurrent with the far chain
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_near = nullptr;       // after the near-field instantiation on aux
+  bool near_pending = false;          // instantiated blocks may still be in flight on aux
   DevArr<double> theta_d;             // T x d_theta on the device (read by the theta-vector kernel)
   double* theta_pin = nullptr;        // pinned staging of theta
   hipEvent_t ev_theta = nullptr;      // after the last use of theta_pin
@@ -200,6 +204,8 @@ struct InstData {
   // launch configuration of the MVM chosen by ph_autotune (0 = default heuristics)
   int tune_chunks = 0, tune_prefetch = 0, tune_overlap = -1;
   ~InstData() {
+    if (aux) (void)hipStreamSynchronize(aux);   // no kernel of this instance may outlive its buffers
+    if (ev_near) (void)hipEventDestroy(ev_near);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (ev_theta) (void)hipEventDestroy(ev_theta);
@@ -207,6 +213,15 @@ struct InstData {
     if (aux) (void)hipStreamDestroy(aux);
   }
 };
+
+// Make `st` wait for a near-field instantiation still running on the instance's second
+// stream (every entry point that reads the instance on a stream calls this first).
+inline void join_near(InstData& in, hipStream_t st) {
+  if (in.near_pending) {
+    PH_HIP(hipStreamWaitEvent(st, in.ev_near, 0));
+    in.near_pending = false;
+  }
+}
 
 // S: compute type (C, x_hat, I/O); DT: storage type of the near blocks D
 template <typename S, typename DT>
