@@ -366,6 +366,23 @@ def main():
     _lib.check(lib.ph_trace_read(stats, 1), "ph_trace_read")
     total_ms = ev0.elapsed_time(ev1)
     ms_step = total_ms / args.steps
+    # the same step once more with the near field on the caller's stream (no overlap), to
+    # report each kernel's own duration beside its duration while sharing the GPU
+    os.environ["PH_SERIAL_MVM"] = "1"
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    iso_stats = _lib.TraceStats()
+    lib.ph_trace_read(iso_stats, 1)
+    lib.ph_trace_enable(1)
+    iso_steps = 3
+    for _ in range(iso_steps):
+        step()
+    torch.cuda.synchronize()
+    lib.ph_trace_enable(0)
+    _lib.check(lib.ph_trace_read(iso_stats, 1), "ph_trace_read")
+    del os.environ["PH_SERIAL_MVM"]
+    iso_stage = {name: iso_stats.ms[i] / max(iso_stats.count[i], 1) for i, name in enumerate(_lib.STAGES)}
     per_stage = {name: {"ms_total": stats.ms[i], "launches": stats.count[i],
                         "ms_avg": stats.ms[i] / max(stats.count[i], 1)}
                  for i, name in enumerate(_lib.STAGES)}
@@ -402,6 +419,12 @@ def main():
                        "algorithmic_per_launch": work, "avg_launch_ms": ms,
                        "ms_per_step": per_stage[stage]["ms_total"] / args.steps}
     dominant = max(roof, key=lambda k: roof[k]["ms_per_step"])
+    roof_iso = {}
+    for kname, (stage, bound, work) in kernels.items():
+        ms = iso_stage[stage]
+        ach = work / (ms * 1e-3) / (1e9 if bound == "hbm" else 1e12)
+        roof_iso[kname] = {"avg_launch_ms": ms, "achieved": ach, "frac": ach / roof[kname]["peak"],
+                           "unit": roof[kname]["unit"]}
     # whole-step algorithmic bytes per theta (near factors once per step, D write + read,
     # couplings, vectors)
     step_bytes = (8.0 * mi["near_factor_entries"] + T * 8.0 * (2 * stored
@@ -423,6 +446,7 @@ def main():
         "stages": per_stage,
         "roofline": roof[dominant],
         "kernels": roof,
+        "kernels_isolated": roof_iso,
         "model": {"near_entries": mi["near_entries"], "near_factor_entries": mi["near_factor_entries"],
                   "near_rank_mean": mi["near_rank_mean"], "far_rank_mean": mi["far_rank_mean"],
                   "classes": ncls, "far_blocks": tree.info["n_far"], "near_blocks": tree.info["n_near"],
