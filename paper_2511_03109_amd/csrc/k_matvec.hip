@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(NT) k_transfer_down(S* __restrict__ yh, const 
 }
 
 // Coupling y_hat_s = sum over far blocks (s, t) of C_class x_hat_t on the matrix cores.
-// One workgroup of NW wavefronts per (class chunk g, target box, RHS tile, slot); a box
+// One workgroup of NW wavefronts per (class chunk g, slot, target box, RHS tile); a box
 // holds NTG nodes of one level and its work list has one entry per translation class,
 // so each C_class panel staged in LDS feeds the MFMAs of every target in the box that
 // uses the class.  The class list of every box is cut into G chunks and g is the fastest
@@ -253,10 +253,12 @@ __global__ void __launch_bounds__(NW * 64) k_coupling(
   static_assert(NTG % WT == 0 && NTG % NW == 0 && BUT >= 1, "work split");
   __shared__ __attribute__((aligned(16))) S As[2][MT * 256];
   __shared__ __attribute__((aligned(16))) S Bs[2][NTG][256];
+  // grid (chunk g, slot, box + n_groups * RHS tile): boxes are sorted heaviest first and
+  // every slot of a box is dispatched before the next box, so the long workgroups start first
   const int g = blockIdx.x;
-  const int grp = blockIdx.y % n_groups;
-  const int r0 = (blockIdx.y / n_groups) * RC;
-  const int64_t slot = blockIdx.z;
+  const int64_t slot = blockIdx.y;
+  const int grp = blockIdx.z % n_groups;
+  const int r0 = (blockIdx.z / n_groups) * RC;
   const int lane = threadIdx.x % WAVE;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int wr = wave % WR, wt = wave / WR;
@@ -413,7 +415,11 @@ __global__ void __launch_bounds__(NT) k_near_mvm(
     int32_t leaf0, int64_t n, int64_t R, int64_t N_nf) {
   typedef Mfma<S> MF;
   constexpr int CH = 128;
-  const int32_t li = blockIdx.x;
+  // Workgroups are dealt to the 8 XCDs round robin; XCD x gets the contiguous leaf range
+  // [x q, x q + q) (q = n_leaves / 8), a compact region of space, so that the two reads of
+  // a stored block (for s and, transposed, for t) mostly meet in the same L2.
+  const int nl = gridDim.x, q8 = nl / 8;
+  const int32_t li = (int)blockIdx.x < 8 * q8 ? (int)(blockIdx.x % 8) * q8 + (int)(blockIdx.x / 8) : (int)blockIdx.x;
   const int32_t s = leaf0 + li;
   const int r0 = blockIdx.y * RC;
   const int64_t slot = blockIdx.z;
@@ -649,7 +655,9 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     }
     const int64_t part_stride = T * m.n_nodes * m.Pp * Rs;
     S* cout = G > 1 ? (S*)in.part.p : yh;
-    dim3 cg((unsigned)G, (unsigned)(m.n_groups * nrc), (unsigned)T);
+    if (T > 65535 || m.n_groups * nrc > 65535)
+      fail(PH_EUNSUPPORTED, "ph_matvec: too many parameter slots or target boxes x RHS tiles for one launch");
+    dim3 cg((unsigned)G, (unsigned)T, (unsigned)(m.n_groups * nrc));
     auto run = [&](auto kern, int nw) {
       launch(PH_STAGE_COUPLING, kern, cg, dim3(64 * nw), st, (const S*)xh, cout, (const S*)in.C.p,
              (const int32_t*)m.grp_targets.p, (const int32_t*)m.grp_entry.p, (const int32_t*)m.ent_cls.p,

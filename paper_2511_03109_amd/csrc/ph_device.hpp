@@ -355,10 +355,11 @@ __host__ __device__ inline int64_t frag_index(int m, int k, int Pp) {
   return (int64_t)(k >> 4) * Pp * 16 + (m >> 4) * 256 + (k & 15) * 16 + (m & 3) * 4 + ((m & 15) >> 2);
 }
 
-// Work estimate of one coupling entry with `act` targets using its class, in units of
-// half a target's matrix-core time for one stage: the multiplications plus the fixed
-// cost of staging a panel (loads, LDS stores, barrier).
-inline int32_t coupling_entry_weight(int act) { return 2 * act + 3; }
+// Work estimate of one coupling entry with `act` targets using its class, in units of one
+// target's matrix-core time per stage: the multiplications plus the fixed cost of a stage
+// (panel copy, fragment reads, barrier), which measured about 6 targets' worth on gfx950
+// (per workgroup: 1.21 us per stage + 0.21 us per active target and stage).
+inline int32_t coupling_entry_weight(int act) { return act + 6; }
 
 // Raw buffer resources (CDNA3/4 word 3: 32-bit data format, no swizzle); a load at
 // BUF_OOB lies past any buffer the library creates and returns zeros.
