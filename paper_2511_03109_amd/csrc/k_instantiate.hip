@@ -242,7 +242,7 @@ void instantiate_impl(InstData& in, const double* theta, hipStream_t st) {
   // ph_matvec, the upward pass and the coupling; the near-field MVM runs on the same
   // stream after them, and every other reader of the instance joins it first (join_near).
   const bool serial = std::getenv("PH_SERIAL_MVM") ? std::atoi(std::getenv("PH_SERIAL_MVM")) != 0
-                                                   : in.tune_overlap == 0;
+                                                   : in.tune_overlap != 1;
   hipStream_t nst = serial ? st : in.aux;
   if (!serial) {
     PH_HIP(hipEventRecord(in.ev_fork, st));          // theta vectors are ready

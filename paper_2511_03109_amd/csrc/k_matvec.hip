@@ -597,7 +597,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     if (g >= 1 && g <= 64 && (g & (g - 1)) == 0) G = g;
   }
   // PH_SERIAL_MVM=1 runs the near field on the caller's stream (no overlap; profiling)
-  bool serial = in.tune_overlap == 0;
+  bool serial = in.tune_overlap != 1;   // default: one stream (sharing the GPU measured no gain)
   if (const char* env = std::getenv("PH_SERIAL_MVM")) serial = std::atoi(env) != 0;
   hipStream_t nst = serial ? st : in.aux;
   if (Rs > in.Rcap || G > in.Gcap) {
