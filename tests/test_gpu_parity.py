@@ -433,3 +433,43 @@ def test_autotune_and_graph_replays():
     del g
     inst.matvec(xb)
     torch.cuda.synchronize()
+
+
+def test_nine_slots_twenty_rhs_and_tuned_config():
+    """T = 9 parameter slots (one more than the 8 the instantiation kernels batch) and R = 20
+    right-hand sides (two 16-wide tiles, the second ragged), before and after autotuning."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    n, T, R = 3000, 9, 20
+    X = inputs.points_for(2, n)
+    lt, lm, om = _setup(X, "matern32", [0.05], [0.5], 4, 9, 1e-8, 2, (3, 1))
+    thetas = np.linspace(0.06, 0.49, T)[:, None]
+    inst = api.Instance(lm, thetas)
+    x = inputs.normal_vectors(n, T * R, 12).T.reshape(T, R, n)
+    xd = torch.tensor(np.ascontiguousarray(x), device="cuda")
+    refs = [om.matvec(om.instantiate(thetas[t]), x[t].T).T for t in range(T)]
+    y = inst.matvec(xd).cpu().numpy()
+    for t in (0, 7, 8):
+        _close(y[t], refs[t], what=f"slot {t}")
+    cfg = inst.autotune(xd)
+    y = inst.matvec(xd).cpu().numpy()
+    for t in (1, 8):
+        _close(y[t], refs[t], what=f"slot {t} tuned {cfg}")
+
+
+def test_near_field_on_second_stream(monkeypatch):
+    """The near field on the instance's second stream (instantiation and MVM), including two
+    instantiations in a row without an MVM between them (the second must wait for the first
+    to finish reading the parametric vectors)."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    monkeypatch.setenv("PH_SERIAL_MVM", "0")
+    n = 3000
+    X = inputs.points_for(2, n)
+    lt, lm, om = _setup(X, "matern32", [0.05], [0.5], 4, 9, 1e-8, 2, (3, 1))
+    inst = api.Instance(lm, [[0.2], [0.3]])
+    inst.reinstantiate([[0.41], [0.11]])
+    x = inputs.normal_vectors(n, 2 * 3, 13).T.reshape(2, 3, n)
+    y = inst.matvec(torch.tensor(np.ascontiguousarray(x), device="cuda")).cpu().numpy()
+    for t, th in enumerate((0.41, 0.11)):
+        _close(y[t], om.matvec(om.instantiate(th), x[t].T).T, what=f"slot {t}")
