@@ -3,7 +3,7 @@
 // H^2-Matrix MVM"), for all parameter slots of an instance in one pass.
 //
 // Scratch layouts (S = double or float; Rs = R rounded up to a multiple of 16, the
-// padding columns hold zeros):
+// padding columns hold zeros, and Rs = 1 for a single right-hand side):
 //   xt, yt   [T][n][Rs]             tree order, right-hand side fastest
 //   xh, yh   [T][nodes][Pp][Rs]     P padded to Pp (multiple of 16) with zero rows
 //   part     [G][T][nodes][Pp][Rs]  coupling partial sums when the class list is split
@@ -234,7 +234,11 @@ __global__ void __launch_bounds__(NT) k_transfer_down(S* __restrict__ yh, const 
 // sources) is wave-uniform and read with scalar loads.  Waves form a WR x (NW / WR) grid:
 // wave (wr, wt) owns row tiles wr + WR j (j < TPW) of targets wt NTW .. wt NTW + NTW - 1;
 // FULL: the row tiles are exactly Pp / 16 (no tile test).
-template <typename S, int NW, int WR, int TPW, int PD, bool FULL>
+// PACK (one right-hand side): the 16 targets of the box are the 16 matrix-core columns,
+// B[k][c] = x_hat of target c's source for the entry's class (zero if c does not use it),
+// so a stage multiplies one C panel by one 16-column tile instead of 16 tiles of which 15
+// columns would be padding.  Requires the unpadded single-RHS layout (Rs = 1, r0 = 0).
+template <typename S, int NW, int WR, int TPW, int PD, bool FULL, bool PACK = false>
 __global__ void __launch_bounds__(NW * 64) k_coupling(
     const S* __restrict__ xh, S* __restrict__ out, const S* __restrict__ C,
     const int32_t* __restrict__ grp_targets, const int32_t* __restrict__ grp_entry,
@@ -244,15 +248,17 @@ __global__ void __launch_bounds__(NW * 64) k_coupling(
   typedef Tile16<S> MF;
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
   constexpr int NTH = NW * 64;
-  constexpr int WT = NW / WR, NTW = NTG / WT, MT = WR * TPW;
+  constexpr int NB = PACK ? 1 : NTG;            // 16-column B tiles per box
+  constexpr int WT = NW / WR, NTW = NB / WT, MT = WR * TPW;
   constexpr int KC = 16;                        // K rows per stage
   constexpr int EPU = 16 / (int)sizeof(S);      // elements per 16-byte unit
   constexpr int AU = (MT * 256 / EPU + NTH - 1) / NTH;   // C units per thread per stage
-  constexpr int TSW = NTG / NW;                 // targets staged per wave
+  constexpr int TSW = PACK ? 1 : NTG / NW;      // targets staged per wave
   constexpr int BUT = 256 / EPU / 64;           // x_hat units per lane per target
-  static_assert(NTG % WT == 0 && NTG % NW == 0 && BUT >= 1, "work split");
+  static_assert(NB % WT == 0 && (PACK || NTG % NW == 0) && BUT >= 1, "work split");
+  static_assert(!PACK || (WT == 1 && NTH >= 256), "packed mode: one column tile, 256 B loaders");
   __shared__ __attribute__((aligned(16))) S As[2][MT * 256];
-  __shared__ __attribute__((aligned(16))) S Bs[2][NTG][256];
+  __shared__ __attribute__((aligned(16))) S Bs[2][NB][256];
   // grid (chunk g, slot, box + n_groups * RHS tile): boxes are sorted heaviest first and
   // every slot of a box is dispatched before the next box, so the long workgroups start first
   const int g = blockIdx.x;
@@ -281,6 +287,7 @@ __global__ void __launch_bounds__(NW * 64) k_coupling(
   const int nsteps = (eb - ea) * nk;
   constexpr int A_LDS_UNITS = MT * 256 / EPU;
   u4 areg[PD][AU], breg[PD][TSW][BUT];
+  S preg[PD];   // packed mode: this thread's element (k = tid / 16, column tid % 16) of B
   // every load and LDS store below is unconditional (clamped stage, out-of-range offsets),
   // so the compiler tracks each register's pending load exactly and waits only at stash
   auto fetch = [&](int step, int rb) {
@@ -292,15 +299,33 @@ __global__ void __launch_bounds__(NW * 64) k_coupling(
       const int off = (FULL || u < a_units) ? cbase + u * 16 : BUF_OOB;
       areg[rb][q] = __builtin_amdgcn_raw_buffer_load_b128(crs, off, 0, 0);
     }
+    if constexpr (PACK) {
+      if (NTH == 256 || threadIdx.x < 256) {
+        // the 16 sources of the entry are wave-uniform (scalar loads); pick this lane's
+        const int c = lane & 15, k = threadIdx.x >> 4;
+        int tv = ent_tau[e * NTG];
 #pragma unroll
-    for (int q = 0; q < TSW; ++q) {
-      const int tv = ent_tau[e * NTG + wave * TSW + q];
-      const int base = ((tv * Pp + kc * KC) * (int)Rs + r0) * (int)sizeof(S);
+        for (int i = 1; i < NTG; ++i) {
+          const int ti = ent_tau[e * NTG + i];
+          tv = c == i ? ti : tv;
+        }
+        const int off = tv >= 0 ? ((tv * Pp + kc * KC + k) * (int)Rs + r0) * (int)sizeof(S) : BUF_OOB;
+        if constexpr (sizeof(S) == 8)
+          preg[rb] = __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(xrs, off, 0, 0));
+        else
+          preg[rb] = __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(xrs, off, 0, 0));
+      }
+    } else {
 #pragma unroll
-      for (int h = 0; h < BUT; ++h) {
-        const int u = lane + 64 * h;
-        const int rel = ((u / (RC / EPU)) * (int)Rs + (u % (RC / EPU)) * EPU) * (int)sizeof(S);
-        breg[rb][q][h] = __builtin_amdgcn_raw_buffer_load_b128(xrs, tv >= 0 ? base + rel : BUF_OOB, 0, 0);
+      for (int q = 0; q < TSW; ++q) {
+        const int tv = ent_tau[e * NTG + wave * TSW + q];
+        const int base = ((tv * Pp + kc * KC) * (int)Rs + r0) * (int)sizeof(S);
+#pragma unroll
+        for (int h = 0; h < BUT; ++h) {
+          const int u = lane + 64 * h;
+          const int rel = ((u / (RC / EPU)) * (int)Rs + (u % (RC / EPU)) * EPU) * (int)sizeof(S);
+          breg[rb][q][h] = __builtin_amdgcn_raw_buffer_load_b128(xrs, tv >= 0 ? base + rel : BUF_OOB, 0, 0);
+        }
       }
     }
   };
@@ -310,10 +335,14 @@ __global__ void __launch_bounds__(NW * 64) k_coupling(
       const int u = threadIdx.x + q * NTH;
       if (u < A_LDS_UNITS) reinterpret_cast<u4*>(As[buf])[u] = areg[rb][q];
     }
+    if constexpr (PACK) {
+      if (NTH == 256 || threadIdx.x < 256) Bs[buf][0][threadIdx.x] = preg[rb];
+    } else {
 #pragma unroll
-    for (int q = 0; q < TSW; ++q)
+      for (int q = 0; q < TSW; ++q)
 #pragma unroll
-      for (int h = 0; h < BUT; ++h) reinterpret_cast<u4*>(Bs[buf][wave * TSW + q])[lane + 64 * h] = breg[rb][q][h];
+        for (int h = 0; h < BUT; ++h) reinterpret_cast<u4*>(Bs[buf][wave * TSW + q])[lane + 64 * h] = breg[rb][q][h];
+    }
   };
   // one stage: prefetch stage st + PD into ring slot RF, multiply from LDS buffer BUF,
   // store stage st + 1 (ring slot RS) into the other LDS buffer.  With PD = 2 the loads of
@@ -326,7 +355,7 @@ __global__ void __launch_bounds__(NW * 64) k_coupling(
     const int e = ea + st / nk;
     bool use[NTW];
 #pragma unroll
-    for (int s = 0; s < NTW; ++s) use[s] = ent_tau[e * NTG + wt * NTW + s] >= 0;
+    for (int s = 0; s < NTW; ++s) use[s] = PACK || ent_tau[e * NTG + wt * NTW + s] >= 0;
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       const int k = kk + (lane >> 4);
@@ -366,6 +395,21 @@ __global__ void __launch_bounds__(NW * 64) k_coupling(
     if (st + 1 < nsteps) body(st + 1, I1(), R1(), I0());
   }
   S* o = out + (int64_t)g * part_stride + slot * nodes * Pp * Rs;
+  if constexpr (PACK) {
+    // column c of the tile is target c of the box, right-hand side 0
+    const int32_t node = grp_targets[grp * NTG + (lane & 15)];
+    if (node >= 0) {
+      S* on = o + (int64_t)node * Pp * Rs + r0;
+#pragma unroll
+      for (int j = 0; j < TPW; ++j) {
+        const int mt = wr + WR * j;
+        if (!FULL && mt >= nMt) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) on[(int64_t)(mt * 16 + MF::row(lane, q)) * Rs] = acc[0][j][q];
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int s = 0; s < NTW; ++s) {
     const int32_t node = grp_targets[grp * NTG + wt * NTW + s];
@@ -582,8 +626,9 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
   const DeviceModel& m = *in.m;
   const TreeData& t = *m.tree;
   const int64_t T = in.T;
-  const int64_t Rs = rhs_stride(R);
-  const int64_t nrc = Rs / RC;
+  // one right-hand side is stored unpadded (the coupling packs box targets instead)
+  const int64_t Rs = R == 1 ? 1 : rhs_stride(R);
+  const int64_t nrc = (Rs + RC - 1) / RC;
   const bool use_far = m.min_far >= 0;
   // class-list chunks per target box: 8 (one per XCD) unless the lists are too short;
   // PH_COUPLING_CHUNKS overrides (tuning)
@@ -654,6 +699,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
              (const int32_t*)m.nchild.p, (const int32_t*)m.cid.p, a, m.d, m.p_s, m.P, m.Pp, m.n_nodes, Rs);
     }
     const int64_t part_stride = T * m.n_nodes * m.Pp * Rs;
+    const bool pack = Rs == 1;   // packed coupling (box targets as matrix-core columns)
     S* cout = G > 1 ? (S*)in.part.p : yh;
     if (T > 65535 || m.n_groups * nrc > 65535)
       fail(PH_EUNSUPPORTED, "ph_matvec: too many parameter slots or target boxes x RHS tiles for one launch");
@@ -669,7 +715,19 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     int pd = in.tune_prefetch == 1 ? 1 : 2;
     if (const char* env = std::getenv("PH_COUPLING_PD")) pd = std::atoi(env) == 2 ? 2 : 1;
     const int nMt = m.Pp / 16;
-    if (nMt == 8) {
+    if (pack) {
+      // one right-hand side: 4 waves over the row tiles, one 16-target column tile
+      if (nMt == 8) {
+        if (pd == 2) run(k_coupling<S, 4, 4, 2, 2, true, true>, 4);
+        else run(k_coupling<S, 4, 4, 2, 1, true, true>, 4);
+      } else if (nMt > 4) {
+        run(k_coupling<S, 4, 4, 2, 1, false, true>, 4);
+      } else if (nMt == 4) {
+        run(k_coupling<S, 4, 4, 1, 1, true, true>, 4);
+      } else {
+        run(k_coupling<S, 4, 4, 1, 1, false, true>, 4);
+      }
+    } else if (nMt == 8) {
       if (pd == 2) run(k_coupling<S, 8, 4, 2, 2, true>, 8);
       else run(k_coupling<S, 8, 4, 2, 1, true>, 8);
     } else if (nMt > 4) {

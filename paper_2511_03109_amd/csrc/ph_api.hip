@@ -134,6 +134,61 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
     ntr[b] = m->D_tr_host[b];
   }
   for (int64_t i = 0; i < m->n_leaves; ++i) nrow[i + 1] += nrow[i];
+  // Each stored block is read twice by the near MVM: directly by the workgroup of one of
+  // its leaves and transposed by that of the other.  Ordering every leaf's list by an edge
+  // colouring of the near graph (one block per colour and leaf, both leaves of a block at
+  // the same colour) puts the two reads at the same list position, so the second one
+  // finds the block still in the memory-side cache.  Colour of the pair (s, u): its leaf
+  // offset o = coords(u) - coords(s) up to sign (o' with a positive first non-zero
+  // component a), and the parity of floor(c_a / o'_a) at the lower end c; the two blocks
+  // of a leaf with offsets o' and -o' differ in that parity.  The diagonal block is first.
+  {
+    const int d = t.d;
+    auto canon = [&](int32_t s, int32_t u, std::vector<int32_t>& o) {
+      o.resize(d);
+      int sg = 0;
+      for (int k = 0; k < d; ++k) {
+        o[k] = t.coords[(size_t)u * d + k] - t.coords[(size_t)s * d + k];
+        if (sg == 0 && o[k] != 0) sg = o[k] > 0 ? 1 : -1;
+      }
+      if (sg < 0)
+        for (int k = 0; k < d; ++k) o[k] = -o[k];
+      return sg;   // 0 on the diagonal, +1 when s is the lower end, -1 when u is
+    };
+    std::map<std::vector<int32_t>, int32_t> rank;
+    std::vector<int32_t> o;
+    for (int64_t b = 0; b < m->n_near; ++b)
+      if (canon(t.near[2 * b], t.near[2 * b + 1], o) != 0) rank.emplace(o, 0);
+    int32_t r = 0;
+    for (auto& kv : rank) kv.second = r++;
+    std::vector<int64_t> color(m->n_near), order(m->n_near);
+    for (int64_t b = 0; b < m->n_near; ++b) {
+      const int32_t s = t.near[2 * b], u = t.near[2 * b + 1];
+      const int sg = canon(s, u, o);
+      if (sg == 0) {
+        color[b] = 0;
+        continue;
+      }
+      int a = 0;
+      while (o[a] == 0) ++a;
+      const int32_t lower = sg > 0 ? s : u;
+      const int32_t c = t.coords[(size_t)lower * d + a];
+      const int32_t par = (c / o[a]) & 1;   // leaf coordinates are non-negative
+      color[b] = 1 + 2 * (int64_t)rank[o] + par;
+    }
+    for (int64_t b = 0; b < m->n_near; ++b) order[b] = b;
+    for (int64_t i = 0; i < m->n_leaves; ++i)
+      std::stable_sort(order.begin() + nrow[i], order.begin() + nrow[i + 1],
+                       [&](int64_t x, int64_t y) { return color[x] < color[y]; });
+    auto permute = [&](auto& v) {
+      auto w = v;
+      for (int64_t b = 0; b < m->n_near; ++b) v[b] = w[order[b]];
+    };
+    permute(ntb);
+    permute(nD);
+    permute(nnt);
+    permute(ntr);
+  }
   // Coupling work list.  The nodes of every level >= min_far are cut into boxes of NTG = 16
   // nodes (4 x 2 x 2 in 3-D, 4 x 4 in 2-D, 16 in 1-D, axis 1 longest); neighbouring
   // targets share most translation classes, so one coupling matrix fetched for a box

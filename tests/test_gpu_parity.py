@@ -113,6 +113,43 @@ def test_ragged_and_degenerate(d, n, l, eta2, R):
     _mvm_case(X, "matern12", [0.05], [0.5], 4, 7, 1e-8, l, eta2, [0.31], R=R, nugget=0.01)
 
 
+@pytest.mark.parametrize("d,n,p_s,p_theta,l,eta2,T", [(3, 2000, 5, 11, 2, (3, 1), 3), (3, 1500, 4, 7, 2, (3, 1), 1),
+                                                      (2, 1800, 9, 7, 3, (2, 1), 1)])
+def test_single_rhs_packed_coupling(d, n, p_s, p_theta, l, eta2, T):
+    """One right-hand side: the coupling packs the 16 targets of a box into the matrix-core
+    columns.  Row-tile counts Pp / 16 = 8 (with 3 parameter slots), 4 and 6 (a partial
+    last row group) against the oracle, slot by slot.  (With p_theta = 7 the 3-D p_s = 5
+    case has far classes whose truncated factors differ between the two sides' SVD
+    routines by up to 4e-7 of the instantiated coupling at l = 0.07, with equal ranks: the
+    truncation is ill-conditioned there.  That case uses the benchmark's p_theta = 11.)"""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    X = np.random.default_rng([11, d, n]).random((n, d))
+    lt, lm, om = _setup(X, "matern32", [0.05], [0.5], p_s, p_theta, 1e-8, l, eta2)
+    _check_ranks(lm, om)
+    thetas = np.linspace(0.07, 0.45, T)[:, None]
+    inst = api.Instance(lm, thetas)
+    x = inputs.normal_vectors(n, T, 13).T.reshape(T, 1, n)
+    xd = torch.tensor(np.ascontiguousarray(x if T > 1 else x[0, 0]), device="cuda")
+    y = inst.matvec(xd, nugget=0.05).cpu().numpy().reshape(T, 1, n)
+    for t in range(T):
+        ref = om.matvec(om.instantiate(thetas[t]), x[t, 0], nugget=0.05)
+        _close(y[t, 0], ref, what=f"R = 1, slot {t}")
+
+
+def test_single_rhs_fp32_error_bound():
+    """FP32 with one right-hand side (packed coupling, FP32 matrix cores): within the FP32
+    instance's 2e-6 relative bound of the FP64 oracle."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    X = inputs.points_for(2, 4096)
+    lt, lm, om = _setup(X, "matern32", [0.05], [0.5], 5, 11, 1e-8, 2, (3, 1))
+    inst = api.Instance(lm, [0.3], dtype="f32")
+    x = inputs.normal_vectors(4096, 1, 9)[:, 0]
+    y = inst.matvec(torch.tensor(x, device="cuda", dtype=torch.float32))
+    _close(y.cpu().numpy().astype(np.float64), om.matvec(om.instantiate(0.3), x), 2e-6)
+
+
 def test_polynomial_kernel_against_dense_product():
     """Exactly interpolated kernel: the GPU MVM equals the textbook dense K(theta) x."""
     torch = _torch()
