@@ -317,7 +317,8 @@ enum {
   PH_STAGE_LEAF_DOWN = 11,    /* FastBackward, leaves */
   PH_STAGE_BILINEAR = 12,     /* reduction of ph_bilinear */
   PH_STAGE_SOLVE = 13,        /* vector updates and inner products of ph_cg_solve */
-  PH_NUM_STAGES = 14
+  PH_STAGE_NEAR_GATHER = 14,  /* near field, one right-hand side: y_t += D_st^T x_s (s < t) */
+  PH_NUM_STAGES = 15
 };
 typedef struct {
   double ms[16];

@@ -53,7 +53,7 @@ class TraceStats(C.Structure):
 
 STAGES = ["theta", "far_inst", "near_inst", "perm_in", "leaf_up", "transfer_up", "coupling",
           "transfer_down", "near_mvm", "perm_out", "coupling_reduce", "leaf_down", "bilinear",
-          "solve"]
+          "solve", "near_gather"]
 
 _P = C.c_void_p
 _I32P = C.POINTER(C.c_int32)

@@ -456,14 +456,17 @@ __global__ void __launch_bounds__(NT) k_near_mvm(
     const S* __restrict__ xt, S* __restrict__ yt, const DT* __restrict__ D, const int64_t* __restrict__ nbegin,
     const int64_t* __restrict__ nend, const int64_t* __restrict__ rowptr, const int64_t* __restrict__ ntb,
     const int32_t* __restrict__ nnt, const int32_t* __restrict__ ntr, const int64_t* __restrict__ nD,
-    int32_t leaf0, int64_t n, int64_t R, int64_t N_nf) {
+    int32_t leaf0, int64_t n, int64_t R, int64_t N_nf, int xcd) {
   typedef Mfma<S> MF;
   constexpr int CH = 128;
-  // Workgroups are dealt to the 8 XCDs round robin; XCD x gets the contiguous leaf range
-  // [x q, x q + q) (q = n_leaves / 8), a compact region of space, so that the two reads of
-  // a stored block (for s and, transposed, for t) mostly meet in the same L2.
+  // Workgroups are dealt to the 8 XCDs round robin; with xcd set, XCD x gets the contiguous
+  // leaf range [x q, x q + q) (q = n_leaves / 8), a compact region of space, so that the two
+  // reads of a stored block (for s and, transposed, for t) mostly meet in the same L2.  The
+  // host sets it only when those ranges carry about equal work (uneven point sets leave it
+  // off: one XCD would get the dense region).
   const int nl = gridDim.x, q8 = nl / 8;
-  const int32_t li = (int)blockIdx.x < 8 * q8 ? (int)(blockIdx.x % 8) * q8 + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+  const int32_t li = xcd && (int)blockIdx.x < 8 * q8 ? (int)(blockIdx.x % 8) * q8 + (int)(blockIdx.x / 8)
+                                                      : (int)blockIdx.x;
   const int32_t s = leaf0 + li;
   const int r0 = blockIdx.y * RC;
   const int64_t slot = blockIdx.z;
@@ -542,6 +545,181 @@ __global__ void __launch_bounds__(NT) k_near_mvm(
         if (t1ok && rb < cn) ys[(b + c0 + rb) * R + r0 + m16] = acc1[q];
       }
     }
+  }
+}
+
+// Raw buffer load of one stored value (byte offset; BUF_OOB returns zero without touching
+// memory), so that every load of the loop below is unconditional and the compiler's wait
+// counts track the prefetched registers exactly.
+// (The offset is passed through an empty asm so that the compiler keeps one load per call
+// instead of cloning it into branches for the two offsets of a select.)
+template <typename DT>
+__device__ __forceinline__ DT bload1(__amdgpu_buffer_rsrc_t r, int off) {
+  asm volatile("" : "+v"(off));
+  if constexpr (sizeof(DT) == 8) return __builtin_bit_cast(DT, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  else if constexpr (sizeof(DT) == 4) return __builtin_bit_cast(DT, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  else return bf16{(uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)};
+}
+
+// Near field with one right-hand side, every stored block read once.  With R = 1 there is
+// no matrix product for the matrix cores, so this is plain FMA streaming: the workgroup of
+// leaf s (one per leaf and slot) walks the 4-column groups of its stored blocks D_st, t >= s;
+// wave w takes every fourth group, and lane (r = l % 16, c = l / 16) reads rows 16 p + r of
+// column 4 g + c of every 16-row panel p (one 512-byte run per panel and wave):
+//   y_s[16 p + r] += D[16 p + r][j] x_t[j]   (summed over lanes and waves at the end)
+//   z_st[j] = sum_i D[i][j] x_s[i]          (over the lane's panels, then the 16 lanes of
+//                                            its column; t > s only)
+// z goes to the pair buffer and k_near_gather adds it into y_t.  A chunk covers MP panels
+// (chosen on the host from the leaf sizes); larger leaves take several row chunks and later
+// chunks add to z (same lane, same element).
+// sum over the 16 lanes of each row of the wavefront (valid in lane 15 of the row): DPP
+// row shifts with zero fill, on the 32-bit halves of a double
+template <int SH, typename S>
+__device__ __forceinline__ S row_shr_add(S v) {
+  S u;
+  if constexpr (sizeof(S) == 8) {
+    typedef int i2 __attribute__((ext_vector_type(2)));
+    i2 h = __builtin_bit_cast(i2, v);
+    h[0] = __builtin_amdgcn_mov_dpp(h[0], 0x110 + SH, 0xf, 0xf, true);
+    h[1] = __builtin_amdgcn_mov_dpp(h[1], 0x110 + SH, 0xf, 0xf, true);
+    u = __builtin_bit_cast(S, h);
+  } else {
+    u = __builtin_bit_cast(S, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x110 + SH, 0xf, 0xf, true));
+  }
+  return v + u;
+}
+template <typename S>
+__device__ __forceinline__ S row_sum16(S v) {
+  return row_shr_add<8>(row_shr_add<4>(row_shr_add<2>(row_shr_add<1>(v))));
+}
+
+template <typename S, typename DT, int MP>
+__global__ void __launch_bounds__(NT) k_near_gemv(
+    const S* __restrict__ xt, S* __restrict__ yt, S* __restrict__ zb, const DT* __restrict__ D,
+    const int64_t* __restrict__ nbegin, const int64_t* __restrict__ nend, const int64_t* __restrict__ up_rowptr,
+    const int64_t* __restrict__ up_tb, const int32_t* __restrict__ up_nt, const int64_t* __restrict__ up_D,
+    const int64_t* __restrict__ up_z, int32_t leaf0, int64_t n, int64_t N_nf, int64_t Zt, int xcd) {
+  constexpr int SS = (int)sizeof(S), SD = (int)sizeof(DT);
+  __shared__ S ysum[4][MP * 16];
+  const int nl = gridDim.x, q8 = nl / 8;
+  const int32_t li = xcd && (int)blockIdx.x < 8 * q8 ? (int)(blockIdx.x % 8) * q8 + (int)(blockIdx.x / 8)
+                                                      : (int)blockIdx.x;
+  const int32_t s = leaf0 + li;
+  const int64_t slot = blockIdx.y;
+  const int lane = threadIdx.x % WAVE;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int r = lane & 15, cq = lane >> 4;
+  const int64_t b = nbegin[s], ns = nend[s] - b;
+  const S* xs = xt + slot * n;
+  S* ys = yt + slot * n;
+  S* zs = zb + slot * Zt;
+  // byte ranges checked on the host (below BUF_MAX_BYTES)
+  const __amdgpu_buffer_rsrc_t dr =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(D + slot * N_nf), (short)0, (int)(N_nf * SD), BUF_WORD3);
+  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)xs, (short)0, (int)(n * SS), BUF_WORD3);
+  const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc((void*)zs, (short)0, (int)(Zt * SS), BUF_WORD3);
+  const int64_t bb0 = up_rowptr[li], bb1 = up_rowptr[li + 1];
+  for (int64_t c0 = 0; c0 < ns; c0 += MP * 16) {
+    const int cn = (int)min<int64_t>(MP * 16, ns - c0);
+    const int np = (cn + 15) >> 4;
+    S xsr[MP], yacc[MP];
+#pragma unroll
+    for (int p = 0; p < MP; ++p) {
+      const int i = 16 * p + r;
+      xsr[p] = i < cn ? xs[b + c0 + i] : (S)0;
+      yacc[p] = (S)0;
+    }
+    // this wave's groups: the flattened (block, 4-column group) sequence from index `wave`
+    // in steps of 4 (wave-uniform)
+    int64_t bb = bb0;
+    int g = wave;
+    // (block indices are made visibly wave-uniform so that the metadata is read with
+    // scalar loads, which do not wait on the vector loads in flight)
+    auto settle = [&](int64_t& fb, int& fg) {
+      while (fb < bb1) {
+        const int ngr = (up_nt[__builtin_amdgcn_readfirstlane((int)fb)] + 3) >> 2;
+        if (fg < ngr) break;
+        fg -= ngr;
+        ++fb;
+      }
+      fb = __builtin_amdgcn_readfirstlane((int)fb);
+      fg = __builtin_amdgcn_readfirstlane(fg);
+    };
+    settle(bb, g);
+    S v[MP], vn[MP], xc = (S)0, xcn = (S)0;
+    auto fetch = [&](int64_t fb, int fg, S (&vo)[MP], S& xo) {
+      const bool valid = fb < bb1;
+      const int fc = __builtin_amdgcn_readfirstlane((int)(valid ? fb : bb1 - 1));
+      const int nt = up_nt[fc];
+      const int col = 4 * fg + cq;
+      const bool ok = valid && col < nt;
+      const int dbase = (int)up_D[fc] + (int)panel_index((int)c0 + r, col, nt);
+#pragma unroll
+      for (int p = 0; p < MP; ++p)
+        vo[p] = widen<S, DT>(bload1<DT>(dr, ok && p < np ? (dbase + 16 * p * nt) * SD : BUF_OOB));
+      xo = bload1<S>(xr, ok ? (int)((up_tb[fc] + col) * SS) : BUF_OOB);
+    };
+    if (bb < bb1) fetch(bb, g, v, xc);
+    while (bb < bb1) {
+      const int bu = __builtin_amdgcn_readfirstlane((int)bb);
+      const int nt = up_nt[bu];
+      const int64_t zo = up_z[bu];
+      const int col = 4 * g + cq;
+      const bool zok = zo >= 0 && col < nt;
+      // after the first chunk: the partial z of this column (issued before the prefetch)
+      const S zold = bload1<S>(zr, zok && c0 > 0 ? (int)((zo + col) * SS) : BUF_OOB);
+      g += 4;
+      settle(bb, g);
+      fetch(bb, g, vn, xcn);
+      S zacc = (S)0;
+#pragma unroll
+      for (int p = 0; p < MP; ++p) {
+        yacc[p] += v[p] * xc;
+        zacc += v[p] * xsr[p];
+      }
+      if (zo >= 0) {
+        zacc = row_sum16(zacc);
+        if (zok && r == 15) zs[zo + col] = zold + zacc;
+      }
+#pragma unroll
+      for (int p = 0; p < MP; ++p) v[p] = vn[p];
+      xc = xcn;
+    }
+    // sum y over the four columns of a lane group, then over the waves (fixed order)
+#pragma unroll
+    for (int p = 0; p < MP; ++p) {
+      S t = yacc[p];
+      t += __shfl_xor(t, 16);
+      t += __shfl_xor(t, 32);
+      if (cq == 0) ysum[wave][16 * p + r] = t;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < cn; i += NT)
+      ys[b + c0 + i] = ysum[0][i] + ysum[1][i] + ysum[2][i] + ysum[3][i];
+    __syncthreads();
+  }
+}
+
+// y_t += sum of the pair buffers z_ut (u < t) of leaf t in list order (one right-hand side),
+// one workgroup per (leaf, slot)
+template <typename S>
+__global__ void __launch_bounds__(NT) k_near_gather(S* __restrict__ yt, const S* __restrict__ zb,
+                                                    const int64_t* __restrict__ nbegin,
+                                                    const int64_t* __restrict__ nend,
+                                                    const int64_t* __restrict__ lo_rowptr,
+                                                    const int64_t* __restrict__ lo_z, int32_t leaf0, int64_t n,
+                                                    int64_t Zt) {
+  const int32_t li = blockIdx.x, s = leaf0 + li;
+  const int64_t slot = blockIdx.y;
+  const int64_t b = nbegin[s], ns = nend[s] - b;
+  const int64_t q0 = lo_rowptr[li], q1 = lo_rowptr[li + 1];
+  if (q0 == q1) return;
+  S* ys = yt + slot * n + b;
+  const S* zs = zb + slot * Zt;
+  for (int64_t i = threadIdx.x; i < ns; i += NT) {
+    S acc = ys[i];
+    for (int64_t q = q0; q < q1; ++q) acc += zs[lo_z[q] + i];
+    ys[i] = acc;
   }
 }
 
@@ -660,6 +838,14 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
   if (use_far && (m.n_nodes * m.Pp * Rs * (int64_t)sizeof(S) > BUF_MAX_BYTES ||
                   m.n_classes * m.Pp * m.Pp * (int64_t)sizeof(S) > BUF_MAX_BYTES))
     fail(PH_EUNSUPPORTED, "ph_matvec: per-slot coupling buffers exceed 2 GiB (reduce R)");
+  // the single-RHS near kernel addresses a slot's blocks, x and pair buffer with 32-bit
+  // byte offsets
+  const bool gemv_ok = m.N_nf_pad * (int64_t)in.d_esize <= BUF_MAX_BYTES &&
+                       m.n * (int64_t)sizeof(S) <= BUF_MAX_BYTES && m.Zt * (int64_t)sizeof(S) <= BUF_MAX_BYTES;
+  if (Rs == 1 && gemv_ok && m.Zt > 0 && in.zb.n == 0) {
+    if (in.graphs > 0) fail(PH_ESTATE, "ph_matvec: the instance has recorded graphs, its scratch cannot grow");
+    in.zb.alloc((size_t)T * m.Zt * sizeof(S));
+  }
   S* xt = (S*)in.xt.p;
   S* yt = (S*)in.yt.p;
   S* xh = (S*)in.xh.p;
@@ -681,10 +867,30 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     } else {
       join_near(in, st);
     }
-    launch(PH_STAGE_NEAR_MVM, k_near_mvm<S, DT>, dim3((unsigned)m.n_leaves, (unsigned)nrc, (unsigned)T), dim3(NT),
-           nst, (const S*)xt, yt, (const DT*)in.D.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
-           (const int64_t*)m.near_rowptr.p, (const int64_t*)m.near_tb.p, (const int32_t*)m.near_nt.p,
-           (const int32_t*)m.near_tr.p, (const int64_t*)m.near_D.p, leaf0, m.n, Rs, m.N_nf_pad);
+    const int xcd = m.near_xcd;
+    if (Rs == 1 && gemv_ok) {
+      // one right-hand side: every stored block read once, transposed products gathered
+      auto gemv = [&](auto kern) {
+        launch(PH_STAGE_NEAR_MVM, kern, dim3((unsigned)m.n_leaves, (unsigned)T), dim3(NT), nst, (const S*)xt, yt,
+               (S*)in.zb.p, (const DT*)in.D.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
+               (const int64_t*)m.up_rowptr.p, (const int64_t*)m.up_tb.p, (const int32_t*)m.up_nt.p,
+               (const int64_t*)m.up_D.p, (const int64_t*)m.up_z.p, leaf0, m.n, m.N_nf_pad, m.Zt, xcd);
+      };
+      int mp = m.gemv_mp;
+      if (const char* e = std::getenv("PH_GEMV_PANELS")) mp = std::atoi(e);   // tuning: 4, 8 or 12
+      if (mp <= 4) gemv(k_near_gemv<S, DT, 4>);
+      else if (mp <= 8) gemv(k_near_gemv<S, DT, 8>);
+      else gemv(k_near_gemv<S, DT, 12>);
+      launch(PH_STAGE_NEAR_GATHER, k_near_gather<S>, dim3((unsigned)m.n_leaves, (unsigned)T), dim3(NT), nst, yt,
+             (const S*)in.zb.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
+             (const int64_t*)m.lo_rowptr.p, (const int64_t*)m.lo_z.p, leaf0, m.n, m.Zt);
+    } else {
+      launch(PH_STAGE_NEAR_MVM, k_near_mvm<S, DT>, dim3((unsigned)m.n_leaves, (unsigned)nrc, (unsigned)T),
+             dim3(NT), nst, (const S*)xt, yt, (const DT*)in.D.p, (const int64_t*)m.nbegin.p,
+             (const int64_t*)m.nend.p, (const int64_t*)m.near_rowptr.p, (const int64_t*)m.near_tb.p,
+             (const int32_t*)m.near_nt.p, (const int32_t*)m.near_tr.p, (const int64_t*)m.near_D.p, leaf0, m.n, Rs,
+             m.N_nf_pad, xcd);
+    }
     if (!serial) PH_HIP(hipEventRecord(in.ev_join, in.aux));
   };
   near_field();

@@ -134,6 +134,31 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
     ntr[b] = m->D_tr_host[b];
   }
   for (int64_t i = 0; i < m->n_leaves; ++i) nrow[i + 1] += nrow[i];
+  // XCD-contiguous leaf ranges in the near MVM only when the 8 ranges carry about equal
+  // work (entries of the leaf's near blocks): within 5% of the mean
+  {
+    std::vector<double> rw(8, 0.0);
+    const int64_t q8 = m->n_leaves / 8;
+    for (int64_t b = 0; b < m->n_near && q8 > 0; ++b) {
+      const int64_t li = t.near[2 * b] - leaf0;
+      if (li < 8 * q8) rw[li / q8] += (double)t.size(t.near[2 * b]) * t.size(t.near[2 * b + 1]);
+    }
+    double mx = 0, sum = 0;
+    for (double v : rw) {
+      mx = std::max(mx, v);
+      sum += v;
+    }
+    m->near_xcd = q8 > 0 && sum > 0 && mx <= 1.05 * sum / 8 ? 1 : 0;
+  }
+  // single-RHS near MVM: the smallest row chunk (4, 8 or 12 panels) that holds 90% of the
+  // leaves in one pass
+  {
+    std::vector<int64_t> sz;
+    for (int32_t v : t.leaves) sz.push_back(t.size(v));
+    std::sort(sz.begin(), sz.end());
+    const int64_t p90 = sz.empty() ? 0 : sz[(size_t)(0.9 * (double)(sz.size() - 1))];
+    m->gemv_mp = p90 <= 64 ? 4 : (p90 <= 128 ? 8 : 12);
+  }
   // Each stored block is read twice by the near MVM: directly by the workgroup of one of
   // its leaves and transposed by that of the other.  Ordering every leaf's list by an edge
   // colouring of the near graph (one block per colour and leaf, both leaves of a block at
@@ -188,6 +213,47 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
     permute(nD);
     permute(nnt);
     permute(ntr);
+  }
+  // Single-RHS near MVM lists.  The workgroup of leaf s streams its stored blocks D_st
+  // (t >= s, canonical order) and writes z_st = D_st^T x_s (t > s) into rows
+  // [zoff, zoff + n_t) of the pair buffer; leaf t then adds the z of its blocks with s < t.
+  // (The host arrays live until the end of the upload: the copies are asynchronous.)
+  std::vector<int64_t> urow(m->n_leaves + 1, 0), lrow(m->n_leaves + 1, 0), utb, uD, uz, lz;
+  std::vector<int32_t> unt;
+  {
+    std::vector<int64_t> zoff(hm.nstore.size(), -1);
+    int64_t zt = 0;
+    for (size_t q = 0; q < hm.nstore.size(); ++q)
+      if (hm.nstore[q].s != hm.nstore[q].t) {
+        zoff[q] = zt;
+        zt += hm.nstore[q].nt;
+      }
+    m->Zt = zt;
+    for (int64_t b = 0; b < m->n_near; ++b) {
+      const int32_t s = t.near[2 * b], u = t.near[2 * b + 1];
+      const int32_t q = hm.near_src[b];
+      if (s <= u) {
+        urow[s - leaf0 + 1]++;
+        utb.push_back(t.begin[u]);
+        unt.push_back((int32_t)t.size(u));
+        uD.push_back(m->D_off_host[b]);
+        uz.push_back(zoff[q]);
+      } else {
+        lrow[s - leaf0 + 1]++;
+        lz.push_back(zoff[q]);
+      }
+    }
+    for (int64_t i = 0; i < m->n_leaves; ++i) {
+      urow[i + 1] += urow[i];
+      lrow[i + 1] += lrow[i];
+    }
+    m->up_rowptr.upload(urow.data(), urow.size(), st);
+    m->up_tb.upload(utb.data(), utb.size(), st);
+    m->up_nt.upload(unt.data(), unt.size(), st);
+    m->up_D.upload(uD.data(), uD.size(), st);
+    m->up_z.upload(uz.data(), uz.size(), st);
+    m->lo_rowptr.upload(lrow.data(), lrow.size(), st);
+    m->lo_z.upload(lz.data(), lz.size(), st);
   }
   // Coupling work list.  The nodes of every level >= min_far are cut into boxes of NTG = 16
   // nodes (4 x 2 x 2 in 3-D, 4 x 4 in 2-D, 16 in 1-D, axis 1 longest); neighbouring
@@ -315,6 +381,8 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
                               m->nstore.bytes() + m->nf_P.bytes() + m->nf_core.bytes() +
                               m->nf_theta.bytes() + m->tiles.bytes() + m->near_rowptr.bytes() +
                               m->near_tb.bytes() + m->near_D.bytes() + m->near_nt.bytes() + m->near_tr.bytes() +
+                              m->up_rowptr.bytes() + m->up_tb.bytes() + m->up_D.bytes() + m->up_z.bytes() +
+                              m->up_nt.bytes() + m->lo_rowptr.bytes() + m->lo_z.bytes() +
                               m->cstore.bytes() + m->ff_chat.bytes() + m->ff_theta.bytes() + m->grp_targets.bytes() +
                               m->grp_entry.bytes() + m->ent_cls.bytes() + m->ent_tau.bytes() +
                               m->chunk_first.bytes());

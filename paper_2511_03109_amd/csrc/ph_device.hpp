@@ -163,6 +163,15 @@ struct DeviceModel {
   DevArr<int64_t> near_rowptr;            // per leaf index
   DevArr<int64_t> near_tb, near_D;        // per canonical near block: tau begin, stored D offset
   DevArr<int32_t> near_nt, near_tr;       // per canonical near block: n_tau, stored transposed
+  // single right-hand side (read-once near MVM): per leaf s, its stored blocks D_st (t >= s,
+  // ascending t) and the pair buffers z_ut = D_ut^T x_u (u < t) that it gathers; Zt = rows
+  // of all pair buffers
+  DevArr<int64_t> up_rowptr, up_tb, up_D, up_z;   // up_z: first row of z_st (-1: t = s)
+  DevArr<int32_t> up_nt;
+  DevArr<int64_t> lo_rowptr, lo_z;
+  int64_t Zt = 0;
+  int near_xcd = 0;   // near MVM: contiguous leaf ranges per XCD (only if they balance)
+  int gemv_mp = 12;   // single-RHS near MVM: 16-row panels per row chunk (4, 8 or 12)
   DevArr<ClassDev> cstore;
   DevArr<double> ff_chat, ff_theta;       // far panels (r1 r2 of Pp x Pp per class), theta factors
   // coupling work list: target boxes of NTG nodes of one level (see coupling_groups)
@@ -189,7 +198,7 @@ struct InstData {
   DevArr<double> v;
   int64_t Rcap = 0;
   int Gcap = 0;
-  DevArr<char> xt, yt, xh, yh, part;
+  DevArr<char> xt, yt, xh, yh, part, zb;   // zb: [T][Zt] near-field pair buffers (R = 1)
   DevArr<char> bil;                   // ph_bilinear: K~ x
   DevArr<double> bil_part;            // ph_bilinear: per-block partial sums
   hipStream_t aux = nullptr;          // second stream: near field concurrent with the far chain
