@@ -234,12 +234,14 @@ __global__ void __launch_bounds__(NT) k_transfer_down(S* __restrict__ yh, const 
 // sources) is wave-uniform and read with scalar loads.  Waves form a WR x (NW / WR) grid:
 // wave (wr, wt) owns row tiles wr + WR j (j < TPW) of targets wt NTW .. wt NTW + NTW - 1;
 // FULL: the row tiles are exactly Pp / 16 (no tile test).
+// HB: the box is split into HB parts of NTG / HB targets, one workgroup each (the C panel
+// is staged by every part).
 // PACK (one right-hand side): the 16 targets of the box are the 16 matrix-core columns,
 // B[k][c] = x_hat of target c's source for the entry's class (zero if c does not use it),
 // so a stage multiplies one C panel by one 16-column tile instead of 16 tiles of which 15
 // columns would be padding.  Requires the unpadded single-RHS layout (Rs = 1, r0 = 0).
-template <typename S, int NW, int WR, int TPW, int PD, bool FULL, bool PACK = false>
-__global__ void __launch_bounds__(NW * 64) k_coupling(
+template <typename S, int NW, int WR, int TPW, int PD, bool FULL, bool PACK = false, int HB = 1>
+__global__ void __launch_bounds__(NW * 64, HB) k_coupling(
     const S* __restrict__ xh, S* __restrict__ out, const S* __restrict__ C,
     const int32_t* __restrict__ grp_targets, const int32_t* __restrict__ grp_entry,
     const int32_t* __restrict__ ent_cls, const int32_t* __restrict__ ent_tau,
@@ -248,14 +250,14 @@ __global__ void __launch_bounds__(NW * 64) k_coupling(
   typedef Tile16<S> MF;
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
   constexpr int NTH = NW * 64;
-  constexpr int NB = PACK ? 1 : NTG;            // 16-column B tiles per box
+  constexpr int NB = PACK ? 1 : NTG / HB;       // 16-column B tiles per workgroup (HB parts per box)
   constexpr int WT = NW / WR, NTW = NB / WT, MT = WR * TPW;
   constexpr int KC = 16;                        // K rows per stage
   constexpr int EPU = 16 / (int)sizeof(S);      // elements per 16-byte unit
   constexpr int AU = (MT * 256 / EPU + NTH - 1) / NTH;   // C units per thread per stage
-  constexpr int TSW = PACK ? 1 : NTG / NW;      // targets staged per wave
+  constexpr int TSW = PACK ? 1 : NB / NW;       // targets staged per wave
   constexpr int BUT = 256 / EPU / 64;           // x_hat units per lane per target
-  static_assert(NB % WT == 0 && (PACK || NTG % NW == 0) && BUT >= 1, "work split");
+  static_assert(NB % WT == 0 && (PACK || NB % NW == 0) && BUT >= 1 && (!PACK || HB == 1), "work split");
   static_assert(!PACK || (WT == 1 && NTH >= 256), "packed mode: one column tile, 256 B loaders");
   __shared__ __attribute__((aligned(16))) S As[2][MT * 256];
   __shared__ __attribute__((aligned(16))) S Bs[2][NB][256];
@@ -263,8 +265,10 @@ __global__ void __launch_bounds__(NW * 64) k_coupling(
   // every slot of a box is dispatched before the next box, so the long workgroups start first
   const int g = blockIdx.x;
   const int64_t slot = blockIdx.y;
-  const int grp = blockIdx.z % n_groups;
-  const int r0 = (blockIdx.z / n_groups) * RC;
+  const int zb = blockIdx.z / HB;
+  const int toff = (int)(blockIdx.z % HB) * NB;   // first target of this part of the box
+  const int grp = zb % n_groups;
+  const int r0 = (zb / n_groups) * RC;
   const int lane = threadIdx.x % WAVE;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int wr = wave % WR, wt = wave / WR;
@@ -318,7 +322,7 @@ __global__ void __launch_bounds__(NW * 64) k_coupling(
     } else {
 #pragma unroll
       for (int q = 0; q < TSW; ++q) {
-        const int tv = ent_tau[e * NTG + wave * TSW + q];
+        const int tv = ent_tau[e * NTG + toff + wave * TSW + q];
         const int base = ((tv * Pp + kc * KC) * (int)Rs + r0) * (int)sizeof(S);
 #pragma unroll
         for (int h = 0; h < BUT; ++h) {
@@ -355,7 +359,7 @@ __global__ void __launch_bounds__(NW * 64) k_coupling(
     const int e = ea + st / nk;
     bool use[NTW];
 #pragma unroll
-    for (int s = 0; s < NTW; ++s) use[s] = PACK || ent_tau[e * NTG + wt * NTW + s] >= 0;
+    for (int s = 0; s < NTW; ++s) use[s] = PACK || ent_tau[e * NTG + toff + wt * NTW + s] >= 0;
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       const int k = kk + (lane >> 4);
@@ -412,7 +416,7 @@ __global__ void __launch_bounds__(NW * 64) k_coupling(
   }
 #pragma unroll
   for (int s = 0; s < NTW; ++s) {
-    const int32_t node = grp_targets[grp * NTG + wt * NTW + s];
+    const int32_t node = grp_targets[grp * NTG + toff + wt * NTW + s];
     if (node < 0) continue;
     S* on = o + (int64_t)node * Pp * Rs + r0 + (lane & 15);
 #pragma unroll
@@ -907,9 +911,16 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     const int64_t part_stride = T * m.n_nodes * m.Pp * Rs;
     const bool pack = Rs == 1;   // packed coupling (box targets as matrix-core columns)
     S* cout = G > 1 ? (S*)in.part.p : yh;
-    if (T > 65535 || m.n_groups * nrc > 65535)
+    // Pp = 128: each box in two halves of 8 targets (4 waves, 64 KB of LDS), so two
+    // workgroups share a CU and their stage barriers fall at different times; one
+    // workgroup per box: 5.54 ms, halves: 5.28 ms on the benchmark (PH_COUPLING_HALF=0
+    // selects whole boxes; quarters measured 5.4-5.6 ms)
+    int hb = 2;
+    if (const char* env = std::getenv("PH_COUPLING_HALF")) hb = std::atoi(env) == 0 ? 1 : 2;
+    if (pack || m.Pp / 16 != 8) hb = 1;
+    if (T > 65535 || m.n_groups * nrc * hb > 65535)
       fail(PH_EUNSUPPORTED, "ph_matvec: too many parameter slots or target boxes x RHS tiles for one launch");
-    dim3 cg((unsigned)G, (unsigned)T, (unsigned)(m.n_groups * nrc));
+    dim3 cg((unsigned)G, (unsigned)T, (unsigned)(m.n_groups * nrc * hb));
     auto run = [&](auto kern, int nw) {
       launch(PH_STAGE_COUPLING, kern, cg, dim3(64 * nw), st, (const S*)xh, cout, (const S*)in.C.p,
              (const int32_t*)m.grp_targets.p, (const int32_t*)m.grp_entry.p, (const int32_t*)m.ent_cls.p,
@@ -933,6 +944,9 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
       } else {
         run(k_coupling<S, 4, 4, 1, 1, false, true>, 4);
       }
+    } else if (nMt == 8 && hb == 2) {
+      if (pd == 2) run(k_coupling<S, 4, 4, 2, 2, true, false, 2>, 4);
+      else run(k_coupling<S, 4, 4, 2, 1, true, false, 2>, 4);
     } else if (nMt == 8) {
       if (pd == 2) run(k_coupling<S, 8, 4, 2, 2, true>, 8);
       else run(k_coupling<S, 8, 4, 2, 1, true>, 8);
