@@ -816,8 +816,15 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
   // PH_COUPLING_CHUNKS overrides (tuning)
   // launch configuration: environment override (tuning sweeps), else ph_autotune's
   // choice, else the heuristic (8 chunks, prefetch 1, near field overlapped)
-  int G = 1;   // a power of two <= 64
-  if (use_far && m.n_groups > 0) G = m.max_group_entries >= 16 ? 8 : (m.max_group_entries >= 4 ? 2 : 1);
+  // Pp = 128: each box in two halves of 8 targets (4 waves, 64 KB of LDS), so two
+  // workgroups share a CU and their stage barriers fall at different times; one
+  // workgroup per box: 5.54 ms, halves: 5.28 ms on the benchmark (PH_COUPLING_HALF=0
+  // selects whole boxes; quarters measured 5.4-5.6 ms)
+  int hb = 2;
+  if (const char* env = std::getenv("PH_COUPLING_HALF")) hb = std::atoi(env) == 0 ? 1 : 2;
+  if (Rs == 1 || m.Pp / 16 != 8) hb = 1;
+  int G = 1;   // a power of two <= 64 (half boxes double the workgroups: 4 chunks)
+  if (use_far && m.n_groups > 0) G = m.max_group_entries >= 16 ? 8 / hb : (m.max_group_entries >= 4 ? 2 : 1);
   if (in.tune_chunks > 0) G = in.tune_chunks;
   if (const char* env = std::getenv("PH_COUPLING_CHUNKS")) {
     const int g = std::atoi(env);
@@ -911,13 +918,6 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     const int64_t part_stride = T * m.n_nodes * m.Pp * Rs;
     const bool pack = Rs == 1;   // packed coupling (box targets as matrix-core columns)
     S* cout = G > 1 ? (S*)in.part.p : yh;
-    // Pp = 128: each box in two halves of 8 targets (4 waves, 64 KB of LDS), so two
-    // workgroups share a CU and their stage barriers fall at different times; one
-    // workgroup per box: 5.54 ms, halves: 5.28 ms on the benchmark (PH_COUPLING_HALF=0
-    // selects whole boxes; quarters measured 5.4-5.6 ms)
-    int hb = 2;
-    if (const char* env = std::getenv("PH_COUPLING_HALF")) hb = std::atoi(env) == 0 ? 1 : 2;
-    if (pack || m.Pp / 16 != 8) hb = 1;
     if (T > 65535 || m.n_groups * nrc * hb > 65535)
       fail(PH_EUNSUPPORTED, "ph_matvec: too many parameter slots or target boxes x RHS tiles for one launch");
     dim3 cg((unsigned)G, (unsigned)T, (unsigned)(m.n_groups * nrc * hb));
@@ -929,7 +929,8 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     };
     // 8 waves (4 row groups x 2 target halves) for Pp > 64, else 4 waves over the targets;
     // register prefetch depth 2 (PH_COUPLING_PD or the autotuner may select 1)
-    int pd = in.tune_prefetch == 1 ? 1 : 2;
+    // (half boxes: depth 1 measured 0.5% faster)
+    int pd = in.tune_prefetch > 0 ? in.tune_prefetch : (hb == 2 ? 1 : 2);
     if (const char* env = std::getenv("PH_COUPLING_PD")) pd = std::atoi(env) == 2 ? 2 : 1;
     const int nMt = m.Pp / 16;
     if (pack) {
