@@ -46,13 +46,14 @@ __global__ void k_theta_vectors(const double* __restrict__ theta, ThetaBox box, 
   }
 }
 
-// Far field, one workgroup per (16 x 16 tile of the Pp x Pp coupling, stored class), all
-// slots:  w_k = Theta_k^T v_k(theta_t);  C_t = sum_q w_1[k_1] w_2[k_2] Chat_q  (Sec. 4.2,
-// C = L H(theta) R^T with H linear in the weights, the panels L G_q R^T formed offline).
-// C is in fragment order, where a 16 x 16 tile is 256 contiguous entries, so thread p
-// reads and writes entry p of the tile; the mirrored class receives C^T (entry (k, m) of
-// the transposed tile).
-template <typename S>
+// Far field, one workgroup per (FT consecutive 16 x 16 tiles of the Pp x Pp coupling, stored
+// class), all slots:  w_k = Theta_k^T v_k(theta_t);  C_t = sum_q w_1[k_1] w_2[k_2] Chat_q
+// (Sec. 4.2, C = L H(theta) R^T with H linear in the weights, the panels L G_q R^T formed
+// offline).  C is in fragment order, where a 16 x 16 tile is 256 contiguous entries, so
+// thread p reads and writes entry p of each of its tiles; the mirrored class receives C^T
+// (entry (k, m) of the transposed tile).  The weights are formed once per workgroup and
+// the FT tiles' panel loads of each q are in flight together.
+template <typename S, int FT>
 __global__ void __launch_bounds__(NT) k_far_instantiate(const ClassDev* __restrict__ cls,
                                                         const double* __restrict__ chat,
                                                         const double* __restrict__ th, const double* __restrict__ v,
@@ -60,15 +61,22 @@ __global__ void __launch_bounds__(NT) k_far_instantiate(const ClassDev* __restri
                                                         int dth) {
   __shared__ double w1[TC][16], w2[TC][16];
   const ClassDev c = cls[blockIdx.y];
-  const int nMt = Pp / 16;
-  const int mt = blockIdx.x % nMt, kc = blockIdx.x / nMt;
+  const int nMt = Pp / 16, ntiles = nMt * nMt;
   const int pos = threadIdx.x;                                   // entry of the tile
   const int kl = pos >> 4, ml = (pos & 3) * 4 + ((pos & 15) >> 2);
-  const int m = mt * 16 + ml, k = kc * 16 + kl;
-  const int64_t at = (int64_t)kc * Pp * 16 + mt * 256 + pos;    // = frag_index(m, k)
-  const int64_t mirror_at = frag_index(k, m, Pp);
+  int64_t at[FT], mirror_at[FT];
+  bool ok[FT];
+#pragma unroll
+  for (int u = 0; u < FT; ++u) {
+    const int tile = blockIdx.x * FT + u;
+    ok[u] = tile < ntiles;
+    const int mt = tile % nMt, kc = tile / nMt;
+    const int m = mt * 16 + ml, k = kc * 16 + kl;
+    at[u] = (int64_t)kc * Pp * 16 + mt * 256 + pos;              // = frag_index(m, k)
+    mirror_at[u] = frag_index(k, m, Pp);
+  }
   const int rq = c.r1 * c.r2;
-  const double* cp = chat + c.chat_off + at;
+  const double* cp = chat + c.chat_off;
   for (int t0 = 0; t0 < T; t0 += TC) {
     const int tc = min(TC, T - t0);
     __syncthreads();
@@ -90,21 +98,33 @@ __global__ void __launch_bounds__(NT) k_far_instantiate(const ClassDev* __restri
       w2[tt][a] = s;
     }
     __syncthreads();
-    double acc[TC];
+    double acc[FT][TC];
 #pragma unroll
-    for (int tt = 0; tt < TC; ++tt) acc[tt] = 0.0;
+    for (int u = 0; u < FT; ++u)
+#pragma unroll
+      for (int tt = 0; tt < TC; ++tt) acc[u][tt] = 0.0;
     for (int q = 0; q < rq; ++q) {
-      const double pv = cp[(int64_t)q * Pp * Pp];
+      double pv[FT];
+#pragma unroll
+      for (int u = 0; u < FT; ++u) pv[u] = ok[u] ? cp[(int64_t)q * Pp * Pp + at[u]] : 0.0;
       const int k1 = q % c.r1, k2 = q / c.r1;
 #pragma unroll
-      for (int tt = 0; tt < TC; ++tt) acc[tt] += pv * (w1[tt][k1] * w2[tt][k2]);
+      for (int tt = 0; tt < TC; ++tt) {
+        const double w = w1[tt][k1] * w2[tt][k2];
+#pragma unroll
+        for (int u = 0; u < FT; ++u) acc[u][tt] += pv[u] * w;
+      }
     }
 #pragma unroll
     for (int tt = 0; tt < TC; ++tt) {
       if (tt >= tc) break;
       S* Ct = C + (size_t)(t0 + tt) * C_per_slot;
-      Ct[c.C_off + at] = (S)acc[tt];
-      if (c.Cm_off >= 0) Ct[c.Cm_off + mirror_at] = (S)acc[tt];
+#pragma unroll
+      for (int u = 0; u < FT; ++u) {
+        if (!ok[u]) continue;
+        Ct[c.C_off + at[u]] = (S)acc[u][tt];
+        if (c.Cm_off >= 0) Ct[c.Cm_off + mirror_at[u]] = (S)acc[u][tt];
+      }
     }
   }
 }
@@ -234,9 +254,12 @@ void instantiate_impl(InstData& in, const double* theta, hipStream_t st) {
          box, in.v.p, in.T, m.d_theta, m.p_theta, in.grad_dim);
   const int64_t Cps = m.n_classes * m.Pp * m.Pp;
   const int nMt = m.Pp / 16;
-  launch(PH_STAGE_FAR_INST, k_far_instantiate<S>, dim3((unsigned)(nMt * nMt), (unsigned)m.n_stored_cls), dim3(NT), st,
-         (const ClassDev*)m.cstore.p, (const double*)m.ff_chat.p, (const double*)m.ff_theta.p,
-         (const double*)in.v.p, (S*)in.C.p, Cps, m.Pp, in.T, m.p_theta, m.d_theta);
+  {
+    constexpr int FT = 4;
+    launch(PH_STAGE_FAR_INST, k_far_instantiate<S, FT>, dim3((unsigned)((nMt * nMt + FT - 1) / FT),
+           (unsigned)m.n_stored_cls), dim3(NT), st, (const ClassDev*)m.cstore.p, (const double*)m.ff_chat.p,
+           (const double*)m.ff_theta.p, (const double*)in.v.p, (S*)in.C.p, Cps, m.Pp, in.T, m.p_theta, m.d_theta);
+  }
   // The near-field blocks (HBM-bound, the bulk of the instantiation) are written on the
   // instance's second stream: they overlap the far-field panels here and, in a following
   // ph_matvec, the upward pass and the coupling; the near-field MVM runs on the same
