@@ -107,8 +107,12 @@ def test_3d_matern_small():
 
 @pytest.mark.parametrize("d,n,l,eta2,R", [(1, 777, 5, (1, 1), 3), (2, 1500, 3, (2, 1), 5),
                                            (3, 1100, 2, (3, 1), 2), (2, 300, 0, (2, 1), 2),
-                                           (2, 37, 2, (2, 1), 1)])
+                                           (2, 37, 2, (2, 1), 1), (2, 3000, 1, (2, 1), 1),
+                                           (2, 4000, 2, (2, 1), 1), (2, 1600, 2, (2, 1), 1)])
 def test_ragged_and_degenerate(d, n, l, eta2, R):
+    """Ragged and degenerate trees.  The single-RHS cases with leaves of 750, 250 and 100
+    points run the read-once near kernel with several row chunks (later chunks add to the
+    pair buffers) and with 8-panel chunks."""
     X = np.random.default_rng([5, d, n]).random((n, d))
     _mvm_case(X, "matern12", [0.05], [0.5], 4, 7, 1e-8, l, eta2, [0.31], R=R, nugget=0.01)
 
@@ -470,6 +474,40 @@ def test_autotune_and_graph_replays():
     del g
     inst.matvec(xb)
     torch.cuda.synchronize()
+
+
+def test_single_rhs_graph_replays():
+    """One right-hand side inside a recorded graph (packed coupling, read-once near field and
+    its gather, T = 2 slots, after the instance ran with 16 right-hand sides): every replay
+    equals the eager result bit for bit and matches the oracle."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    n, T = 2500, 2
+    X = inputs.points_for(4, n)
+    lt, lm, om = _setup(X, "gaussian", [0.05], [0.5], 6, 9, 1e-8, 3, (2, 1))
+    rng = np.random.default_rng(21)
+    inst = api.Instance(lm, rng.uniform(0.05, 0.5, (T, 1)))
+    wide = torch.tensor(np.ascontiguousarray(inputs.normal_vectors(n, T * 16, 5).T.reshape(T, 16, n)), device="cuda")
+    inst.matvec(wide)
+    x = torch.tensor(np.ascontiguousarray(inputs.normal_vectors(n, T, 6).T.reshape(T, 1, n)), device="cuda")
+    y = torch.empty_like(x)
+    s = torch.cuda.Stream()
+    g = inst.record(x, y, stream=s)
+    ref = torch.empty_like(x)
+    for rep in range(3):
+        th = rng.uniform(0.05, 0.5, (T, 1))
+        g.launch(th)
+        s.synchronize()
+        got = y.clone()
+        inst.reinstantiate(th)
+        inst.matvec(x, ref)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), f"replay {rep}"
+        if rep == 2:
+            xs = x.cpu().numpy()
+            for t in range(T):
+                _close(got[t, 0].cpu().numpy(), om.matvec(om.instantiate(th[t]), xs[t, 0]), what=f"R = 1 graph slot {t}")
+    del g
 
 
 def test_nine_slots_twenty_rhs_and_tuned_config():
