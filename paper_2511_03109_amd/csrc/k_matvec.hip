@@ -43,6 +43,67 @@ __global__ void k_perm_out(S* __restrict__ y, const S* __restrict__ yt, const S*
   }
 }
 
+// The same two permutations for Rs >= 16, through an LDS tile of 64 points x 16 right-hand
+// sides: the user's rows x[slot][r][j0 .. j0 + 63] are read and y's written as 512-byte
+// runs, and each point's 16 values in tree order (iperm[j] = tree position of point j) as
+// one 128-byte run, instead of 8-byte accesses scattered by the permutation.
+template <typename S>
+__global__ void __launch_bounds__(NT) k_perm_in_tile(const S* __restrict__ x, S* __restrict__ xt,
+                                                     const int64_t* __restrict__ iperm, int64_t n, int64_t R,
+                                                     int64_t Rs) {
+  __shared__ S tile[16][65];
+  const int64_t j0 = (int64_t)blockIdx.x * 64, slot = blockIdx.z;
+  const int r0 = blockIdx.y * RC;
+  const int jj = threadIdx.x & 63, rq = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = rq * 4 + k;
+    const int64_t j = j0 + jj;
+    tile[r][jj] = (j < n && r0 + r < R) ? x[(slot * R + r0 + r) * n + j] : (S)0;
+  }
+  __syncthreads();
+  const int rr = threadIdx.x & 15, jq = threadIdx.x >> 4;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int jl = jq * 4 + k;
+    const int64_t j = j0 + jl;
+    if (j < n) xt[(slot * n + iperm[j]) * Rs + r0 + rr] = tile[rr][jl];
+  }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(NT) k_perm_out_tile(S* __restrict__ y, const S* __restrict__ yt,
+                                                      const S* __restrict__ xt, const int64_t* __restrict__ iperm,
+                                                      int64_t n, int64_t R, int64_t Rs, double alpha, double beta,
+                                                      double nugget) {
+  __shared__ double tile[16][65];
+  const int64_t j0 = (int64_t)blockIdx.x * 64, slot = blockIdx.z;
+  const int r0 = blockIdx.y * RC;
+  const int rr = threadIdx.x & 15, jq = threadIdx.x >> 4;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int jl = jq * 4 + k;
+    const int64_t j = j0 + jl;
+    if (j < n) {
+      const int64_t src = (slot * n + iperm[j]) * Rs + r0 + rr;
+      tile[rr][jl] = alpha * ((double)yt[src] + nugget * (double)xt[src]);
+    }
+  }
+  __syncthreads();
+  const int jj = threadIdx.x & 63, rq = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = rq * 4 + k;
+    const int64_t j = j0 + jj;
+    if (j < n && r0 + r < R) {
+      S* d = y + (slot * R + r0 + r) * n + j;
+      double val = tile[r][jj];
+      if (beta != 0.0) val += beta * (double)*d;
+      *d = (S)val;
+    }
+  }
+}
+
 // FastForward, leaves: x_hat_s = U_s^T x_s on the matrix cores.  M = i (Chebyshev
 // multi-index, Pp rows), K = points of the leaf, N = 16 right-hand sides.
 // U_s[pt, i] = prod_k U_k[pt][i_k] is formed on the fly from the factor rows in LDS.
@@ -864,8 +925,12 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
   const int32_t leaf0 = t.leaves.front();
   const int64_t Cps = m.n_classes * m.Pp * m.Pp;
   const int64_t total_in = T * m.n * Rs;
-  launch(PH_STAGE_PERM_IN, k_perm_in<S>, dim3((unsigned)grid_for(total_in)), dim3(NT), st, x, xt,
-         (const int64_t*)m.perm.p, m.n, R, Rs, total_in);
+  const dim3 ptile((unsigned)((m.n + 63) / 64), (unsigned)nrc, (unsigned)T);
+  if (Rs >= RC)
+    launch(PH_STAGE_PERM_IN, k_perm_in_tile<S>, ptile, dim3(NT), st, x, xt, (const int64_t*)m.iperm.p, m.n, R, Rs);
+  else
+    launch(PH_STAGE_PERM_IN, k_perm_in<S>, dim3((unsigned)grid_for(total_in)), dim3(NT), st, x, xt,
+           (const int64_t*)m.perm.p, m.n, R, Rs, total_in);
   // The near field (HBM-bound) runs on the instance's second stream, concurrently with
   // the far-field chain (matrix-core bound) on the caller's stream.  (Forking it after
   // the upward pass instead measured slower: it then overlaps the coupling throughout.)
@@ -982,8 +1047,12 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
            dim3(NT), st, yt, (const S*)yh, (const double*)m.U.p, (const int64_t*)m.nbegin.p,
            (const int64_t*)m.nend.p, leaf0, m.d, m.p_s, m.P, m.Pp, m.n, m.n_nodes, Rs);
   const int64_t total_out = T * m.n * R;
-  launch(PH_STAGE_PERM_OUT, k_perm_out<S>, dim3((unsigned)grid_for(total_out)), dim3(NT), st, y, (const S*)yt,
-         (const S*)xt, (const int64_t*)m.perm.p, m.n, R, Rs, total_out, alpha, beta, nugget);
+  if (Rs >= RC)
+    launch(PH_STAGE_PERM_OUT, k_perm_out_tile<S>, ptile, dim3(NT), st, y, (const S*)yt, (const S*)xt,
+           (const int64_t*)m.iperm.p, m.n, R, Rs, alpha, beta, nugget);
+  else
+    launch(PH_STAGE_PERM_OUT, k_perm_out<S>, dim3((unsigned)grid_for(total_out)), dim3(NT), st, y, (const S*)yt,
+           (const S*)xt, (const int64_t*)m.perm.p, m.n, R, Rs, total_out, alpha, beta, nugget);
 }
 
 // Bilinear form, first pass: part[t][b] = sum over the elements e = b, b + NB, ... of

@@ -334,6 +334,9 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   m->U.upload(hm.U.data(), hm.U.size(), st);
   m->E.upload(hm.E.data(), hm.E.size(), st);
   m->perm.upload(t.perm.data(), t.perm.size(), st);
+  std::vector<int64_t> ip(t.perm.size());
+  for (size_t i = 0; i < t.perm.size(); ++i) ip[(size_t)t.perm[i]] = (int64_t)i;
+  m->iperm.upload(ip.data(), ip.size(), st);
   m->first_child.upload(t.first_child.data(), t.first_child.size(), st);
   m->nchild.upload(t.nchild.data(), t.nchild.size(), st);
   m->cid.upload(t.cid.data(), t.cid.size(), st);
@@ -377,7 +380,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   m->chunk_first.upload(cfirst.data(), cfirst.size(), st);
   PH_HIP(hipStreamSynchronize(st));  // host staging buffers die with this call
   m->device_bytes = (int64_t)(m->U.bytes() + m->E.bytes() + m->perm.bytes() + m->first_child.bytes() +
-                              m->nchild.bytes() + m->cid.bytes() + m->parent.bytes() + m->nbegin.bytes() + m->nend.bytes() +
+                              m->iperm.bytes() + m->nchild.bytes() + m->cid.bytes() + m->parent.bytes() + m->nbegin.bytes() + m->nend.bytes() +
                               m->nstore.bytes() + m->nf_P.bytes() + m->nf_core.bytes() +
                               m->nf_theta.bytes() + m->tiles.bytes() + m->near_rowptr.bytes() +
                               m->near_tb.bytes() + m->near_D.bytes() + m->near_nt.bytes() + m->near_tr.bytes() +

@@ -154,7 +154,7 @@ struct DeviceModel {
   std::vector<int32_t> D_tr_host;         // per canonical near block: 1 if stored as its transpose
   // device arrays
   DevArr<double> U, E;
-  DevArr<int64_t> perm;
+  DevArr<int64_t> perm, iperm;            // tree position -> point, point -> tree position
   DevArr<int32_t> first_child, nchild, cid, parent;
   DevArr<int64_t> nbegin, nend;
   DevArr<NearDev> nstore;
