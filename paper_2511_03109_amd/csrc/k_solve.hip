@@ -4,6 +4,7 @@
 // correction d solves (K~_lo + nugget I) d = r approximately with CG on an FP32 / BF16
 // instance of the same theta.  Vector updates and inner products are HIP kernels; the
 // inner products use the fixed-order two-pass reduction, so a solve is reproducible.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -57,6 +58,50 @@ __global__ void k_xpby(S* __restrict__ p, const S* __restrict__ r, double beta, 
 }
 
 // dst = (D) src * scale
+// CG scalars on the device, sc = {rr, pq, rr_new, alpha, beta, stop, active, iterations}:
+// the vector kernels read alpha / beta from sc and do nothing once `active` is 0 (converged
+// or lost positive definiteness), so iterations are launched in batches without a host
+// round trip per inner product.
+enum { SC_RR, SC_PQ, SC_RRN, SC_ALPHA, SC_BETA, SC_STOP, SC_ACTIVE, SC_IT, SC_N };
+
+__global__ void k_cg_alpha(double* sc) {
+  if (threadIdx.x != 0 || sc[SC_ACTIVE] == 0.0) return;
+  const double pq = sc[SC_PQ];
+  if (!(pq > 0)) {   // loss of positive definiteness in the low precision: stop
+    sc[SC_ACTIVE] = 0.0;
+    return;
+  }
+  sc[SC_ALPHA] = sc[SC_RR] / pq;
+}
+
+__global__ void k_cg_beta(double* sc) {
+  if (threadIdx.x != 0 || sc[SC_ACTIVE] == 0.0) return;
+  const double rn = sc[SC_RRN];
+  sc[SC_BETA] = rn / sc[SC_RR];
+  sc[SC_RR] = rn;
+  sc[SC_IT] += 1.0;
+  if (!(rn > sc[SC_STOP])) sc[SC_ACTIVE] = 0.0;   // converged (p is not needed any more)
+}
+
+// y += sign alpha x (alpha from sc) while active
+template <typename S>
+__global__ void k_axpy_dev(S* __restrict__ y, const S* __restrict__ x, const double* __restrict__ sc, double sign,
+                           int64_t n) {
+  if (sc[SC_ACTIVE] == 0.0) return;
+  const double a = sign * sc[SC_ALPHA];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (S)((double)y[i] + a * (double)x[i]);
+}
+
+// p = r + beta p (beta from sc) while active
+template <typename S>
+__global__ void k_xpby_dev(S* __restrict__ p, const S* __restrict__ r, const double* __restrict__ sc, int64_t n) {
+  if (sc[SC_ACTIVE] == 0.0) return;
+  const double b = sc[SC_BETA];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (S)((double)r[i] + b * (double)p[i]);
+}
+
 template <typename D, typename S>
 __global__ void k_convert(D* __restrict__ dst, const S* __restrict__ src, double scale, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -68,12 +113,19 @@ namespace {
 struct Solver {
   hipStream_t st;
   int64_t n;
-  DevArr<double> part, dots;
-  double* host = nullptr;   // pinned, 1 double
+  DevArr<double> part, dots, sc;
+  double* host = nullptr;   // pinned, SC_N doubles
   Solver(hipStream_t s, int64_t n_) : st(s), n(n_) {
     part.alloc(DOT_BLOCKS);
     dots.alloc(1);
-    PH_HIP(hipHostMalloc((void**)&host, sizeof(double), hipHostMallocDefault));
+    sc.alloc(SC_N);
+    PH_HIP(hipHostMalloc((void**)&host, SC_N * sizeof(double), hipHostMallocDefault));
+  }
+  // inner product into a device scalar, no host round trip
+  template <typename S>
+  void dot_dev(const S* u, const S* v, double* out) {
+    launch(PH_STAGE_SOLVE, k_vdot_partial<S>, dim3(DOT_BLOCKS), dim3(NT), st, u, v, part.p, n);
+    launch(PH_STAGE_SOLVE, k_vdot_final, dim3(1), dim3(NT), st, (const double*)part.p, out);
   }
   ~Solver() {
     if (host) (void)hipHostFree(host);
@@ -121,23 +173,41 @@ int cg(Solver& sv, InstData& in, const S* b, S* x, S* r, S* p, S* q, double nugg
   PH_HIP(hipMemcpyAsync(r, b, n * sizeof(S), hipMemcpyDeviceToDevice, sv.st));
   PH_HIP(hipMemcpyAsync(p, b, n * sizeof(S), hipMemcpyDeviceToDevice, sv.st));
   const double bb = sv.dot(b, b);
-  double rr = bb;
   const double stop = rtol * rtol * bb;
-  int it = 0;
-  while (it < maxit && rr > stop && bb > 0) {
-    apply<S>(in, p, q, nugget, sv.st);
-    const double pq = sv.dot(p, q);
-    if (!(pq > 0)) break;   // loss of positive definiteness in the low precision: stop
-    const double alpha = rr / pq;
-    sv.axpy(x, p, alpha);
-    sv.axpy(r, q, -alpha);
-    const double rr_new = sv.dot(r, r);
-    sv.xpby(p, r, rr_new / rr);
-    rr = rr_new;
-    ++it;
+  const double h[SC_N] = {bb, 0, 0, 0, 0, stop, (bb > 0 && bb > stop && maxit > 0) ? 1.0 : 0.0, 0};
+  std::copy(h, h + SC_N, sv.host);   // pinned staging (the stream was synchronised by dot)
+  PH_HIP(hipMemcpyAsync(sv.sc.p, sv.host, SC_N * sizeof(double), hipMemcpyHostToDevice, sv.st));
+  double* sc = sv.sc.p;
+  const unsigned gv = (unsigned)grid_for(n);
+  // batches of CHK iterations between host checks; iterations after convergence are no-ops
+  // (at most CHK - 1 products are wasted)
+  constexpr int CHK = 8;
+  int launched = 0;
+  bool active = h[SC_ACTIVE] != 0.0;
+  while (active && launched < maxit) {
+    const int nb = std::min(CHK, maxit - launched);
+    for (int k = 0; k < nb; ++k) {
+      apply<S>(in, p, q, nugget, sv.st);
+      sv.dot_dev(p, q, sc + SC_PQ);
+      launch(PH_STAGE_SOLVE, k_cg_alpha, dim3(1), dim3(64), sv.st, sc);
+      launch(PH_STAGE_SOLVE, k_axpy_dev<S>, dim3(gv), dim3(NT), sv.st, x, (const S*)p, (const double*)sc, 1.0, n);
+      launch(PH_STAGE_SOLVE, k_axpy_dev<S>, dim3(gv), dim3(NT), sv.st, r, (const S*)q, (const double*)sc, -1.0, n);
+      sv.dot_dev(r, r, sc + SC_RRN);
+      launch(PH_STAGE_SOLVE, k_cg_beta, dim3(1), dim3(64), sv.st, sc);
+      launch(PH_STAGE_SOLVE, k_xpby_dev<S>, dim3(gv), dim3(NT), sv.st, p, (const S*)r, (const double*)sc, n);
+    }
+    launched += nb;
+    PH_HIP(hipMemcpyAsync(sv.host, sc, SC_N * sizeof(double), hipMemcpyDeviceToHost, sv.st));
+    PH_HIP(hipStreamSynchronize(sv.st));
+    active = sv.host[SC_ACTIVE] != 0.0;
   }
+  if (launched == 0) {
+    sv.host[SC_RR] = bb;
+    sv.host[SC_IT] = 0;
+  }
+  const double rr = sv.host[SC_RR];
   if (rel_out) *rel_out = bb > 0 ? std::sqrt(rr / bb) : 0.0;
-  return it;
+  return (int)sv.host[SC_IT];
 }
 
 }  // namespace
