@@ -170,14 +170,28 @@ __global__ void __launch_bounds__(NT) k_leaf_up(const S* __restrict__ xt, S* __r
   }
 }
 
+// digits (i_0, i_1, i_2) of every multi-index i = i_0 + p_s i_1 + p_s^2 i_2 < P into an LDS
+// table (visible after the caller's next barrier)
+__device__ inline void multi_index_digits(int* dg, int P, int ps) {
+  for (int i = threadIdx.x; i < P; i += NT) {
+    int rem = i;
+    for (int k = 0; k < 3; ++k) {
+      dg[3 * i + k] = rem % ps;
+      rem /= ps;
+    }
+  }
+}
+
 // Apply a per-axis transfer factor along axis k of a p_s^d x RC tensor in LDS:
 //   transpose == true:  out[.., a, ..] = sum_j E_h[j][a] in[.., j, ..]   (FastForward, E^T)
 //   transpose == false: out[.., j, ..] = sum_a E_h[j][a] in[.., a, ..]   (FastBackward, E)
-__device__ inline void kron_axis(const double* __restrict__ Es, int h, int ps, int stride, int P,
-                                 const double* __restrict__ src, double* __restrict__ dst, bool transpose) {
+// (dg: digit `axis` of every multi-index i < P at dg[3 i + axis], a table in LDS)
+__device__ inline void kron_axis(const double* __restrict__ Es, int h, int ps, int stride, int axis, int P,
+                                 const int* __restrict__ dg, const double* __restrict__ src,
+                                 double* __restrict__ dst, bool transpose) {
   for (int o = threadIdx.x; o < P * RC; o += NT) {
     const int i = o / RC, r = o % RC;
-    const int a = (i / stride) % ps;
+    const int a = dg[3 * i + axis];
     const int base = i - a * stride;
     double s = 0;
     for (int j = 0; j < ps; ++j) {
@@ -198,11 +212,13 @@ __global__ void __launch_bounds__(NT) k_transfer_up(S* __restrict__ xh, const do
                                                     int ps, int P, int Pp, int64_t nodes, int64_t R) {
   __shared__ double Es[2 * 16 * 16];
   __shared__ double bufA[128 * RC], bufB[128 * RC];
+  __shared__ int Dg[128 * 3];
   const int32_t s = node0 + blockIdx.x;
   const int r0 = blockIdx.y * RC;
   const int64_t slot = blockIdx.z;
   const int rc = (int)min<int64_t>(RC, R - r0);
   for (int o = threadIdx.x; o < 2 * ps * ps; o += NT) Es[o] = E[o];
+  multi_index_digits(Dg, P, ps);
   double acc[8];
   for (int q = 0; q < 8; ++q) acc[q] = 0;
   const int32_t f = first_child[s], nc = nchild[s];
@@ -220,7 +236,7 @@ __global__ void __launch_bounds__(NT) k_transfer_up(S* __restrict__ xh, const do
     double* dst = bufB;
     int stride = 1;
     for (int k = 0; k < d; ++k) {
-      kron_axis(Es, (cc >> k) & 1, ps, stride, P, src, dst, true);
+      kron_axis(Es, (cc >> k) & 1, ps, stride, k, P, Dg, src, dst, true);
       __syncthreads();
       double* tmp = src;
       src = dst;
@@ -248,11 +264,13 @@ __global__ void __launch_bounds__(NT) k_transfer_down(S* __restrict__ yh, const 
                                                       int ps, int P, int Pp, int64_t nodes, int64_t R) {
   __shared__ double Es[2 * 16 * 16];
   __shared__ double bufA[128 * RC], bufB[128 * RC];
+  __shared__ int Dg[128 * 3];
   const int32_t c = node0 + blockIdx.x;
   const int r0 = blockIdx.y * RC;
   const int64_t slot = blockIdx.z;
   const int rc = (int)min<int64_t>(RC, R - r0);
   for (int o = threadIdx.x; o < 2 * ps * ps; o += NT) Es[o] = E[o];
+  multi_index_digits(Dg, P, ps);
   const S* in = yh + (slot * nodes + parent_of[c]) * Pp * R;
   for (int o = threadIdx.x; o < P * RC; o += NT) {
     const int i = o / RC, r = o % RC;
@@ -264,7 +282,7 @@ __global__ void __launch_bounds__(NT) k_transfer_down(S* __restrict__ yh, const 
   double* dst = bufB;
   int stride = 1;
   for (int k = 0; k < d; ++k) {
-    kron_axis(Es, (cc >> k) & 1, ps, stride, P, src, dst, false);
+    kron_axis(Es, (cc >> k) & 1, ps, stride, k, P, Dg, src, dst, false);
     __syncthreads();
     double* tmp = src;
     src = dst;
@@ -799,6 +817,7 @@ __global__ void __launch_bounds__(NT) k_leaf_down(S* __restrict__ yt, const S* _
   typedef Mfma<S> MF;
   constexpr int CH = 128;
   __shared__ double Us[CH * 22];
+  __shared__ int Dg[128 * 3];   // per multi-index i < Pp: offsets k ps + i_k of its d digits in a Us row
   const int32_t s = leaf0 + blockIdx.x;
   const int r0 = blockIdx.y * RC;
   const int64_t slot = blockIdx.z;
@@ -809,6 +828,13 @@ __global__ void __launch_bounds__(NT) k_leaf_down(S* __restrict__ yt, const S* _
   const int dps = d * ps;
   const bool colok = r0 + m16 < R;
   const S* yhs = yh + (slot * nodes + s) * Pp * R;
+  for (int i = threadIdx.x; i < Pp; i += NT) {
+    int rem = i;
+    for (int k = 0; k < 3; ++k) {
+      Dg[i * 3 + k] = k * ps + rem % ps;
+      rem /= ps;
+    }
+  }
   S* ys = yt + slot * n * R;
   for (int64_t c0 = 0; c0 < ns; c0 += CH) {
     const int cn = (int)min<int64_t>(CH, ns - c0);
@@ -823,20 +849,15 @@ __global__ void __launch_bounds__(NT) k_leaf_down(S* __restrict__ yt, const S* _
       const int ii = k0 + kq;
       const bool iok = ii < P;
       const S bv = (iok && colok) ? yhs[(int64_t)ii * R + r0 + m16] : (S)0;
-      int dg[3];
-      int rem = ii;
-      for (int k = 0; k < 3; ++k) {
-        dg[k] = rem % ps;
-        rem /= ps;
-      }
+      const int* dg = &Dg[ii * 3];
       double u0 = 0.0, u1 = 0.0;
       if (iok && r0ok) {
         u0 = Us[i0 * dps + dg[0]];
-        for (int k = 1; k < d; ++k) u0 *= Us[i0 * dps + k * ps + dg[k]];
+        for (int k = 1; k < d; ++k) u0 *= Us[i0 * dps + dg[k]];
       }
       if (iok && r1ok) {
         u1 = Us[i1 * dps + dg[0]];
-        for (int k = 1; k < d; ++k) u1 *= Us[i1 * dps + k * ps + dg[k]];
+        for (int k = 1; k < d; ++k) u1 *= Us[i1 * dps + dg[k]];
       }
       if (t0ok) acc0 = MF::mac((S)u0, bv, acc0);
       if (t1ok) acc1 = MF::mac((S)u1, bv, acc1);
