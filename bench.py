@@ -310,8 +310,8 @@ def main():
         print(json.dumps({"copy_bytes": args.copy_calibration, "repeats": 5}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in the design notes, not built)"}))
+        print(json.dumps({"error": "--gpus must be 1: the library runs on a single GPU "
+                                   "(sharding across GPUs is not implemented)"}))
         sys.exit(2)
     if args.mode != "step":
         MODES[args.mode](args)
