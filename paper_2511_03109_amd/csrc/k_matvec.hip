@@ -344,10 +344,10 @@ __global__ void __launch_bounds__(NW * 64, HB) k_coupling(
   // every slot of a box is dispatched before the next box, so the long workgroups start first
   const int g = blockIdx.x;
   const int64_t slot = blockIdx.y;
-  const int zb = blockIdx.z / HB;
-  const int toff = (int)(blockIdx.z % HB) * NB;   // first target of this part of the box
-  const int grp = zb % n_groups;
-  const int r0 = (zb / n_groups) * RC;
+  // HB = 2: the groups are half boxes (halves adjacent), so the half is the group's parity
+  const int grp = blockIdx.z % n_groups;
+  const int toff = HB == 2 ? (grp & 1) * NB : 0;   // first target of this part of the box
+  const int r0 = (blockIdx.z / n_groups) * RC;
   const int lane = threadIdx.x % WAVE;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int wr = wave % WR, wt = wave / WR;
@@ -1004,14 +1004,21 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     const int64_t part_stride = T * m.n_nodes * m.Pp * Rs;
     const bool pack = Rs == 1;   // packed coupling (box targets as matrix-core columns)
     S* cout = G > 1 ? (S*)in.part.p : yh;
-    if (T > 65535 || m.n_groups * nrc * hb > 65535)
+    const int64_t ngr = hb == 2 ? m.n_hgroups : m.n_groups;
+    if (T > 65535 || ngr * nrc > 65535)
       fail(PH_EUNSUPPORTED, "ph_matvec: too many parameter slots or target boxes x RHS tiles for one launch");
-    dim3 cg((unsigned)G, (unsigned)T, (unsigned)(m.n_groups * nrc * hb));
+    dim3 cg((unsigned)G, (unsigned)T, (unsigned)(ngr * nrc));
     auto run = [&](auto kern, int nw) {
-      launch(PH_STAGE_COUPLING, kern, cg, dim3(64 * nw), st, (const S*)xh, cout, (const S*)in.C.p,
-             (const int32_t*)m.grp_targets.p, (const int32_t*)m.grp_entry.p, (const int32_t*)m.ent_cls.p,
-             (const int32_t*)m.ent_tau.p, (const int32_t*)m.chunk_first.p + m.chunk_off[ilog2(G)], m.Pp,
-             m.n_nodes, Rs, G, Cps, part_stride, (int)m.n_groups);
+      if (hb == 2)
+        launch(PH_STAGE_COUPLING, kern, cg, dim3(64 * nw), st, (const S*)xh, cout, (const S*)in.C.p,
+               (const int32_t*)m.hgrp_targets.p, (const int32_t*)nullptr, (const int32_t*)m.hent_cls.p,
+               (const int32_t*)m.hent_tau.p, (const int32_t*)m.hchunk_first.p + m.hchunk_off[ilog2(G)], m.Pp,
+               m.n_nodes, Rs, G, Cps, part_stride, (int)ngr);
+      else
+        launch(PH_STAGE_COUPLING, kern, cg, dim3(64 * nw), st, (const S*)xh, cout, (const S*)in.C.p,
+               (const int32_t*)m.grp_targets.p, (const int32_t*)m.grp_entry.p, (const int32_t*)m.ent_cls.p,
+               (const int32_t*)m.ent_tau.p, (const int32_t*)m.chunk_first.p + m.chunk_off[ilog2(G)], m.Pp,
+               m.n_nodes, Rs, G, Cps, part_stride, (int)ngr);
     };
     // 8 waves (4 row groups x 2 target halves) for Pp > 64, else 4 waves over the targets;
     // register prefetch depth 2 (PH_COUPLING_PD or the autotuner may select 1)

@@ -261,6 +261,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   // serves several targets.  For each box, one entry per class used by any of its nodes,
   // holding the source node of every target that uses it (-1 otherwise), classes ascending.
   std::vector<int32_t> gt, gptr{0}, ecls, etau, ewpre, gw;
+  std::vector<int32_t> hgt, hgptr{0}, hecls, hetau, hewpre, hgw;   // half boxes
   struct Box {
     std::vector<int32_t> targets, cls, tau, w;
     int64_t wsum = 0;
@@ -327,9 +328,30 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
       gw.push_back(pre);
       m->max_group_entries = std::max<int64_t>(m->max_group_entries, (int64_t)b.cls.size());
     }
+    // Half boxes (the 8-target workgroups of Pp = 128): each half keeps only the entries
+    // with at least one active target in it (18% of half-entries have none on the 3-D
+    // benchmark: their stages would be pure overhead).  Halves of a box stay adjacent, so
+    // the half is the parity of the group index.
+    for (const Box& b : boxes_all)
+      for (int h = 0; h < 2; ++h) {
+        hgt.insert(hgt.end(), b.targets.begin(), b.targets.end());
+        int32_t pre = 0;
+        for (size_t e = 0; e < b.cls.size(); ++e) {
+          int act = 0;
+          for (int sl = h * (NTG / 2); sl < (h + 1) * (NTG / 2); ++sl) act += b.tau[e * NTG + sl] >= 0;
+          if (act == 0) continue;
+          hecls.push_back(b.cls[e]);
+          hewpre.push_back(pre);
+          pre += coupling_entry_weight(act);
+          hetau.insert(hetau.end(), b.tau.begin() + e * NTG, b.tau.begin() + (e + 1) * NTG);
+        }
+        hgptr.push_back((int32_t)hecls.size());
+        hgw.push_back(pre);
+      }
   }
   m->n_groups = (int64_t)gptr.size() - 1;
   m->n_entries = (int64_t)ecls.size();
+  m->n_hgroups = (int64_t)hgptr.size() - 1;
 
   m->U.upload(hm.U.data(), hm.U.size(), st);
   m->E.upload(hm.E.data(), hm.E.size(), st);
@@ -360,24 +382,33 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   m->grp_entry.upload(gptr.data(), gptr.size(), st);
   m->ent_cls.upload(ecls.data(), ecls.size(), st);
   m->ent_tau.upload(etau.data(), etau.size(), st);
+  m->hgrp_targets.upload(hgt.data(), hgt.size(), st);
+  m->hent_cls.upload(hecls.data(), hecls.size(), st);
+  m->hent_tau.upload(hetau.data(), hetau.size(), st);
   // chunk boundaries: chunk g of G holds the entries whose work prefix lies in
   // [ceil(W g / G), ceil(W (g + 1) / G))
-  std::vector<int32_t> cfirst;
-  for (int c = 0; c < 7; ++c) {
-    const int G = 1 << c;
-    m->chunk_off[c] = (int64_t)cfirst.size();
-    for (size_t b = 0; b + 1 < gptr.size(); ++b) {
-      const int32_t e0 = gptr[b], e1 = gptr[b + 1];
-      const int64_t W = gw[b];
-      for (int g = 0; g <= G; ++g) {
-        const int64_t lim = (W * g + G - 1) / G;
-        int32_t e = e0;
-        while (e < e1 && ewpre[e] < lim) ++e;
-        cfirst.push_back(e);
+  auto chunks = [](const std::vector<int32_t>& ptr, const std::vector<int32_t>& wpre,
+                   const std::vector<int32_t>& wsum, std::vector<int32_t>& out, int64_t* off) {
+    for (int c = 0; c < 7; ++c) {
+      const int G = 1 << c;
+      off[c] = (int64_t)out.size();
+      for (size_t b = 0; b + 1 < ptr.size(); ++b) {
+        const int32_t e0 = ptr[b], e1 = ptr[b + 1];
+        const int64_t W = wsum[b];
+        for (int g = 0; g <= G; ++g) {
+          const int64_t lim = (W * g + G - 1) / G;
+          int32_t e = e0;
+          while (e < e1 && wpre[e] < lim) ++e;
+          out.push_back(e);
+        }
       }
     }
-  }
+  };
+  std::vector<int32_t> cfirst, hcfirst;
+  chunks(gptr, ewpre, gw, cfirst, m->chunk_off);
+  chunks(hgptr, hewpre, hgw, hcfirst, m->hchunk_off);
   m->chunk_first.upload(cfirst.data(), cfirst.size(), st);
+  m->hchunk_first.upload(hcfirst.data(), hcfirst.size(), st);
   PH_HIP(hipStreamSynchronize(st));  // host staging buffers die with this call
   m->device_bytes = (int64_t)(m->U.bytes() + m->E.bytes() + m->perm.bytes() + m->first_child.bytes() +
                               m->iperm.bytes() + m->nchild.bytes() + m->cid.bytes() + m->parent.bytes() + m->nbegin.bytes() + m->nend.bytes() +
@@ -388,7 +419,8 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
                               m->up_nt.bytes() + m->lo_rowptr.bytes() + m->lo_z.bytes() +
                               m->cstore.bytes() + m->ff_chat.bytes() + m->ff_theta.bytes() + m->grp_targets.bytes() +
                               m->grp_entry.bytes() + m->ent_cls.bytes() + m->ent_tau.bytes() +
-                              m->chunk_first.bytes());
+                              m->chunk_first.bytes() + m->hgrp_targets.bytes() + m->hent_cls.bytes() +
+                              m->hent_tau.bytes() + m->hchunk_first.bytes());
   return m;
 }
 

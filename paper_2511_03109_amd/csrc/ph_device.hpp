@@ -183,6 +183,11 @@ struct DeviceModel {
   // is entries [chunk_first[chunk_off[c] + b (G + 1) + g], ... + g + 1)
   DevArr<int32_t> chunk_first;
   int64_t chunk_off[7] = {0, 0, 0, 0, 0, 0, 0};
+  // the same for half boxes (two groups per box, halves adjacent): entries with at least one
+  // active target in the half, weights from the half's activity
+  DevArr<int32_t> hgrp_targets, hent_cls, hent_tau, hchunk_first;
+  int64_t hchunk_off[7] = {0, 0, 0, 0, 0, 0, 0};
+  int64_t n_hgroups = 0;
   int64_t device_bytes = 0;
 };
 
