@@ -845,22 +845,33 @@ __global__ void __launch_bounds__(NT) k_leaf_down(S* __restrict__ yt, const S* _
     const bool t0ok = wave * 16 < cn, t1ok = (wave + 4) * 16 < cn;
     const bool r0ok = i0 < cn, r1ok = i1 < cn;
     typename MF::acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < Pp; k0 += 4) {
-      const int ii = k0 + kq;
-      const bool iok = ii < P;
-      const S bv = (iok && colok) ? yhs[(int64_t)ii * R + r0 + m16] : (S)0;
-      const int* dg = &Dg[ii * 3];
-      double u0 = 0.0, u1 = 0.0;
-      if (iok && r0ok) {
-        u0 = Us[i0 * dps + dg[0]];
-        for (int k = 1; k < d; ++k) u0 *= Us[i0 * dps + dg[k]];
+    // y_hat values of 8 K-steps are loaded together (one global load per K-step otherwise
+    // leaves the loop waiting on memory latency at every step)
+    for (int kb = 0; kb < Pp; kb += 32) {
+      S by[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int iq = kb + 4 * q + kq;
+        by[q] = (iq < P && colok) ? yhs[(int64_t)iq * R + r0 + m16] : (S)0;
       }
-      if (iok && r1ok) {
-        u1 = Us[i1 * dps + dg[0]];
-        for (int k = 1; k < d; ++k) u1 *= Us[i1 * dps + dg[k]];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int ii = kb + 4 * q + kq;
+        if (kb + 4 * q >= Pp) break;
+        const bool iok = ii < P;
+        const int* dg = &Dg[(iok ? ii : 0) * 3];
+        double u0 = 0.0, u1 = 0.0;
+        if (iok && r0ok) {
+          u0 = Us[i0 * dps + dg[0]];
+          for (int k = 1; k < d; ++k) u0 *= Us[i0 * dps + dg[k]];
+        }
+        if (iok && r1ok) {
+          u1 = Us[i1 * dps + dg[0]];
+          for (int k = 1; k < d; ++k) u1 *= Us[i1 * dps + dg[k]];
+        }
+        if (t0ok) acc0 = MF::mac((S)u0, by[q], acc0);
+        if (t1ok) acc1 = MF::mac((S)u1, by[q], acc1);
       }
-      if (t0ok) acc0 = MF::mac((S)u0, bv, acc0);
-      if (t1ok) acc1 = MF::mac((S)u1, bv, acc1);
     }
     if (colok) {
       for (int q = 0; q < 4; ++q) {
