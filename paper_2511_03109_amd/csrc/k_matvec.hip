@@ -539,17 +539,20 @@ __global__ void __launch_bounds__(NT) k_near_mvm(
     const S* __restrict__ xt, S* __restrict__ yt, const DT* __restrict__ D, const int64_t* __restrict__ nbegin,
     const int64_t* __restrict__ nend, const int64_t* __restrict__ rowptr, const int64_t* __restrict__ ntb,
     const int32_t* __restrict__ nnt, const int32_t* __restrict__ ntr, const int64_t* __restrict__ nD,
-    int32_t leaf0, int64_t n, int64_t R, int64_t N_nf, int xcd) {
+    const int32_t* __restrict__ items, int32_t leaf0, int64_t n, int64_t R, int64_t N_nf, int xcd) {
   typedef Mfma<S> MF;
   constexpr int CH = 128;
-  // Workgroups are dealt to the 8 XCDs round robin; with xcd set, XCD x gets the contiguous
-  // leaf range [x q, x q + q) (q = n_leaves / 8), a compact region of space, so that the two
-  // reads of a stored block (for s and, transposed, for t) mostly meet in the same L2.  The
-  // host sets it only when those ranges carry about equal work (uneven point sets leave it
-  // off: one XCD would get the dense region).
+  // One workgroup per work item = (leaf, 128-row chunk of it), so that the large leaves of
+  // uneven point sets are spread over several workgroups.  Workgroups are dealt to the 8
+  // XCDs round robin; with xcd set, XCD x gets the contiguous item range [x q, x q + q)
+  // (q = items / 8), a compact region of space, so that the two reads of a stored block
+  // (for s and, transposed, for t) mostly meet in the same L2.  The host sets it only when
+  // those ranges carry about equal work (uneven point sets leave it off: one XCD would get
+  // the dense region).
   const int nl = gridDim.x, q8 = nl / 8;
-  const int32_t li = xcd && (int)blockIdx.x < 8 * q8 ? (int)(blockIdx.x % 8) * q8 + (int)(blockIdx.x / 8)
+  const int32_t it = xcd && (int)blockIdx.x < 8 * q8 ? (int)(blockIdx.x % 8) * q8 + (int)(blockIdx.x / 8)
                                                       : (int)blockIdx.x;
+  const int32_t li = items[2 * it], cstart = items[2 * it + 1];
   const int32_t s = leaf0 + li;
   const int r0 = blockIdx.y * RC;
   const int64_t slot = blockIdx.z;
@@ -561,7 +564,7 @@ __global__ void __launch_bounds__(NT) k_near_mvm(
   const S* xs = xt + slot * n * R;
   const DT* Ds = D + slot * N_nf;
   const int64_t bb0 = rowptr[li], bb1 = rowptr[li + 1];
-  for (int64_t c0 = 0; c0 < ns; c0 += CH) {
+  for (int64_t c0 = cstart; c0 < ns && c0 < cstart + CH; c0 += CH) {
     const int cn = (int)min<int64_t>(CH, ns - c0);
     const int64_t i0 = c0 + wave * 16 + m16, i1 = c0 + (wave + 4) * 16 + m16;   // rows of the leaf
     const bool t0ok = wave * 16 < cn, t1ok = (wave + 4) * 16 < cn;
@@ -993,11 +996,11 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
              (const S*)in.zb.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
              (const int64_t*)m.lo_rowptr.p, (const int64_t*)m.lo_z.p, leaf0, m.n, m.Zt);
     } else {
-      launch(PH_STAGE_NEAR_MVM, k_near_mvm<S, DT>, dim3((unsigned)m.n_leaves, (unsigned)nrc, (unsigned)T),
+      launch(PH_STAGE_NEAR_MVM, k_near_mvm<S, DT>, dim3((unsigned)m.n_mvm_items, (unsigned)nrc, (unsigned)T),
              dim3(NT), nst, (const S*)xt, yt, (const DT*)in.D.p, (const int64_t*)m.nbegin.p,
              (const int64_t*)m.nend.p, (const int64_t*)m.near_rowptr.p, (const int64_t*)m.near_tb.p,
-             (const int32_t*)m.near_nt.p, (const int32_t*)m.near_tr.p, (const int64_t*)m.near_D.p, leaf0, m.n, Rs,
-             m.N_nf_pad, xcd);
+             (const int32_t*)m.near_nt.p, (const int32_t*)m.near_tr.p, (const int64_t*)m.near_D.p,
+             (const int32_t*)m.mvm_items.p, leaf0, m.n, Rs, m.N_nf_pad, xcd);
     }
     if (!serial) PH_HIP(hipEventRecord(in.ev_join, in.aux));
   };

@@ -134,6 +134,17 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
     ntr[b] = m->D_tr_host[b];
   }
   for (int64_t i = 0; i < m->n_leaves; ++i) nrow[i + 1] += nrow[i];
+  // near MVM work items, one per 128-row chunk of every leaf (leaf order)
+  std::vector<int32_t> items;
+  for (int64_t li = 0; li < m->n_leaves; ++li) {
+    const int64_t ns = t.size(t.leaves[(size_t)li]);
+    for (int64_t c0 = 0; c0 < std::max<int64_t>(ns, 1); c0 += 128) {
+      items.push_back((int32_t)li);
+      items.push_back((int32_t)c0);
+    }
+  }
+  m->n_mvm_items = (int64_t)items.size() / 2;
+  m->mvm_items.upload(items.data(), items.size(), st);
   // XCD-contiguous leaf ranges in the near MVM only when the 8 ranges carry about equal
   // work (entries of the leaf's near blocks): within 5% of the mean
   {
@@ -419,7 +430,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
                               m->up_nt.bytes() + m->lo_rowptr.bytes() + m->lo_z.bytes() +
                               m->cstore.bytes() + m->ff_chat.bytes() + m->ff_theta.bytes() + m->grp_targets.bytes() +
                               m->grp_entry.bytes() + m->ent_cls.bytes() + m->ent_tau.bytes() +
-                              m->chunk_first.bytes() + m->hgrp_targets.bytes() + m->hent_cls.bytes() +
+                              m->chunk_first.bytes() + m->mvm_items.bytes() + m->hgrp_targets.bytes() + m->hent_cls.bytes() +
                               m->hent_tau.bytes() + m->hchunk_first.bytes());
   return m;
 }
