@@ -815,13 +815,15 @@ template <typename S>
 __global__ void __launch_bounds__(NT) k_leaf_down(S* __restrict__ yt, const S* __restrict__ yh,
                                                   const double* __restrict__ U,
                                                   const int64_t* __restrict__ nbegin,
-                                                  const int64_t* __restrict__ nend, int32_t leaf0, int d,
+                                                  const int64_t* __restrict__ nend,
+                                                  const int32_t* __restrict__ items, int32_t leaf0, int d,
                                                   int ps, int P, int Pp, int64_t n, int64_t nodes, int64_t R) {
   typedef Mfma<S> MF;
   constexpr int CH = 128;
   __shared__ double Us[CH * 22];
   __shared__ int Dg[128 * 3];   // per multi-index i < Pp: offsets k ps + i_k of its d digits in a Us row
-  const int32_t s = leaf0 + blockIdx.x;
+  // one workgroup per (leaf, 128-row chunk): the chunks of a leaf are independent here
+  const int32_t s = leaf0 + items[2 * blockIdx.x], cstart = items[2 * blockIdx.x + 1];
   const int r0 = blockIdx.y * RC;
   const int64_t slot = blockIdx.z;
   const int lane = threadIdx.x % WAVE;
@@ -839,7 +841,7 @@ __global__ void __launch_bounds__(NT) k_leaf_down(S* __restrict__ yt, const S* _
     }
   }
   S* ys = yt + slot * n * R;
-  for (int64_t c0 = 0; c0 < ns; c0 += CH) {
+  for (int64_t c0 = cstart; c0 < ns && c0 < cstart + CH; c0 += CH) {
     const int cn = (int)min<int64_t>(CH, ns - c0);
     __syncthreads();
     for (int q = threadIdx.x; q < cn * dps; q += NT) Us[q] = U[(b + c0) * dps + q];
@@ -1085,9 +1087,10 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
   }
   if (!serial) PH_HIP(hipStreamWaitEvent(st, in.ev_join, 0));
   if (use_far)
-    launch(PH_STAGE_LEAF_DOWN, k_leaf_down<S>, dim3((unsigned)m.n_leaves, (unsigned)nrc, (unsigned)T),
+    launch(PH_STAGE_LEAF_DOWN, k_leaf_down<S>, dim3((unsigned)m.n_mvm_items, (unsigned)nrc, (unsigned)T),
            dim3(NT), st, yt, (const S*)yh, (const double*)m.U.p, (const int64_t*)m.nbegin.p,
-           (const int64_t*)m.nend.p, leaf0, m.d, m.p_s, m.P, m.Pp, m.n, m.n_nodes, Rs);
+           (const int64_t*)m.nend.p, (const int32_t*)m.mvm_items.p, leaf0, m.d, m.p_s, m.P, m.Pp, m.n,
+           m.n_nodes, Rs);
   const int64_t total_out = T * m.n * R;
   if (Rs >= RC)
     launch(PH_STAGE_PERM_OUT, k_perm_out_tile<S>, ptile, dim3(NT), st, y, (const S*)yt, (const S*)xt,

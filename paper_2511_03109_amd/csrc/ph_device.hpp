@@ -171,7 +171,7 @@ struct DeviceModel {
   DevArr<int64_t> lo_rowptr, lo_z;
   int64_t Zt = 0;
   int near_xcd = 0;   // near MVM: contiguous leaf ranges per XCD (only if they balance)
-  DevArr<int32_t> mvm_items;   // near MVM work items: (leaf index, first row of a 128-row chunk)
+  DevArr<int32_t> mvm_items;   // near MVM and leaf-down work items: (leaf index, first row of a 128-row chunk)
   int64_t n_mvm_items = 0;
   int gemv_mp = 12;   // single-RHS near MVM: 16-row panels per row chunk (4, 8 or 12)
   DevArr<ClassDev> cstore;
