@@ -97,3 +97,73 @@ def test_tree_rejects_bad_input(bad):
     with pytest.raises(_lib.PHError) as e:
         api.Tree(X, **kw)
     assert e.value.code == _lib.PH_EINVAL
+
+
+def test_entry_points_reject_null_handles():
+    """Every entry point that takes a handle returns PH_EINVAL with a message for a NULL one
+    (checked before any HIP call, so this runs without a GPU)."""
+    import ctypes as C
+    lib = _lib.lib()
+    d = C.c_double(0.0)
+    out = C.c_void_p()
+    calls = {
+        "ph_tree_info_get": lambda: lib.ph_tree_info_get(None, None),
+        "ph_offline_compress": lambda: lib.ph_offline_compress(None, None, None, C.byref(out)),
+        "ph_model_info_get": lambda: lib.ph_model_info_get(None, None),
+        "ph_instantiate": lambda: lib.ph_instantiate(None, C.byref(d), 1, 0, None, C.byref(out)),
+        "ph_instantiate_grad": lambda: lib.ph_instantiate_grad(None, C.byref(d), 1, -1, 0, None,
+                                                              C.byref(out)),
+        "ph_matvec": lambda: lib.ph_matvec(None, None, None, 1, 1.0, 0.0, 0.0, None),
+        "ph_bilinear": lambda: lib.ph_bilinear(None, None, None, 1, None, None),
+        "ph_cg_solve": lambda: lib.ph_cg_solve(None, None, None, None, 0.0, 1e-6, 10, 1, 1e-6,
+                                               None, None),
+        "ph_autotune": lambda: lib.ph_autotune(None, None, None, 1, None, None),
+        "ph_graph_create": lambda: lib.ph_graph_create(None, None, None, 1, 0.0, None, C.byref(out)),
+        "ph_graph_launch": lambda: lib.ph_graph_launch(None, None, None),
+        "ph_inst_near_block": lambda: lib.ph_inst_near_block(None, 0, 0, None),
+        "ph_inst_coupling": lambda: lib.ph_inst_coupling(None, 0, 0, None),
+    }
+    for name, call in calls.items():
+        assert call() == _lib.PH_EINVAL, name
+        assert lib.ph_last_error(), name
+    assert not out.value
+    for free in ("ph_tree_free", "ph_model_free", "ph_inst_free", "ph_graph_free"):
+        getattr(lib, free)(None)          # freeing NULL is a no-op
+
+
+@pytest.mark.parametrize("bad,code", [("p_s", _lib.PH_EINVAL), ("p_theta", _lib.PH_EINVAL),
+                                      ("tol", _lib.PH_EINVAL), ("box", _lib.PH_EINVAL),
+                                      ("d_theta", _lib.PH_EUNSUPPORTED), ("P", _lib.PH_EUNSUPPORTED),
+                                      ("aniso3d", _lib.PH_EUNSUPPORTED)])
+def test_offline_rejects_bad_options(bad, code):
+    """The offline stage validates its options on the host before any work or upload."""
+    d = 3 if bad in ("P", "aniso3d") else 2
+    t = api.Tree(np.random.default_rng(1).random((50, d)), l_max=1)
+    kernel, lo, hi = "matern12", [0.1], [0.5]
+    kw = dict(p_s=4, p_theta=5, tol=1e-8)
+    if bad == "p_s":
+        kw["p_s"] = 0
+    elif bad == "p_theta":
+        kw["p_theta"] = 17
+    elif bad == "tol":
+        kw["tol"] = float("nan")
+    elif bad == "box":
+        lo, hi = [0.5], [0.5]
+    elif bad == "d_theta":
+        lo, hi = [0.1, 0.1], [0.5, 0.5]
+    elif bad == "P":
+        kw["p_s"] = 6                     # 6^3 = 216 > 128
+    else:
+        kernel, lo, hi = "aniso_gaussian", [0.1] * 2, [0.5] * 2
+    import ctypes as C
+    opts = _lib.OfflineOpts()
+    opts.kernel = _lib.KERNELS[kernel]
+    opts.d_theta = len(lo)
+    for k in range(len(lo)):
+        opts.theta_lo[k], opts.theta_hi[k] = lo[k], hi[k]
+    opts.p_s, opts.p_theta, opts.tol, opts.num_threads = kw["p_s"], kw["p_theta"], kw["tol"], 1
+    out = C.c_void_p()
+    lib = _lib.lib()
+    # NULL stream: the call must fail in the option checks, before anything is uploaded
+    assert lib.ph_offline_compress(t._h, C.byref(opts), None, C.byref(out)) == code
+    assert lib.ph_last_error() and not out.value
