@@ -182,21 +182,22 @@ __device__ inline void multi_index_digits(int* dg, int P, int ps) {
   }
 }
 
-// Apply a per-axis transfer factor along axis k of a p_s^d x RC tensor in LDS:
+// Apply a per-axis transfer factor along axis k of a p_s^d x 2^lc tensor in LDS (2^lc
+// right-hand-side columns: 16, or 1 for a single right-hand side):
 //   transpose == true:  out[.., a, ..] = sum_j E_h[j][a] in[.., j, ..]   (FastForward, E^T)
 //   transpose == false: out[.., j, ..] = sum_a E_h[j][a] in[.., a, ..]   (FastBackward, E)
 // (dg: digit `axis` of every multi-index i < P at dg[3 i + axis], a table in LDS)
 __device__ inline void kron_axis(const double* __restrict__ Es, int h, int ps, int stride, int axis, int P,
-                                 const int* __restrict__ dg, const double* __restrict__ src,
+                                 int lc, const int* __restrict__ dg, const double* __restrict__ src,
                                  double* __restrict__ dst, bool transpose) {
-  for (int o = threadIdx.x; o < P * RC; o += NT) {
-    const int i = o / RC, r = o % RC;
+  for (int o = threadIdx.x; o < (P << lc); o += NT) {
+    const int i = o >> lc, r = o & ((1 << lc) - 1);
     const int a = dg[3 * i + axis];
     const int base = i - a * stride;
     double s = 0;
     for (int j = 0; j < ps; ++j) {
       const double e = transpose ? Es[(h * ps + j) * ps + a] : Es[(h * ps + a) * ps + j];
-      s += e * src[(base + j * stride) * RC + r];
+      s += e * src[((base + j * stride) << lc) + r];
     }
     dst[o] = s;
   }
@@ -204,7 +205,8 @@ __device__ inline void kron_axis(const double* __restrict__ Es, int h, int ps, i
 
 // FastForward, inner nodes: x_hat_s = sum_{children c} E_c^T x_hat_c with
 // E_c = E_{c,d} (x) ... (x) E_{c,1} applied one axis at a time (FastKron).
-template <typename S>
+// LC: log2 of the right-hand-side columns held in LDS (4, or 0 for a single one).
+template <typename S, int LC>
 __global__ void __launch_bounds__(NT) k_transfer_up(S* __restrict__ xh, const double* __restrict__ E,
                                                     const int32_t* __restrict__ first_child,
                                                     const int32_t* __restrict__ nchild,
@@ -217,6 +219,7 @@ __global__ void __launch_bounds__(NT) k_transfer_up(S* __restrict__ xh, const do
   const int r0 = blockIdx.y * RC;
   const int64_t slot = blockIdx.z;
   const int rc = (int)min<int64_t>(RC, R - r0);
+  constexpr int lc = LC;
   for (int o = threadIdx.x; o < 2 * ps * ps; o += NT) Es[o] = E[o];
   multi_index_digits(Dg, P, ps);
   double acc[8];
@@ -226,8 +229,8 @@ __global__ void __launch_bounds__(NT) k_transfer_up(S* __restrict__ xh, const do
     const int32_t ch = f + c;
     const S* in = xh + (slot * nodes + ch) * Pp * R;
     __syncthreads();
-    for (int o = threadIdx.x; o < P * RC; o += NT) {
-      const int i = o / RC, r = o % RC;
+    for (int o = threadIdx.x; o < (P << lc); o += NT) {
+      const int i = o >> lc, r = o & ((1 << lc) - 1);
       bufA[o] = r < rc ? (double)in[(int64_t)i * R + r0 + r] : 0.0;
     }
     __syncthreads();
@@ -236,7 +239,7 @@ __global__ void __launch_bounds__(NT) k_transfer_up(S* __restrict__ xh, const do
     double* dst = bufB;
     int stride = 1;
     for (int k = 0; k < d; ++k) {
-      kron_axis(Es, (cc >> k) & 1, ps, stride, k, P, Dg, src, dst, true);
+      kron_axis(Es, (cc >> k) & 1, ps, stride, k, P, lc, Dg, src, dst, true);
       __syncthreads();
       double* tmp = src;
       src = dst;
@@ -245,19 +248,20 @@ __global__ void __launch_bounds__(NT) k_transfer_up(S* __restrict__ xh, const do
     }
     for (int q = 0; q < 8; ++q) {
       const int o = threadIdx.x + q * NT;
-      if (o < P * RC) acc[q] += src[o];
+      if (o < (P << lc)) acc[q] += src[o];
     }
   }
   S* out = xh + (slot * nodes + s) * Pp * R;
   for (int q = 0; q < 8; ++q) {
     const int o = threadIdx.x + q * NT;
-    const int i = o / RC, r = o % RC;
+    const int i = o >> lc, r = o & ((1 << lc) - 1);
     if (i < Pp && r < rc) out[(int64_t)i * R + r0 + r] = (S)(i < P ? acc[q] : 0.0);
   }
 }
 
 // FastBackward, inner nodes: y_hat_c += E_c y_hat_parent, one workgroup per child.
-template <typename S>
+// LC as in k_transfer_up.
+template <typename S, int LC>
 __global__ void __launch_bounds__(NT) k_transfer_down(S* __restrict__ yh, const double* __restrict__ E,
                                                       const int32_t* __restrict__ parent_of,
                                                       const int32_t* __restrict__ cid, int32_t node0, int d,
@@ -269,11 +273,12 @@ __global__ void __launch_bounds__(NT) k_transfer_down(S* __restrict__ yh, const 
   const int r0 = blockIdx.y * RC;
   const int64_t slot = blockIdx.z;
   const int rc = (int)min<int64_t>(RC, R - r0);
+  constexpr int lc = LC;
   for (int o = threadIdx.x; o < 2 * ps * ps; o += NT) Es[o] = E[o];
   multi_index_digits(Dg, P, ps);
   const S* in = yh + (slot * nodes + parent_of[c]) * Pp * R;
-  for (int o = threadIdx.x; o < P * RC; o += NT) {
-    const int i = o / RC, r = o % RC;
+  for (int o = threadIdx.x; o < (P << lc); o += NT) {
+    const int i = o >> lc, r = o & ((1 << lc) - 1);
     bufA[o] = r < rc ? (double)in[(int64_t)i * R + r0 + r] : 0.0;
   }
   __syncthreads();
@@ -282,7 +287,7 @@ __global__ void __launch_bounds__(NT) k_transfer_down(S* __restrict__ yh, const 
   double* dst = bufB;
   int stride = 1;
   for (int k = 0; k < d; ++k) {
-    kron_axis(Es, (cc >> k) & 1, ps, stride, k, P, Dg, src, dst, false);
+    kron_axis(Es, (cc >> k) & 1, ps, stride, k, P, lc, Dg, src, dst, false);
     __syncthreads();
     double* tmp = src;
     src = dst;
@@ -290,8 +295,8 @@ __global__ void __launch_bounds__(NT) k_transfer_down(S* __restrict__ yh, const 
     stride *= ps;
   }
   S* out = yh + (slot * nodes + c) * Pp * R;
-  for (int o = threadIdx.x; o < P * RC; o += NT) {
-    const int i = o / RC, r = o % RC;
+  for (int o = threadIdx.x; o < (P << lc); o += NT) {
+    const int i = o >> lc, r = o & ((1 << lc) - 1);
     if (r < rc) {
       const int64_t idx = (int64_t)i * R + r0 + r;
       out[idx] = (S)((double)out[idx] + src[o]);
@@ -1013,7 +1018,8 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
            leaf0, m.d, m.p_s, m.P, m.Pp, m.n, m.n_nodes, Rs);
     for (int l = m.l_max - 1; l >= m.min_far; --l) {
       const int32_t a = t.level_start[l], b = t.level_start[l + 1];
-      launch(PH_STAGE_TRANSFER_UP, k_transfer_up<S>, dim3((unsigned)(b - a), (unsigned)nrc, (unsigned)T),
+      launch(PH_STAGE_TRANSFER_UP, Rs == 1 ? k_transfer_up<S, 0> : k_transfer_up<S, 4>,
+             dim3((unsigned)(b - a), (unsigned)nrc, (unsigned)T),
              dim3(NT), st, xh, (const double*)m.E.p, (const int32_t*)m.first_child.p,
              (const int32_t*)m.nchild.p, (const int32_t*)m.cid.p, a, m.d, m.p_s, m.P, m.Pp, m.n_nodes, Rs);
     }
@@ -1080,7 +1086,8 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     }
     for (int l = m.min_far; l < m.l_max; ++l) {
       const int32_t a = t.level_start[l + 1], b = t.level_start[l + 2];
-      launch(PH_STAGE_TRANSFER_DOWN, k_transfer_down<S>, dim3((unsigned)(b - a), (unsigned)nrc, (unsigned)T),
+      launch(PH_STAGE_TRANSFER_DOWN, Rs == 1 ? k_transfer_down<S, 0> : k_transfer_down<S, 4>,
+             dim3((unsigned)(b - a), (unsigned)nrc, (unsigned)T),
              dim3(NT), st, yh, (const double*)m.E.p, (const int32_t*)m.parent.p, (const int32_t*)m.cid.p, a,
              m.d, m.p_s, m.P, m.Pp, m.n_nodes, Rs);
     }
