@@ -26,7 +26,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_MFMA_PEAK_TFS = 78.6      # MI355X dense FP64 matrix
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 CSRC = os.path.join(ROOT, "paper_2511_03109_amd", "csrc")
-# source files whose text determines each hot kernel's code
+# source files whose text determines each hot kernel's code: the kernel's own definition in
+# the first file (template line to closing brace), the whole shared header
 KERNEL_SOURCES = {
     "k_coupling": ["k_matvec.hip", "ph_device.hpp"],
     "k_near_mvm": ["k_matvec.hip", "ph_device.hpp"],
@@ -38,12 +39,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_hash(kernel):
+def kernel_text(text, kernel):
+    """The definition of `kernel` in a source text: from its template line to the first
+    closing brace in column 0."""
+    import re
+    m = re.search(r"^template <[^\n]*>\n__global__[^\n]*\b" + kernel + r"\(", text, re.M)
+    if m is None:
+        raise KeyError(kernel)
+    end = text.index("\n}\n", m.start())
+    return text[m.start():end + 3]
+
+
+def source_hash(kernel, read=None):
+    """Hash of the kernel's definition and the shared header; read(f) returns a source
+    file's text (default: the working tree)."""
     import hashlib
+    if read is None:
+        def read(f):
+            with open(os.path.join(CSRC, f)) as fh:
+                return fh.read()
+    files = KERNEL_SOURCES[kernel]
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES[kernel]:
-        with open(os.path.join(CSRC, f), "rb") as fh:
-            h.update(fh.read())
+    h.update(kernel_text(read(files[0]), kernel).encode())
+    for f in files[1:]:
+        h.update(read(f).encode())
     return h.hexdigest()[:16]
 
 
