@@ -167,3 +167,23 @@ def test_offline_rejects_bad_options(bad, code):
     # NULL stream: the call must fail in the option checks, before anything is uploaded
     assert lib.ph_offline_compress(t._h, C.byref(opts), None, C.byref(out)) == code
     assert lib.ph_last_error() and not out.value
+
+
+def test_counter_records_key_on_each_kernel_definition():
+    """The benchmark's counter records are keyed by the text of each hot kernel's own
+    definition: the extraction finds every kernel, returns exactly one definition (template
+    line to closing brace), and an edit outside that text leaves the key unchanged."""
+    import bench
+    csrc = os.path.join(ROOT, "paper_2511_03109_amd", "csrc")
+    for k, files in bench.KERNEL_SOURCES.items():
+        text = open(os.path.join(csrc, files[0])).read()
+        body = bench.kernel_text(text, k)
+        assert body.startswith("template <") and body.endswith("\n}\n")
+        assert f" {k}(" in body.split("\n")[1]
+        assert body.count("\n}\n") == 1
+        h = bench.source_hash(k)
+        edited = {f: open(os.path.join(csrc, f)).read() for f in files}
+        edited[files[0]] = edited[files[0]] + "\n// trailing edit\n"
+        assert bench.source_hash(k, read=lambda f: edited[f]) == h
+        edited[files[0]] = edited[files[0]].replace(body, body.replace("{", "{ ", 1))
+        assert bench.source_hash(k, read=lambda f: edited[f]) != h
