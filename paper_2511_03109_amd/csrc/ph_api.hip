@@ -735,9 +735,29 @@ int ph_autotune(ph_inst* k, const void* x, void* y, int64_t R, void* stream, ph_
     need(in.graphs == 0, "instance has recorded graphs; tune before recording");
     const ph::DeviceModel& m = *in.m;
     hipStream_t st = (hipStream_t)stream;
-    hipEvent_t a, b;
-    PH_HIP(hipEventCreate(&a));
-    PH_HIP(hipEventCreate(&b));
+    // the events are destroyed, and the instance keeps its previous configuration, also when
+    // a trial fails
+    struct Events {
+      hipEvent_t a = nullptr, b = nullptr;
+      ~Events() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+      }
+    } ev;
+    struct Restore {
+      ph::InstData& in;
+      int chunks, prefetch, overlap;
+      bool done = false;
+      ~Restore() {
+        if (done) return;
+        in.tune_chunks = chunks;
+        in.tune_prefetch = prefetch;
+        in.tune_overlap = overlap;
+      }
+    } restore{in, in.tune_chunks, in.tune_prefetch, in.tune_overlap};
+    PH_HIP(hipEventCreate(&ev.a));
+    PH_HIP(hipEventCreate(&ev.b));
+    hipEvent_t a = ev.a, b = ev.b;
     auto run = [&] {
       if (in.dt == PH_F64)
         ph::matvec_impl<double, double>(in, (const double*)x, (double*)y, R, 1.0, 0.0, 0.0, st);
@@ -771,11 +791,10 @@ int ph_autotune(ph_inst* k, const void* x, void* y, int64_t R, void* stream, ph_
             bi = ph_tune_info{g, pd, ov, (double)ms};
           }
         }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
     in.tune_chunks = bi.chunks;
     in.tune_prefetch = bi.prefetch;
     in.tune_overlap = bi.overlap;
+    restore.done = true;
     if (info) *info = bi;
   });
 }
