@@ -265,7 +265,8 @@ int ph_cg_solve(ph_inst* hi, ph_inst* lo, const double* y, double* a, double nug
  * depth of the coupling pipeline (1, 2) and near field overlapped on a second stream or
  * not is timed (3 runs after a warm-up, HIP events on `stream`), and the fastest is kept
  * in the instance for all later ph_matvec calls.  x, y: as ph_matvec (y is overwritten).
- * Synchronises `stream`.  Must precede ph_graph_create. */
+ * Synchronises `stream`.  Must precede ph_graph_create (PH_ESTATE after it).  On any
+ * failure the instance keeps the configuration it had before the call. */
 typedef struct {
   int chunks, prefetch, overlap;
   double ms;              /* measured time of one ph_matvec with this configuration */
