@@ -732,7 +732,7 @@ int ph_autotune(ph_inst* k, const void* x, void* y, int64_t R, void* stream, ph_
     need(k && k->p, "instance is NULL");
     need(x && y && R >= 1, "x, y must be non-NULL and R >= 1");
     ph::InstData& in = *k->p;
-    need(in.graphs == 0, "instance has recorded graphs; tune before recording");
+    if (in.graphs > 0) ph::fail(PH_ESTATE, "instance has recorded graphs; tune before recording");
     const ph::DeviceModel& m = *in.m;
     hipStream_t st = (hipStream_t)stream;
     // the events are destroyed, and the instance keeps its previous configuration, also when
