@@ -822,8 +822,9 @@ int ph_graph_create(ph_inst* k, const void* x, void* y, int64_t R, double nugget
     mv();   // allocates every scratch buffer the recorded launches use
     PH_HIP(hipStreamSynchronize(st));
     if (in.theta_pending) PH_HIP(hipEventSynchronize(in.ev_theta));
+    // (g->in is set only once the graph exists: the destructor releases the instance's
+    // graph count, which a failed recording never took)
     auto g = std::make_unique<ph_graph>();
-    g->in = k->p;
     ph::g_capturing = true;
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
     if (e == hipSuccess) {
@@ -842,6 +843,7 @@ int ph_graph_create(ph_inst* k, const void* x, void* y, int64_t R, double nugget
     ph::g_capturing = false;
     if (e != hipSuccess) ph::fail(PH_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
     PH_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    g->in = k->p;
     ++in.graphs;
     *out = g.release();
   });
