@@ -187,3 +187,15 @@ def test_counter_records_key_on_each_kernel_definition():
         assert bench.source_hash(k, read=lambda f: edited[f]) == h
         edited[files[0]] = edited[files[0]].replace(body, body.replace("{", "{ ", 1))
         assert bench.source_hash(k, read=lambda f: edited[f]) != h
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU; --gpus N > 1 exits with a message before touching a GPU."""
+    import json
+    import subprocess
+    import sys
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode != 0
+    msg = json.loads(res.stdout.strip().splitlines()[-1])["error"]
+    assert "single GPU" in msg
