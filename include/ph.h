@@ -167,11 +167,16 @@ typedef struct {
   int64_t device_bytes;       /* bytes the model holds on the device */
   int64_t kernel_evals;       /* kernel evaluations done by the offline stage */
   int P, p_theta, d_theta;
+  int svd_sweeps_max;         /* most one-sided Jacobi sweeps any SVD of the offline stage took */
 } ph_model_info;
 
 /* Offline stage.  stream: the upload stream.  Errors: PH_EINVAL (NULL, bad sizes,
- * theta_lo >= theta_hi), PH_EUNSUPPORTED (kernel / d / d_theta combination),
- * PH_ENOMEM, PH_EHIP.  *out is owned by the caller (ph_model_free); the tree may be
+ * theta_lo >= theta_hi), PH_EUNSUPPORTED (kernel / d / d_theta combination, or an SVD
+ * whose one-sided Jacobi iteration still rotates after 80 sweeps), PH_ENOMEM, PH_EHIP.
+ * Truncation: the rank of each mode is cut as stated above, then moved past every
+ * following singular value within relative 1e-4 of the last one kept, so that a cluster
+ * of equal singular values (exactly degenerate pairs arise from symmetric geometry) is
+ * kept or dropped as a whole and the kept subspace is unique.  *out is owned by the caller (ph_model_free); the tree may be
  * freed right after this call. */
 int ph_offline_compress(const ph_tree* t, const ph_offline_opts* opts, void* stream,
                         ph_model** out);
@@ -275,7 +280,8 @@ int ph_autotune(ph_inst* k, const void* x, void* y, int64_t R, void* stream, ph_
 
 /* Record instantiation + MVM of instance k as one HIP graph: theta vectors, far and near
  * instantiation of all T slots, then y = (K~ + nugget I) x for R right-hand sides (alpha
- * 1, beta 0), with the near field on the instance's second stream.  x, y (device) are
+ * 1, beta 0).  The near field runs on the recording stream, or on the instance's second
+ * stream (concurrently with the far field) when ph_autotune selected that.  x, y (device) are
  * bound into the graph.  stream must not be the null stream.  Runs one MVM first to
  * allocate all scratch; afterwards the instance's scratch is fixed (a ph_matvec that
  * would need more fails with PH_ESTATE) until every graph of the instance is freed.
@@ -285,7 +291,10 @@ int ph_graph_create(ph_inst* k, const void* x, void* y, int64_t R, double nugget
 
 /* Replay a recorded graph: with theta != NULL (host, T x d_theta, checked against Theta
  * as ph_instantiate does) the instance is re-instantiated at these values, else at the
- * last ones.  One graph launch on `stream`; asynchronous (the host waits only for the
+ * last ones.  The replay is ordered after every earlier call on the instance (a near-field
+ * instantiation still running on its second stream is joined first).  An instance with
+ * live graphs cannot be re-instantiated as the other kind (ph_instantiate after
+ * ph_instantiate_grad or the reverse: PH_ESTATE).  One graph launch on `stream`; asynchronous (the host waits only for the
  * previous launch's read of its theta staging buffer). */
 int ph_graph_launch(ph_graph* g, const double* theta, void* stream);
 void ph_graph_free(ph_graph* g);

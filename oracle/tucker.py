@@ -15,6 +15,17 @@ the max norm by a heuristic.  Here it is a relative Frobenius-norm bound: each
 of the N modes keeps the smallest rank r with
     sum_{j > r} s_j^2 <= (tol^2 / N) * ||M||_F^2,
 which gives ||M - M_hat||_F <= tol * ||M||_F for the truncated HOSVD.
+
+Reading of the cut: the leading-r subspace of a matrix is unique only when
+s_r > s_{r+1}, and a backward-stable SVD determines it to about
+eps ||A|| / (s_r - s_{r+1}).  Tensors with symmetric geometry (a translation
+class whose offset is symmetric under swapping two axes) have exactly
+degenerate singular pairs, and the rule above can cut between the two members
+of a pair; two correct SVD routines then keep different vectors of the pair and
+their truncations differ by about s_r.  So the cut is moved past every
+following singular value within relative CLUSTER_GAP of the last one kept: a
+cluster of (numerically) equal singular values is kept or dropped as a whole,
+which only ever raises the rank and keeps the bound above.
 """
 
 import numpy as np
@@ -31,15 +42,24 @@ def mode_product(T, A, m):
     return np.moveaxis(out, 0, m)
 
 
+CLUSTER_GAP = 1e-4
+
+
 def truncation_rank(s, thr):
-    """Smallest r >= 0 with sum_{j >= r} s_j^2 <= thr (0-based tail)."""
-    s2 = np.asarray(s, dtype=np.float64) ** 2
+    """Smallest r >= 0 with sum_{j >= r} s_j^2 <= thr (0-based tail), moved past every
+    following singular value s_r with s_{r-1} - s_r <= CLUSTER_GAP * s_{r-1}."""
+    s = np.asarray(s, dtype=np.float64)
+    s2 = s ** 2
     # tail[r] = sum_{j >= r} s2[j], summed from the smallest value upward
     tail = np.concatenate([np.cumsum(s2[::-1])[::-1], [0.0]])
-    for r in range(len(tail)):
-        if tail[r] <= thr:
-            return r
-    return len(s2)
+    r = len(s2)
+    for q in range(len(tail)):
+        if tail[q] <= thr:
+            r = q
+            break
+    while 0 < r < len(s) and s[r - 1] - s[r] <= CLUSTER_GAP * s[r - 1]:
+        r += 1
+    return r
 
 
 def thosvd(T, tol):

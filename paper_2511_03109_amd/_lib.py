@@ -44,7 +44,7 @@ class ModelInfo(C.Structure):
                 ("near_rank_mean", C.c_double), ("near_rank_max", C.c_int),
                 ("far_rank_mean", C.c_double), ("far_rank_max", C.c_int),
                 ("device_bytes", C.c_int64), ("kernel_evals", C.c_int64), ("P", C.c_int),
-                ("p_theta", C.c_int), ("d_theta", C.c_int)]
+                ("p_theta", C.c_int), ("d_theta", C.c_int), ("svd_sweeps_max", C.c_int)]
 
 
 class TraceStats(C.Structure):

@@ -16,7 +16,10 @@
 //    e = i + j n_s.
 //  * Compression: truncated HOSVD (Tucker) over the grouped modes; per mode the
 //    smallest rank r with sum_{j>r} s_j^2 <= (tol^2 / N) ||M||_F^2 (N = number of
-//    modes), giving ||M - M^||_F <= tol ||M||_F.  Singular values and vectors of
+//    modes), giving ||M - M^||_F <= tol ||M||_F.  The cut never splits a cluster of
+//    equal singular values (s_r - s_{r+1} <= 1e-4 s_r): the kept subspace is then
+//    unique, so any backward-stable SVD keeps the same one (symmetric geometry gives
+//    exactly degenerate pairs).  Singular values and vectors of
 //    each unfolding come from a Householder QR of the tall orientation followed by a
 //    one-sided (Hestenes) Jacobi SVD of the small triangular factor.
 //  * Symmetry: kappa(x, y) = kappa(y, x), so A_{ts} is A_{st} with the pair index
@@ -99,13 +102,18 @@ void apply_q(const double* A, int64_t m, int k, const double* tau, double* Y, in
   }
 }
 
+constexpr int JACOBI_MAX_SWEEPS = 80;
+
 // One-sided Jacobi SVD of the k x k matrix W (overwritten): W V = U S.
-// Outputs s (descending), U and V (k x k column-major).
-void jacobi_svd(double* W, int k, double* s, double* U, double* V) {
+// Outputs s (descending), U and V (k x k column-major).  Returns the number of sweeps
+// that rotated; JACOBI_MAX_SWEEPS + 1 when the last allowed sweep still rotated (not
+// converged).
+int jacobi_svd(double* W, int k, double* s, double* U, double* V) {
   std::vector<double> Vw((size_t)k * k, 0.0);
   for (int i = 0; i < k; ++i) Vw[(size_t)i * k + i] = 1.0;
   const double eps = 2.220446049250313e-16;
-  for (int sweep = 0; sweep < 80; ++sweep) {
+  int sweeps = 0;
+  for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
     bool rotated = false;
     for (int p = 0; p < k - 1; ++p) {
       for (int q = p + 1; q < k; ++q) {
@@ -139,6 +147,7 @@ void jacobi_svd(double* W, int k, double* s, double* U, double* V) {
       }
     }
     if (!rotated) break;
+    sweeps = sweep + 1 == JACOBI_MAX_SWEEPS ? JACOBI_MAX_SWEEPS + 1 : sweep + 1;
   }
   std::vector<double> nrm(k);
   for (int j = 0; j < k; ++j) {
@@ -157,15 +166,24 @@ void jacobi_svd(double* W, int k, double* s, double* U, double* V) {
       V[(size_t)jj * k + i] = Vw[(size_t)j * k + i];
     }
   }
+  return sweeps;
 }
 
-// Smallest r >= 0 with sum_{j >= r} s_j^2 <= thr (tail summed from the smallest value up).
+// Smallest r >= 0 with sum_{j >= r} s_j^2 <= thr (tail summed from the smallest value up),
+// then moved past every following s_r with s_{r-1} - s_r <= CLUSTER_GAP s_{r-1}: a cluster of
+// equal singular values is kept or dropped as a whole.
+constexpr double CLUSTER_GAP = 1e-4;
 int truncation_rank(const double* s, int k, double thr) {
   std::vector<double> tail(k + 1, 0.0);
   for (int j = k - 1; j >= 0; --j) tail[j] = tail[j + 1] + s[j] * s[j];
-  for (int r = 0; r <= k; ++r)
-    if (tail[r] <= thr) return r;
-  return k;
+  int r = k;
+  for (int q = 0; q <= k; ++q)
+    if (tail[q] <= thr) {
+      r = q;
+      break;
+    }
+  while (r > 0 && r < k && s[r - 1] - s[r] <= CLUSTER_GAP * s[r - 1]) ++r;
+  return r;
 }
 
 // Left singular vectors (first r columns) and singular values of the m x q matrix X
@@ -175,6 +193,7 @@ struct LeftSV {
   std::vector<double> s;  // kk
   int64_t m = 0;
   int kk = 0;
+  int sweeps = 0;   // Jacobi sweeps (JACOBI_MAX_SWEEPS + 1: not converged)
 };
 
 // X column-major m x q (leading dimension m).
@@ -190,7 +209,7 @@ LeftSV left_sv(const double* X, int64_t m, int64_t q) {
     for (int c = 0; c < k; ++c)
       for (int i = 0; i <= c; ++i) R[(size_t)c * k + i] = A[(size_t)c * m + i];
     out.s.resize(k);
-    jacobi_svd(R.data(), k, out.s.data(), UR.data(), VR.data());
+    out.sweeps = jacobi_svd(R.data(), k, out.s.data(), UR.data(), VR.data());
     out.U.assign((size_t)m * k, 0.0);
     for (int c = 0; c < k; ++c)
       for (int i = 0; i < k; ++i) out.U[(size_t)c * m + i] = UR[(size_t)c * k + i];
@@ -207,7 +226,7 @@ LeftSV left_sv(const double* X, int64_t m, int64_t q) {
     for (int c = 0; c < k; ++c)
       for (int i = 0; i <= c; ++i) R[(size_t)c * k + i] = A[(size_t)c * q + i];
     out.s.resize(k);
-    jacobi_svd(R.data(), k, out.s.data(), UR.data(), VR.data());
+    out.sweeps = jacobi_svd(R.data(), k, out.s.data(), UR.data(), VR.data());
     out.U = VR;
     out.kk = k;
   }
@@ -253,6 +272,7 @@ struct Tucker {
   std::vector<std::vector<double>> factors;  // column-major n[m] x r[m]
   std::vector<int> ranks;
   std::vector<double> core;                  // column-major r[0] x r[1] x ...
+  int sweeps = 0;                            // most Jacobi sweeps of any mode
 };
 
 // Truncated HOSVD of the column-major tensor T with dims n.
@@ -274,6 +294,7 @@ Tucker thosvd(const std::vector<double>& T, const std::vector<int64_t>& n, doubl
       sv = left_sv(X.data(), n[m], rest);
     }
     int r = normsq == 0.0 ? 0 : truncation_rank(sv.s.data(), sv.kk, thr);
+    out.sweeps = std::max(out.sweeps, sv.sweeps);
     out.ranks.push_back(r);
     out.factors.emplace_back(sv.U.begin(), sv.U.begin() + (size_t)n[m] * r);
   }
@@ -450,6 +471,7 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
     dims.push_back(P);
     ftuck[ci] = thosvd(M, dims, o.tol);
   }
+  for (const Tucker& tk : ftuck) m->svd_sweeps_max = std::max(m->svd_sweeps_max, tk.sweeps);
   for (int64_t ci = 0; ci < nfc; ++ci) {
     ClassStored& cs = m->cstore[ci];
     Tucker& tk = ftuck[ci];
@@ -551,6 +573,10 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
     else { dims.push_back(pt); dims.push_back(pt); }
     ntuck[bi] = thosvd(A, dims, o.tol);
   }
+  for (const Tucker& tk : ntuck) m->svd_sweeps_max = std::max(m->svd_sweeps_max, tk.sweeps);
+  if (m->svd_sweeps_max > JACOBI_MAX_SWEEPS)
+    fail(PH_EUNSUPPORTED, "ph_offline_compress: a one-sided Jacobi SVD was still rotating after " +
+                              std::to_string(JACOBI_MAX_SWEEPS) + " sweeps (not converged)");
   {
     size_t totP = 0, totC = 0, totT = 0;
     for (int64_t bi = 0; bi < nst; ++bi) {

@@ -45,6 +45,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   m->n_stored_cls = (int64_t)hm.cstore.size();
   m->kernel_evals = hm.kernel_evals;
   m->near_factor_entries = hm.near_factor_entries;
+  m->svd_sweeps_max = hm.svd_sweeps_max;
 
   // stored near blocks (s <= t): offsets of the instantiated blocks (rows padded to 16)
   std::vector<int64_t> doff(hm.nstore.size() + 1, 0);
@@ -507,6 +508,9 @@ int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype
       in = (*inout)->p;
       need(in && in->m.get() == &md && in->T == T && in->dt == dt,
            "instance does not match (model, T, dtype)");
+      // a recorded graph replays the theta-vector launch with the flag it was recorded with
+      if (in->graphs > 0 && dim != in->grad_dim)
+        ph::fail(PH_ESTATE, "instance has recorded graphs; it cannot switch between K~ and dK~/dtheta");
       in->grad_dim = dim;
     } else {
       in = std::make_shared<ph::InstData>();
@@ -637,6 +641,7 @@ int ph_model_info_get(const ph_model* m, ph_model_info* info) {
     info->P = d.P;
     info->p_theta = d.p_theta;
     info->d_theta = d.d_theta;
+    info->svd_sweeps_max = d.svd_sweeps_max;
   });
 }
 
@@ -865,6 +870,9 @@ int ph_graph_launch(ph_graph* g, const double* theta, void* stream) {
       in.theta.assign(theta, theta + (size_t)in.T * md.d_theta);
     }
     hipStream_t st = (hipStream_t)stream;
+    // a near-field instantiation of an eager call may still run on the second stream; the
+    // replay rewrites the theta vectors and the near blocks it reads
+    ph::join_near(in, st);
     PH_HIP(hipGraphLaunch(g->exec, st));
     PH_HIP(hipEventRecord(in.ev_theta, st));
     in.theta_pending = true;

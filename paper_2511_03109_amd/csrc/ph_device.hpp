@@ -148,6 +148,7 @@ struct DeviceModel {
   int64_t near_factor_entries = 0, kernel_evals = 0;
   double near_rank_mean = 0, far_rank_mean = 0;
   int near_rank_max = 0, far_rank_max = 0;
+  int svd_sweeps_max = 0;
   std::vector<int32_t> near_rank_canon;   // per canonical near block (-1 if transposed copy)
   std::vector<int32_t> class_ranks;       // per class, 2 + d_theta entries
   std::vector<int64_t> D_off_host;        // per canonical near block: offset of its stored block

@@ -92,6 +92,7 @@ struct HostModel {
   std::vector<int32_t> class_src, class_tr; // per class: stored index, transposed?
   int64_t kernel_evals = 0;
   int64_t near_factor_entries = 0;
+  int svd_sweeps_max = 0;   // most one-sided Jacobi sweeps any SVD of the stage needed
 };
 
 std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts& o);

@@ -63,6 +63,34 @@ def test_tensor_lagrange_little_endian():
     assert nodes[1 + 2 * 3, 0] == n1[1] and nodes[1 + 2 * 3, 1] == n2[2]
 
 
+@pytest.mark.parametrize("l", [0.05, 0.137, 0.5, 2.0])
+def test_workload_kernels_match_sklearn(l):
+    """The closed forms of the workloads against scikit-learn's Gaussian-process kernels:
+    RBF(l) = exp(-r^2 / (2 l^2)), Matern(l, nu=1.5) = (1 + sqrt3 r / l) exp(-sqrt3 r / l),
+    Matern(l, nu=0.5) = exp(-r / l) (the paper's E kernel), and RBF([l1, l2]) for one
+    length scale per axis; distances include r = 0.  Bound: 16 ulp of 1 (scikit-learn
+    scales the points by 1 / l before taking distances, a different rounding order; a
+    wrong constant or exponent would differ by 1e-3 or more)."""
+    from sklearn.gaussian_process.kernels import Matern, RBF
+    atol = 16 * np.finfo(float).eps
+    g = np.random.default_rng(17)
+    for d in (1, 2, 3):
+        X = g.random((40, d))
+        Y = np.concatenate([g.random((39, d)), X[:1]])            # one pair at r = 0
+        Xb, Yb = X[:, None, :], Y[None, :, :]
+        th = np.array([l])
+        np.testing.assert_allclose(kernels.gaussian(Xb, Yb, th), RBF(l)(X, Y), rtol=0, atol=atol)
+        np.testing.assert_allclose(kernels.matern32(Xb, Yb, th), Matern(l, nu=1.5)(X, Y), rtol=0, atol=atol)
+        np.testing.assert_allclose(kernels.matern12(Xb, Yb, th), Matern(l, nu=0.5)(X, Y), rtol=0, atol=atol)
+        assert kernels.gaussian(X[0], X[0], th) == 1.0 and kernels.matern32(X[0], X[0], th) == 1.0
+        assert kernels.matern12(X[0], X[0], th) == 1.0
+    X = g.random((40, 2))
+    Y = g.random((35, 2))
+    ls = np.array([l, 0.7 * l + 0.01])
+    np.testing.assert_allclose(kernels.aniso_gaussian(X[:, None, :], Y[None, :, :], ls), RBF(ls)(X, Y),
+                               rtol=0, atol=atol)
+
+
 # ---------------------------------------------------------------- cluster tree
 def _pts(n, d, seed=0):
     return np.random.default_rng(seed).random((n, d))
@@ -202,6 +230,27 @@ def test_truncation_rank_rule():
     assert tucker.truncation_rank(s, 100.0) == 0
 
 
+def test_truncation_keeps_clusters_of_equal_singular_values():
+    """The cut never splits singular values within relative 1e-4 (the kept subspace of a
+    cut inside such a cluster is not unique)."""
+    s = np.array([4.0, 2.0, 1.0, 1.0 - 1e-12, 0.01])
+    assert tucker.truncation_rank(s, 1.5) == 4          # plain rule: 3 (inside the pair)
+    s = np.array([4.0, 2.0, 1.0, 0.9, 0.01])
+    assert tucker.truncation_rank(s, 1.5) == 3          # a real gap is cut as before
+    # the truncation of a matrix with a degenerate pair is the unique best approximation
+    # that keeps the whole pair, independent of the basis the SVD picks inside it
+    g = np.random.default_rng(6)
+    Q1 = np.linalg.qr(g.standard_normal((40, 6)))[0]
+    Q2 = np.linalg.qr(g.standard_normal((30, 6)))[0]
+    sv = np.array([4.0, 2.0, 1.0, 1.0, 1e-3, 1e-9])
+    A = Q1 @ np.diag(sv) @ Q2.T
+    tol = np.sqrt(2.0 * 1.5) / np.linalg.norm(sv)        # per-mode threshold 1.5 (plain cut at 3)
+    core, facs, _ = tucker.thosvd(A, tol)
+    assert [f.shape[1] for f in facs] == [4, 4]
+    ref = Q1[:, :4] @ np.diag(sv[:4]) @ Q2[:, :4].T
+    np.testing.assert_allclose(tucker.reconstruct(core, facs), ref, atol=1e-13)
+
+
 def test_thosvd_bound_and_exact_ranks():
     g = np.random.default_rng(3)
     # exactly multilinear rank (2, 3, 2) tensor (each rank <= product of the others)
@@ -265,6 +314,22 @@ def test_untruncated_mvm_equals_plain_interpolant(d, n, l, eta2, p_s):
     assert np.max(np.abs(y - K0 @ x)) <= 1e-12 * np.max(np.abs(K0 @ x))
     if n <= 1500:
         np.testing.assert_allclose(m.dense(inst), K0, atol=1e-13)
+
+
+def test_nugget_added_in_the_mvm():
+    """(K~ + c I) x: the nugget adds c x to the product (rounding aside), and at tol = 0 the
+    MVM with a nugget equals the plain interpolant plus c times the identity, densely."""
+    m = _model(n=700, d=2, l=3, eta2=2, p_s=5, tol=0.0)
+    x = np.random.default_rng(3).standard_normal((700, 2))
+    inst = m.instantiate(0.31)
+    c = 0.037
+    y0 = m.matvec(inst, x)
+    yc = m.matvec(inst, x, nugget=c)
+    eps = np.finfo(float).eps
+    assert np.all(np.abs((yc - y0) - c * x) <= 4 * eps * (np.abs(y0) + np.abs(c * x)))
+    K = m.plain_dense(0.31) + c * np.eye(700)
+    ref = K @ x
+    assert np.max(np.abs(yc - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
 @pytest.mark.parametrize("tol", [0.0, 1e-8])
