@@ -126,9 +126,19 @@ def cpu_baseline(w, X, l_max, thetas, x_host, sample_leaves=160):
         est.append((tb - ta) * scale + (tc - tb) + (td - tc) + per_leaf_mvm * scale)
         measured += te - ta
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": float(np.mean(est)) * 1e3, "unit": "ms per theta (instantiate + MVM, 16 RHS), extrapolated",
-        "cores": int(threads), "kind": "oracle",
+        "cores": int(threads), "kind": "oracle", "cpu_model": cpu_model,
+        "host_cpus_visible": len(os.sched_getaffinity(0)),
         "sample": f"{sample_leaves} of {nleaf} target leaves ({len(rows)} rows, {len(near)} near blocks) for "
                   f"each of {len(thetas)} theta, all {len(all_keys)} far couplings, full upward pass; "
                   f"per-leaf work scaled by {scale:.0f}x; measured {measured:.1f} s of oracle work",
@@ -338,7 +348,6 @@ def main():
 
     import torch
 
-    from oracle import tree as otree  # noqa: F401  (only for l_max derivation parity)
     from paper_2511_03109_amd import _lib, api, inputs
 
     if not torch.cuda.is_available():
@@ -370,9 +379,8 @@ def main():
         step()
     torch.cuda.synchronize()
     lib = _lib.lib()
-    stats = _lib.TraceStats()
-    lib.ph_trace_read(stats, 1)
-    lib.ph_trace_enable(1)
+    # the headline: K steps with tracing off, bracketed by events on the stream every launch
+    # of the step uses (the library's default runs the whole step on the caller's stream)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -381,32 +389,23 @@ def main():
         step()
     ev1.record(stream)
     torch.cuda.synchronize()
-    lib.ph_trace_enable(0)
-    _lib.check(lib.ph_trace_read(stats, 1), "ph_trace_read")
     total_ms = ev0.elapsed_time(ev1)
     ms_step = total_ms / args.steps
-    # the same step once more with the near field on the caller's stream (no overlap), to
-    # report each kernel's own duration beside its duration while sharing the GPU
-    os.environ["PH_SERIAL_MVM"] = "1"
-    for _ in range(2):
-        step()
-    torch.cuda.synchronize()
-    iso_stats = _lib.TraceStats()
-    lib.ph_trace_read(iso_stats, 1)
+    # per-kernel durations: a separate pass with an event pair around every launch
+    stats = _lib.TraceStats()
+    lib.ph_trace_read(stats, 1)
     lib.ph_trace_enable(1)
-    iso_steps = 3
-    for _ in range(iso_steps):
+    trace_steps = max(3, min(args.steps, 10))
+    for _ in range(trace_steps):
         step()
     torch.cuda.synchronize()
     lib.ph_trace_enable(0)
-    _lib.check(lib.ph_trace_read(iso_stats, 1), "ph_trace_read")
-    del os.environ["PH_SERIAL_MVM"]
-    iso_stage = {name: iso_stats.ms[i] / max(iso_stats.count[i], 1) for i, name in enumerate(_lib.STAGES)}
+    _lib.check(lib.ph_trace_read(stats, 1), "ph_trace_read")
     per_stage = {name: {"ms_total": stats.ms[i], "launches": stats.count[i],
                         "ms_avg": stats.ms[i] / max(stats.count[i], 1)}
                  for i, name in enumerate(_lib.STAGES)}
-    inst_ms = sum(per_stage[k]["ms_total"] for k in ("theta", "far_inst", "near_inst")) / args.steps
-    mvm_ms = sum(per_stage[k]["ms_total"] for k in _lib.STAGES[3:]) / args.steps  # sum of kernel times (streams overlap)
+    inst_ms = sum(per_stage[k]["ms_total"] for k in ("theta", "far_inst", "near_inst")) / trace_steps
+    mvm_ms = sum(per_stage[k]["ms_total"] for k in _lib.STAGES[3:]) / trace_steps
 
     # Roofline of the hot kernels, from algorithmic work per launch (all T slots) and the
     # average launch time measured above with HIP events on the launching stream.
@@ -436,14 +435,8 @@ def main():
         roof[kname] = {"bound": bound, "kernel": kname, "achieved": ach, "peak": peak, "unit": unit,
                        "frac": ach / peak, "traffic": measured_traffic(kname),
                        "algorithmic_per_launch": work, "avg_launch_ms": ms,
-                       "ms_per_step": per_stage[stage]["ms_total"] / args.steps}
+                       "ms_per_step": per_stage[stage]["ms_total"] / trace_steps}
     dominant = max(roof, key=lambda k: roof[k]["ms_per_step"])
-    roof_iso = {}
-    for kname, (stage, bound, work) in kernels.items():
-        ms = iso_stage[stage]
-        ach = work / (ms * 1e-3) / (1e9 if bound == "hbm" else 1e12)
-        roof_iso[kname] = {"avg_launch_ms": ms, "achieved": ach, "frac": ach / roof[kname]["peak"],
-                           "unit": roof[kname]["unit"]}
     # whole-step algorithmic bytes per theta (near factors once per step, D write + read,
     # couplings, vectors)
     step_bytes = (8.0 * mi["near_factor_entries"] + T * 8.0 * (2 * stored
@@ -465,7 +458,6 @@ def main():
         "stages": per_stage,
         "roofline": roof[dominant],
         "kernels": roof,
-        "kernels_isolated": roof_iso,
         "model": {"near_entries": mi["near_entries"], "near_factor_entries": mi["near_factor_entries"],
                   "near_rank_mean": mi["near_rank_mean"], "far_rank_mean": mi["far_rank_mean"],
                   "classes": ncls, "far_blocks": tree.info["n_far"], "near_blocks": tree.info["n_near"],
