@@ -111,9 +111,36 @@ constexpr int JACOBI_MAX_SWEEPS = 80;
 int jacobi_svd(double* W, int k, double* s, double* U, double* V) {
   std::vector<double> Vw((size_t)k * k, 0.0);
   for (int i = 0; i < k; ++i) Vw[(size_t)i * k + i] = 1.0;
-  const double eps = 2.220446049250313e-16;
+  // rotation threshold: the rounding level of a k-term inner product (sqrt(k) eps); with eps
+  // alone a pair whose cosine sits at its own rounding noise can keep rotating
+  const double tol = std::sqrt((double)k) * 2.220446049250313e-16;
   int sweeps = 0;
+  std::vector<double> cn(k), tmp((size_t)k * k);
+  std::vector<int> ord(k);
   for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
+    // de Rijk's ordering: columns by decreasing norm at the start of every sweep, so that
+    // the large singular directions are separated first (graded matrices, whose small
+    // columns are otherwise rotated against noise for many sweeps)
+    for (int j = 0; j < k; ++j) {
+      double a = 0;
+      for (int i = 0; i < k; ++i) a += W[(size_t)j * k + i] * W[(size_t)j * k + i];
+      cn[j] = a;
+    }
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cn[a] > cn[b]; });
+    bool perm = false;
+    for (int j = 0; j < k; ++j) perm |= ord[j] != j;
+    if (perm) {
+      for (double* M : {W, Vw.data()}) {
+        for (int j = 0; j < k; ++j)
+          std::copy(M + (size_t)ord[j] * k, M + (size_t)ord[j] * k + k, tmp.data() + (size_t)j * k);
+        std::copy(tmp.begin(), tmp.end(), M);
+      }
+    }
+    // columns below eps times the largest are at the rounding level of the factorisation
+    // (their squared norms can underflow): they are not rotated
+    const double cmax = *std::max_element(cn.begin(), cn.end());
+    const double small = 4.930380657631324e-32 * cmax;   // eps^2 cmax
     bool rotated = false;
     for (int p = 0; p < k - 1; ++p) {
       for (int q = p + 1; q < k; ++q) {
@@ -125,8 +152,8 @@ int jacobi_svd(double* W, int k, double* s, double* U, double* V) {
           be += wq[i] * wq[i];
           ga += wp[i] * wq[i];
         }
-        if (al == 0.0 || be == 0.0) continue;
-        if (std::fabs(ga) <= eps * std::sqrt(al * be)) continue;
+        if (al <= small || be <= small) continue;
+        if (std::fabs(ga) <= tol * std::sqrt(al) * std::sqrt(be)) continue;
         rotated = true;
         double zeta = (be - al) / (2.0 * ga);
         double t = std::copysign(1.0, zeta) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));

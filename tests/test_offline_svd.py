@@ -21,6 +21,7 @@ import numpy as np
 import pytest
 
 from oracle import hmat, kernels, tucker
+from paper_2511_03109_amd import inputs
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -157,3 +158,40 @@ def test_jacobi_reports_convergence_on_random_matrices(harness):
         assert 1 <= sweeps <= 40
         k = min(m, q)
         np.testing.assert_allclose(U.T @ U, np.eye(k), atol=1e-13)
+
+
+def test_jacobi_converges_on_graded_and_underflowing_unfoldings(harness):
+    """Two unfoldings on which the one-sided Jacobi iteration used to rotate until its sweep
+    cap: a 3-D Matern-1/2 far class whose singular values span 12 orders of magnitude (pairs
+    whose cosine sits at the rounding noise of a 64-term inner product), and a near tensor of
+    the anisotropic Gaussian whose smallest singular value is ~1e-160 (squared column norms
+    underflow).  With sqrt(k) eps as the rotation threshold and columns below eps times the
+    largest left alone, both converge in a few sweeps and still match LAPACK."""
+    X = np.random.default_rng([5, 3, 1100]).random((1100, 3))
+    om = hmat.PH2(X, l_max=2, eta2=Fraction(3), kernel=kernels.matern12, theta_lo=[0.05], theta_hi=[0.5],
+                  p_s=4, p_theta=7, tol=1e-8)
+    mats = []
+    for key in range(len(om.classes)):
+        M = om.far_tensor_of_block(om.class_rep[key])
+        A = tucker.unfold(M, 2)
+        s = np.linalg.svd(A, compute_uv=False)
+        if s[-1] < 1e-11 * s[0]:
+            mats.append(A)
+    Xm = inputs.points_for(3, 3000)
+    om2 = hmat.PH2(Xm, l_max=4, eta2=Fraction(2), kernel=kernels.aniso_gaussian, theta_lo=[0.05, 0.05],
+                   theta_hi=[0.5, 0.5], p_s=5, p_theta=7, tol=1e-8)
+    for bi, (s_, u_) in enumerate(om2.near):
+        if s_ > u_:
+            continue
+        A = tucker.unfold(om2.near_tensor(s_, u_), 1)
+        sv = np.linalg.svd(A, compute_uv=False)
+        if sv[-1] < 1e-100 * sv[0]:
+            mats.append(A)
+    assert len(mats) >= 3
+    for A in mats:
+        s_lib, U, sweeps = _lib_left_sv(harness, A)
+        s_np = np.linalg.svd(A, compute_uv=False)
+        print(f"{A.shape}: sweeps {sweeps}, s_min/s_max {s_np[-1] / s_np[0]:.1e}, "
+              f"singular values vs LAPACK {np.max(np.abs(s_lib - s_np)) / s_np[0]:.1e}")
+        assert sweeps <= 30
+        assert np.max(np.abs(s_lib - s_np)) <= 1e-13 * s_np[0]
