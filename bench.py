@@ -32,6 +32,7 @@ KERNEL_SOURCES = {
     "k_coupling": ["k_matvec.hip", "ph_device.hpp"],
     "k_near_mvm": ["k_matvec.hip", "ph_device.hpp"],
     "k_near_instantiate": ["k_instantiate.hip", "ph_device.hpp"],
+    "k_near_fused": ["k_near_fused.hip", "ph_device.hpp"],
 }
 
 
@@ -168,6 +169,61 @@ def _timed(fn, steps, warmup):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps * 1e3
+
+
+def step_legs(model, thetas, x_host, T, R, y64, args):
+    """The same work in other forms, each timed like the headline (events around K steps
+    after W warm-up steps): FP64 one theta at a time (T = 1 instances, near blocks in
+    memory), FP64 batched with the near blocks in memory, FP32 and BF16 batched.  Each
+    low-precision result's relative error is taken against the FP64 headline output y64
+    (which matches the oracle to 1e-12)."""
+    import torch
+    from paper_2511_03109_amd import api
+    steps, warmup = max(3, min(args.steps, 10)), max(1, args.warmup)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    legs = {}
+    x64 = torch.tensor(np.ascontiguousarray(x_host), device="cuda")
+    # one theta at a time: T separate instances of one slot each
+    singles = [api.Instance(model, thetas[t:t + 1]) for t in range(T)]
+    ys = torch.empty_like(x64)
+
+    def per_theta():
+        for t in range(T):
+            singles[t].reinstantiate(thetas[t:t + 1])
+            singles[t].matvec(x64[t], ys[t])
+    ms = timed(per_theta)
+    legs["fp64_one_theta_at_a_time"] = {"ms_per_theta": ms / T, "near_field": "blocks in memory", "T": 1,
+                                        "rel_error_vs_headline": float((ys - y64).norm() / y64.norm())}
+    del singles
+    ib = api.Instance(model, thetas, near="blocks")
+    yb = torch.empty_like(x64)
+    ms = timed(lambda: (ib.reinstantiate(thetas), ib.matvec(x64, yb)))
+    legs["fp64_batched_blocks_in_memory"] = {"ms_per_theta": ms / T, "T": T,
+                                             "rel_error_vs_headline": float((yb - y64).norm() / y64.norm())}
+    del ib, yb
+    torch.cuda.empty_cache()
+    x32 = x64.float()
+    for dt in ("f32", "bf16"):
+        inst = api.Instance(model, thetas, dtype=dt)
+        yl = torch.empty_like(x32)
+        ms = timed(lambda: (inst.reinstantiate(thetas), inst.matvec(x32, yl)))
+        legs[dt + "_batched"] = {"ms_per_theta": ms / T, "T": T, "factored": inst.factored,
+                                 "rel_error_vs_fp64": float((yl.double() - y64).norm() / y64.norm())}
+        del inst, yl
+        torch.cuda.empty_cache()
+    return legs
 
 
 def mode_precision(args):
@@ -319,6 +375,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-leaves", type=int, default=160)
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the comparison legs (per-theta FP64, near blocks in memory, FP32, BF16)")
     ap.add_argument("--mode", default="step", choices=["step", "precision", "cg", "grad", "sweep"],
                     help="step (default): the benchmark step; precision: FP64 / FP32 / BF16 instances of "
                          "the same step; cg: (K + 1e-2 I) a = y at n = 262144 by FP64 CG and by FP64 "
@@ -369,6 +427,7 @@ def main():
     x = torch.tensor(np.ascontiguousarray(x_host), device="cuda")
     y = torch.empty_like(x)
     inst = api.Instance(model, thetas)
+    factored = inst.factored
     stream = torch.cuda.current_stream()
 
     def step():
@@ -417,14 +476,23 @@ def main():
     nd = tree.nodes()
     leaf_sizes = (nd["end"] - nd["begin"])[nd["level"] == tree.info["l_max"]]
     stored = (mi["near_entries"] + float(np.sum(leaf_sizes.astype(np.float64) ** 2))) / 2.0
-    kernels = {
-        # each stored factor entry P_b[k][e] read once, each stored block entry written once per slot
-        "k_near_instantiate": ("near_inst", "hbm", 8.0 * mi["near_factor_entries"] + 8.0 * T * stored),
-        # each stored block entry read once per slot (it serves D_st and D_ts), x and y once
-        "k_near_mvm": ("near_mvm", "hbm", 8.0 * T * (stored + 2.0 * n * R)),
-        # y_hat_s += C x_hat_t for every far block: 2 P^2 R flops per block and slot
-        "k_coupling": ("coupling", "mfma", 2.0 * P * P * R * nfar * T),
-    }
+    if factored:
+        kernels = {
+            # each stored factor entry P_b[k][e] read once per batch of 8 slots, x read and y
+            # written once per slot
+            "k_near_fused": ("near_mvm", "hbm", 8.0 * mi["near_factor_entries"] * ((T + 7) // 8)
+                             + 8.0 * T * 2.0 * n * R),
+            "k_coupling": ("coupling", "mfma", 2.0 * P * P * R * nfar * T),
+        }
+    else:
+        kernels = {
+            # each stored factor entry P_b[k][e] read once, each stored block entry written once per slot
+            "k_near_instantiate": ("near_inst", "hbm", 8.0 * mi["near_factor_entries"] + 8.0 * T * stored),
+            # each stored block entry read once per slot (it serves D_st and D_ts), x and y once
+            "k_near_mvm": ("near_mvm", "hbm", 8.0 * T * (stored + 2.0 * n * R)),
+            # y_hat_s += C x_hat_t for every far block: 2 P^2 R flops per block and slot
+            "k_coupling": ("coupling", "mfma", 2.0 * P * P * R * nfar * T),
+        }
     roof = {}
     for kname, (stage, bound, work) in kernels.items():
         ms = per_stage[stage]["ms_avg"]
@@ -437,10 +505,11 @@ def main():
                        "algorithmic_per_launch": work, "avg_launch_ms": ms,
                        "ms_per_step": per_stage[stage]["ms_total"] / trace_steps}
     dominant = max(roof, key=lambda k: roof[k]["ms_per_step"])
-    # whole-step algorithmic bytes per theta (near factors once per step, D write + read,
-    # couplings, vectors)
-    step_bytes = (8.0 * mi["near_factor_entries"] + T * 8.0 * (2 * stored
+    # whole-step algorithmic bytes (near factors once per step, D write + read when the
+    # blocks are materialised, couplings, vectors)
+    step_bytes = (8.0 * mi["near_factor_entries"] + T * 8.0 * ((0 if factored else 2 * stored)
                   + 2 * ncls * P * P + 4 * n * R + 2 * tree.info["n_nodes"] * P * R))
+    legs = {} if args.no_legs else step_legs(model, thetas, x_host, T, R, y, args)
     out = {
         "metric": METRIC,
         "value": ms_step / T,
@@ -451,13 +520,15 @@ def main():
         "config": {"workload": w["name"], "n": n, "d": w["d"], "kernel": w["kernel"],
                    "theta_box": [w["theta_lo"][0], w["theta_hi"][0]], "p_s": w["p_s"],
                    "p_theta": w["p_theta"], "leaf": w["leaf"], "eta2": list(w["eta2"]),
-                   "tol": w["tol"], "T": T, "R": R, "l_max": tree.info["l_max"]},
+                   "tol": w["tol"], "T": T, "R": R, "l_max": tree.info["l_max"],
+                   "near_field": "factored (blocks formed inside the MVM)" if factored else "blocks in memory"},
         "ms_instantiate_per_theta": inst_ms / T,
         "ms_matvec_per_theta": mvm_ms / T,
         "step_algorithmic_GBps": step_bytes / (ms_step * 1e-3) / 1e9,
         "stages": per_stage,
         "roofline": roof[dominant],
         "kernels": roof,
+        "legs": legs,
         "model": {"near_entries": mi["near_entries"], "near_factor_entries": mi["near_factor_entries"],
                   "near_rank_mean": mi["near_rank_mean"], "far_rank_mean": mi["far_rank_mean"],
                   "classes": ncls, "far_blocks": tree.info["n_far"], "near_blocks": tree.info["n_near"],

@@ -211,6 +211,33 @@ void ph_model_free(ph_model* m);
 int ph_instantiate(const ph_model* m, const double* theta, int T, ph_dtype dt, void* stream,
                    ph_inst** inout);
 
+/* Form of the near field held by an instance (the far field is always instantiated).
+ *   PH_NEAR_BLOCKS    every near block D_b(theta_t) is written to device memory
+ *                     (T N_nf entries) and each ph_matvec reads the blocks.  Suited to many
+ *                     MVMs at few theta (e.g. a solver at one theta).
+ *   PH_NEAR_FACTORED  only the vectors c_b(theta_t) = core_b x_theta (Theta_k^T v_k) are
+ *                     formed (Sec. 4.3); each ph_matvec forms the blocks from the stored
+ *                     factors P_b in registers and applies them at once, reading every factor
+ *                     entry once for up to 8 slots, and no block is ever written.  D_b is
+ *                     linear in c_b, so this is the same matrix.  Suited to batches of theta
+ *                     with one or a few MVMs each.  In FP64 the blocks it forms are identical
+ *                     to those PH_NEAR_BLOCKS writes.  For PH_F32 / PH_BF16 instances the
+ *                     factors are streamed as an FP32 / BF16 copy (rounded to nearest, made
+ *                     once per model on the first such instance) and the blocks are formed in
+ *                     FP32.  Near ranks above 64: PH_EUNSUPPORTED.
+ *   PH_NEAR_AUTO      FACTORED when T >= 4 and the largest near rank is at most 64, else BLOCKS.
+ * ph_instantiate and ph_instantiate_grad use PH_NEAR_AUTO. */
+typedef enum { PH_NEAR_AUTO = 0, PH_NEAR_BLOCKS = 1, PH_NEAR_FACTORED = 2 } ph_near_mode;
+
+/* ph_instantiate (grad_dim = -1) or ph_instantiate_grad (grad_dim >= 0) with an explicit
+ * near-field form.  Re-instantiating an existing instance needs the same form (or
+ * PH_NEAR_AUTO), else PH_EINVAL. */
+int ph_instantiate_ex(const ph_model* m, const double* theta, int T, ph_dtype dt, ph_near_mode near,
+                      int grad_dim, void* stream, ph_inst** inout);
+
+/* *factored = 1 if the instance holds the factored near field, else 0. */
+int ph_inst_near_mode(const ph_inst* k, int* factored);
+
 /* As ph_instantiate, but the instance holds dK~/dtheta_dim at each theta: the
  * parametric vector of dimension dim is replaced by its derivative v_dim'(theta_dim)
  * (the approximation is linear in each v_k, so this is its exact derivative).
@@ -300,8 +327,9 @@ int ph_graph_launch(ph_graph* g, const double* theta, void* stream);
 void ph_graph_free(ph_graph* g);
 
 /* Inspection (tests): copy the instantiated near block of canonical near index b for
- * slot t (n_s x n_t column-major, as double) or the coupling matrix of class c
- * (P x P column-major, as double) to host memory.  Synchronises the device. */
+ * slot t (n_s x n_t column-major, as double; for a factored instance the block is formed
+ * by a kernel in the arithmetic of the MVM) or the coupling matrix of class c (P x P
+ * column-major, as double) to host memory.  Synchronises the device. */
 int ph_inst_near_block(const ph_inst* k, int t, int64_t b, double* host_out);
 int ph_inst_coupling(const ph_inst* k, int t, int64_t c, double* host_out);
 

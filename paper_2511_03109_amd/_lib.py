@@ -10,6 +10,7 @@ PH_OK, PH_EINVAL, PH_EDOMAIN, PH_ENOMEM, PH_EHIP, PH_ESTATE, PH_EUNSUPPORTED = 0
 KERNELS = {"gaussian": 0, "matern32": 1, "matern12": 2, "aniso_gaussian": 3, "poly_test": 4,
            "poly2_test": 5}
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2}
+NEAR_MODES = {"auto": 0, "blocks": 1, "factored": 2}
 
 
 class TreeOpts(C.Structure):
@@ -77,6 +78,8 @@ SIGNATURES = {
     "ph_model_free": ([_P], None),
     "ph_instantiate": ([_P, _DP, C.c_int, C.c_int, _P, C.POINTER(_P)], C.c_int),
     "ph_instantiate_grad": ([_P, _DP, C.c_int, C.c_int, C.c_int, _P, C.POINTER(_P)], C.c_int),
+    "ph_instantiate_ex": ([_P, _DP, C.c_int, C.c_int, C.c_int, C.c_int, _P, C.POINTER(_P)], C.c_int),
+    "ph_inst_near_mode": ([_P, C.POINTER(C.c_int)], C.c_int),
     "ph_matvec": ([_P, _P, _P, C.c_int64, C.c_double, C.c_double, C.c_double, _P], C.c_int),
     "ph_bilinear": ([_P, _P, _P, C.c_int64, _P, _P], C.c_int),
     "ph_cg_solve": ([_P, _P, _P, _P, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,

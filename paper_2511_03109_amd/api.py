@@ -127,10 +127,13 @@ class Model:
 class Instance:
     """An instantiated H^2-matrix for T parameter values (ph_instantiate / ph_instantiate_grad)."""
 
-    def __init__(self, model, theta, *, dtype="f64", grad_dim=None, stream=None):
+    def __init__(self, model, theta, *, dtype="f64", grad_dim=None, near="auto", stream=None):
+        """near: "auto", "blocks" (near blocks written to memory) or "factored" (near blocks
+        formed from the factors inside every MVM, never written); see ph_instantiate_ex."""
         self.model = model
         self._h = C.c_void_p()
         self.dtype = dtype
+        self.near = near
         th = self._theta(theta)
         self.T = th.shape[0]
         self._call(th, grad_dim, stream)
@@ -140,7 +143,12 @@ class Instance:
         return th
 
     def _call(self, th, grad_dim, stream):
-        if grad_dim is None:
+        if self.near != "auto":
+            code = L.lib().ph_instantiate_ex(self.model._h, _dptr(th), th.shape[0], L.DTYPES[self.dtype],
+                                             L.NEAR_MODES[self.near], -1 if grad_dim is None else grad_dim,
+                                             _stream(stream), C.byref(self._h))
+            L.check(code, "ph_instantiate_ex")
+        elif grad_dim is None:
             code = L.lib().ph_instantiate(self.model._h, _dptr(th), th.shape[0], L.DTYPES[self.dtype],
                                           _stream(stream), C.byref(self._h))
             L.check(code, "ph_instantiate")
@@ -148,6 +156,13 @@ class Instance:
             code = L.lib().ph_instantiate_grad(self.model._h, _dptr(th), th.shape[0], grad_dim,
                                                L.DTYPES[self.dtype], _stream(stream), C.byref(self._h))
             L.check(code, "ph_instantiate_grad")
+
+    @property
+    def factored(self):
+        """True if the instance holds the factored near field (no near blocks in memory)."""
+        f = C.c_int()
+        L.check(L.lib().ph_inst_near_mode(self._h, C.byref(f)), "ph_inst_near_mode")
+        return bool(f.value)
 
     def reinstantiate(self, theta, *, grad_dim=None, stream=None):
         """Re-instantiate in place (same T and dtype; no allocation)."""

@@ -260,6 +260,11 @@ void instantiate_impl(InstData& in, const double* theta, hipStream_t st) {
            (unsigned)m.n_stored_cls), dim3(NT), st, (const ClassDev*)m.cstore.p, (const double*)m.ff_chat.p,
            (const double*)m.ff_theta.p, (const double*)in.v.p, (S*)in.C.p, Cps, m.Pp, in.T, m.p_theta, m.d_theta);
   }
+  if (in.factored) {
+    // factored near field: only c_b(theta_t) per stored block (the MVM forms the blocks)
+    near_cores_launch<S>(in, st);
+    return;
+  }
   // The near-field blocks (HBM-bound, the bulk of the instantiation) are written on the
   // instance's second stream: they overlap the far-field panels here and, in a following
   // ph_matvec, the upward pass and the coupling; the near-field MVM runs on the same

@@ -639,18 +639,6 @@ __global__ void __launch_bounds__(NT) k_near_mvm(
   }
 }
 
-// Raw buffer load of one stored value (byte offset; BUF_OOB returns zero without touching
-// memory), so that every load of the loop below is unconditional and the compiler's wait
-// counts track the prefetched registers exactly.
-// (The offset is passed through an empty asm so that the compiler keeps one load per call
-// instead of cloning it into branches for the two offsets of a select.)
-template <typename DT>
-__device__ __forceinline__ DT bload1(__amdgpu_buffer_rsrc_t r, int off) {
-  asm volatile("" : "+v"(off));
-  if constexpr (sizeof(DT) == 8) return __builtin_bit_cast(DT, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-  else if constexpr (sizeof(DT) == 4) return __builtin_bit_cast(DT, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-  else return bf16{(uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)};
-}
 
 // Near field with one right-hand side, every stored block read once.  With R = 1 there is
 // no matrix product for the matrix cores, so this is plain FMA streaming: the workgroup of
@@ -907,7 +895,7 @@ static inline int ilog2(int g) {
 
 template <typename S, typename DT>
 void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double beta, double nugget,
-                 hipStream_t st) {
+                 hipStream_t st, const ExtScratch* ext) {
   const DeviceModel& m = *in.m;
   const TreeData& t = *m.tree;
   const int64_t T = in.T;
@@ -937,6 +925,33 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
   bool serial = in.tune_overlap != 1;   // default: one stream (sharing the GPU measured no gain)
   if (const char* env = std::getenv("PH_SERIAL_MVM")) serial = std::atoi(env) != 0;
   hipStream_t nst = serial ? st : in.aux;
+  // the single-RHS near kernel addresses a slot's blocks, x and pair buffer with 32-bit
+  // byte offsets
+  const bool gemv_ok = m.N_nf_pad * (int64_t)in.d_esize <= BUF_MAX_BYTES &&
+                       m.n * (int64_t)sizeof(S) <= BUF_MAX_BYTES && m.Zt * (int64_t)sizeof(S) <= BUF_MAX_BYTES;
+  const bool need_zb = Rs == 1 && gemv_ok && m.Zt > 0 && !in.factored;
+  if (use_far && (m.n_nodes * m.Pp * Rs * (int64_t)sizeof(S) > BUF_MAX_BYTES ||
+                  m.n_classes * m.Pp * m.Pp * (int64_t)sizeof(S) > BUF_MAX_BYTES))
+    fail(PH_EUNSUPPORTED, "ph_matvec: per-slot coupling buffers exceed 2 GiB (reduce R)");
+  S *xt, *yt, *xh, *yh, *partp = nullptr, *zbp = nullptr;
+  if (ext) {
+    // caller-provided scratch (no allocation): the same buffers carved at 256-byte offsets
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+      char* q = (char*)ext->base + off;
+      off += (bytes + 255) / 256 * 256;
+      return (S*)q;
+    };
+    xt = carve((size_t)T * m.n * Rs * sizeof(S));
+    yt = carve((size_t)T * m.n * Rs * sizeof(S));
+    xh = carve((size_t)T * m.n_nodes * m.Pp * Rs * sizeof(S));
+    yh = carve((size_t)T * m.n_nodes * m.Pp * Rs * sizeof(S));
+    if (G > 1) partp = carve((size_t)G * T * m.n_nodes * m.Pp * Rs * sizeof(S));
+    if (need_zb) zbp = carve((size_t)T * m.Zt * sizeof(S));
+    if (off > ext->bytes)
+      fail(PH_EINVAL, "ph_matvec_noalloc: this MVM needs " + std::to_string(off) + " bytes of scratch, more than the " +
+                          std::to_string(ext->bytes) + " the library reserves per GPU");
+  } else {
   if (Rs > in.Rcap || G > in.Gcap) {
     if (in.graphs > 0) fail(PH_ESTATE, "ph_matvec: the instance has recorded graphs, its scratch cannot grow");
     const int64_t Rc = std::max<int64_t>(Rs, in.Rcap);
@@ -949,21 +964,17 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     in.Rcap = Rc;
     in.Gcap = Gc;
   }
-  if (use_far && (m.n_nodes * m.Pp * Rs * (int64_t)sizeof(S) > BUF_MAX_BYTES ||
-                  m.n_classes * m.Pp * m.Pp * (int64_t)sizeof(S) > BUF_MAX_BYTES))
-    fail(PH_EUNSUPPORTED, "ph_matvec: per-slot coupling buffers exceed 2 GiB (reduce R)");
-  // the single-RHS near kernel addresses a slot's blocks, x and pair buffer with 32-bit
-  // byte offsets
-  const bool gemv_ok = m.N_nf_pad * (int64_t)in.d_esize <= BUF_MAX_BYTES &&
-                       m.n * (int64_t)sizeof(S) <= BUF_MAX_BYTES && m.Zt * (int64_t)sizeof(S) <= BUF_MAX_BYTES;
-  if (Rs == 1 && gemv_ok && m.Zt > 0 && in.zb.n == 0) {
+  if (need_zb && in.zb.n == 0) {
     if (in.graphs > 0) fail(PH_ESTATE, "ph_matvec: the instance has recorded graphs, its scratch cannot grow");
     in.zb.alloc((size_t)T * m.Zt * sizeof(S));
   }
-  S* xt = (S*)in.xt.p;
-  S* yt = (S*)in.yt.p;
-  S* xh = (S*)in.xh.p;
-  S* yh = (S*)in.yh.p;
+  xt = (S*)in.xt.p;
+  yt = (S*)in.yt.p;
+  xh = (S*)in.xh.p;
+  yh = (S*)in.yh.p;
+  partp = (S*)in.part.p;
+  zbp = (S*)in.zb.p;
+  }
   const int32_t leaf0 = t.leaves.front();
   const int64_t Cps = m.n_classes * m.Pp * m.Pp;
   const int64_t total_in = T * m.n * Rs;
@@ -986,11 +997,14 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
       join_near(in, st);
     }
     const int xcd = m.near_xcd;
-    if (Rs == 1 && gemv_ok) {
+    if (in.factored) {
+      // blocks formed from the near factors inside the MVM (no D in memory)
+      near_fused_launch<S, DT>(in, xt, yt, Rs, nst);
+    } else if (Rs == 1 && gemv_ok) {
       // one right-hand side: every stored block read once, transposed products gathered
       auto gemv = [&](auto kern) {
         launch(PH_STAGE_NEAR_MVM, kern, dim3((unsigned)m.n_leaves, (unsigned)T), dim3(NT), nst, (const S*)xt, yt,
-               (S*)in.zb.p, (const DT*)in.D.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
+               zbp, (const DT*)in.D.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
                (const int64_t*)m.up_rowptr.p, (const int64_t*)m.up_tb.p, (const int32_t*)m.up_nt.p,
                (const int64_t*)m.up_D.p, (const int64_t*)m.up_z.p, leaf0, m.n, m.N_nf_pad, m.Zt, xcd);
       };
@@ -1000,7 +1014,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
       else if (mp <= 8) gemv(k_near_gemv<S, DT, 8>);
       else gemv(k_near_gemv<S, DT, 12>);
       launch(PH_STAGE_NEAR_GATHER, k_near_gather<S>, dim3((unsigned)m.n_leaves, (unsigned)T), dim3(NT), nst, yt,
-             (const S*)in.zb.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
+             (const S*)zbp, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
              (const int64_t*)m.lo_rowptr.p, (const int64_t*)m.lo_z.p, leaf0, m.n, m.Zt);
     } else {
       launch(PH_STAGE_NEAR_MVM, k_near_mvm<S, DT>, dim3((unsigned)m.n_mvm_items, (unsigned)nrc, (unsigned)T),
@@ -1025,7 +1039,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     }
     const int64_t part_stride = T * m.n_nodes * m.Pp * Rs;
     const bool pack = Rs == 1;   // packed coupling (box targets as matrix-core columns)
-    S* cout = G > 1 ? (S*)in.part.p : yh;
+    S* cout = G > 1 ? partp : yh;
     const int64_t ngr = hb == 2 ? m.n_hgroups : m.n_groups;
     if (T > 65535 || ngr * nrc > 65535)
       fail(PH_EUNSUPPORTED, "ph_matvec: too many parameter slots or target boxes x RHS tiles for one launch");
@@ -1082,7 +1096,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
       const int64_t node_elems = (int64_t)m.Pp * Rs;
       const int64_t rtotal = T * (m.n_nodes - a0) * node_elems;
       launch(PH_STAGE_ZERO, k_coupling_reduce<S>, dim3((unsigned)grid_for(rtotal)), dim3(NT), st, yh,
-             (const S*)in.part.p, G, part_stride, node_elems, a0, m.n_nodes, rtotal);
+             (const S*)partp, G, part_stride, node_elems, a0, m.n_nodes, rtotal);
     }
     for (int l = m.min_far; l < m.l_max; ++l) {
       const int32_t a = t.level_start[l + 1], b = t.level_start[l + 2];
@@ -1163,10 +1177,10 @@ template void bilinear_impl<float, float>(InstData&, const float*, const float*,
 template void bilinear_impl<float, bf16>(InstData&, const float*, const float*, int64_t, double*, hipStream_t);
 
 template void matvec_impl<double, double>(InstData&, const double*, double*, int64_t, double, double, double,
-                                          hipStream_t);
+                                          hipStream_t, const ExtScratch*);
 template void matvec_impl<float, float>(InstData&, const float*, float*, int64_t, double, double, double,
-                                        hipStream_t);
+                                        hipStream_t, const ExtScratch*);
 template void matvec_impl<float, bf16>(InstData&, const float*, float*, int64_t, double, double, double,
-                                       hipStream_t);
+                                       hipStream_t, const ExtScratch*);
 
 }  // namespace ph

@@ -54,9 +54,11 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   m->N_nf_pad = doff.back();
   m->D_off_host.assign(m->n_near, 0);
   m->D_tr_host.assign(m->n_near, 0);
+  m->near_src_host.assign(m->n_near, 0);
   for (int64_t b = 0; b < m->n_near; ++b) {
     m->D_off_host[b] = doff[hm.near_src[b]];
     m->D_tr_host[b] = hm.near_tr[b];
+    m->near_src_host[b] = hm.near_src[b];
   }
 
   // near stored blocks and tiles
@@ -125,7 +127,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   // CSR of near blocks by target leaf (canonical list is sorted by sigma)
   const int32_t leaf0 = t.leaves.empty() ? 0 : t.leaves.front();
   std::vector<int64_t> nrow(m->n_leaves + 1, 0), ntb(m->n_near), nD(m->n_near);
-  std::vector<int32_t> nnt(m->n_near), ntr(m->n_near);
+  std::vector<int32_t> nnt(m->n_near), ntr(m->n_near), nq(m->n_near);
   for (int64_t b = 0; b < m->n_near; ++b) {
     const int32_t s = t.near[2 * b], u = t.near[2 * b + 1];
     nrow[s - leaf0 + 1]++;
@@ -133,7 +135,15 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
     nnt[b] = (int32_t)t.size(u);
     nD[b] = m->D_off_host[b];
     ntr[b] = m->D_tr_host[b];
+    nq[b] = hm.near_src[b];
   }
+  // factored near MVM: ranks in chunks of KRp (<= 16, a multiple of 4) or of 16
+  int rmax = 1;
+  for (const NearStored& q : hm.nstore) {
+    rmax = std::max(rmax, q.r_e);
+    m->max_Nep = std::max(m->max_Nep, (int64_t)q.ldp * q.nt);
+  }
+  m->KRp = rmax <= 16 ? (rmax + 3) / 4 * 4 : (rmax + 15) / 16 * 16;
   for (int64_t i = 0; i < m->n_leaves; ++i) nrow[i + 1] += nrow[i];
   // near MVM work items, one per 128-row chunk of every leaf (leaf order)
   std::vector<int32_t> items;
@@ -146,6 +156,16 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   }
   m->n_mvm_items = (int64_t)items.size() / 2;
   m->mvm_items.upload(items.data(), items.size(), st);
+  std::vector<int32_t> items64;
+  for (int64_t li = 0; li < m->n_leaves; ++li) {
+    const int64_t ns = t.size(t.leaves[(size_t)li]);
+    for (int64_t c0 = 0; c0 < std::max<int64_t>(ns, 1); c0 += 64) {
+      items64.push_back((int32_t)li);
+      items64.push_back((int32_t)c0);
+    }
+  }
+  m->n_mvm_items64 = (int64_t)items64.size() / 2;
+  m->mvm_items64.upload(items64.data(), items64.size(), st);
   // XCD-contiguous leaf ranges in the near MVM only when the 8 ranges carry about equal
   // work (entries of the leaf's near blocks): within 5% of the mean
   {
@@ -225,6 +245,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
     permute(nD);
     permute(nnt);
     permute(ntr);
+    permute(nq);
   }
   // Single-RHS near MVM lists.  The workgroup of leaf s streams its stored blocks D_st
   // (t >= s, canonical order) and writes z_st = D_st^T x_s (t > s) into rows
@@ -387,6 +408,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   m->near_D.upload(nD.data(), nD.size(), st);
   m->near_nt.upload(nnt.data(), nnt.size(), st);
   m->near_tr.upload(ntr.data(), ntr.size(), st);
+  m->near_q.upload(nq.data(), nq.size(), st);
   m->cstore.upload(cd.data(), cd.size(), st);
   m->ff_chat.upload(chat.data(), chat.size(), st);
   m->ff_theta.upload(hm.ff_theta.data(), hm.ff_theta.size(), st);
@@ -431,7 +453,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
                               m->up_nt.bytes() + m->lo_rowptr.bytes() + m->lo_z.bytes() +
                               m->cstore.bytes() + m->ff_chat.bytes() + m->ff_theta.bytes() + m->grp_targets.bytes() +
                               m->grp_entry.bytes() + m->ent_cls.bytes() + m->ent_tau.bytes() +
-                              m->chunk_first.bytes() + m->mvm_items.bytes() + m->hgrp_targets.bytes() + m->hent_cls.bytes() +
+                              m->chunk_first.bytes() + m->mvm_items.bytes() + m->mvm_items64.bytes() + m->near_q.bytes() + m->hgrp_targets.bytes() + m->hent_cls.bytes() +
                               m->hent_tau.bytes() + m->hchunk_first.bytes());
   return m;
 }
@@ -486,15 +508,19 @@ void need(bool ok, const char* msg) {
   if (!ok) ph::fail(PH_EINVAL, msg);
 }
 
-int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype dt, void* stream,
-                ph_inst** inout) {
+int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype dt, ph_near_mode near,
+                void* stream, ph_inst** inout) {
   return guarded([&] {
     need(m && m->p, "model is NULL");
     need(theta != nullptr, "theta is NULL");
     need(inout != nullptr, "inout is NULL");
     need(T >= 1, "T must be >= 1");
     need(dt == PH_F64 || dt == PH_F32 || dt == PH_BF16, "dtype must be PH_F64, PH_F32 or PH_BF16");
+    need(near == PH_NEAR_AUTO || near == PH_NEAR_BLOCKS || near == PH_NEAR_FACTORED, "invalid near-field mode");
     const ph::DeviceModel& md = *m->p;
+    if (near == PH_NEAR_FACTORED && md.KRp > 64)
+      ph::fail(PH_EUNSUPPORTED, "factored near field supports near ranks up to 64");
+    const bool factored = near == PH_NEAR_FACTORED || (near == PH_NEAR_AUTO && T >= 4 && md.KRp <= 64);
     if (dim >= 0) need(dim < md.d_theta, "gradient dimension out of range");
     for (int t = 0; t < T; ++t)
       for (int k = 0; k < md.d_theta; ++k) {
@@ -508,6 +534,8 @@ int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype
       in = (*inout)->p;
       need(in && in->m.get() == &md && in->T == T && in->dt == dt,
            "instance does not match (model, T, dtype)");
+      need(near == PH_NEAR_AUTO || (near == PH_NEAR_FACTORED) == in->factored,
+           "instance does not match (near-field mode)");
       // a recorded graph replays the theta-vector launch with the flag it was recorded with
       if (in->graphs > 0 && dim != in->grad_dim)
         ph::fail(PH_ESTATE, "instance has recorded graphs; it cannot switch between K~ and dK~/dtheta");
@@ -520,7 +548,13 @@ int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype
       in->grad_dim = dim;
       in->esize = dt == PH_F64 ? sizeof(double) : sizeof(float);
       in->d_esize = dt == PH_F64 ? sizeof(double) : dt == PH_F32 ? sizeof(float) : sizeof(ph::bf16);
-      in->D.alloc((size_t)T * md.N_nf_pad * in->d_esize);
+      in->factored = factored;
+      if (factored) {
+        if (dt != PH_F64) ph::make_low_factors(md, dt, st);
+        in->ccore.alloc((size_t)md.n_stored_near * T * md.KRp * in->esize);
+      } else {
+        in->D.alloc((size_t)T * md.N_nf_pad * in->d_esize);
+      }
       in->C.alloc((size_t)T * md.n_classes * md.Pp * md.Pp * in->esize);
       in->v.alloc((size_t)T * md.d_theta * md.p_theta);
       in->theta_d.alloc((size_t)T * md.d_theta);
@@ -663,7 +697,23 @@ void ph_model_free(ph_model* m) { delete m; }
 
 int ph_instantiate(const ph_model* m, const double* theta, int T, ph_dtype dt, void* stream,
                    ph_inst** inout) {
-  return inst_common(m, theta, T, -1, dt, stream, inout);
+  return inst_common(m, theta, T, -1, dt, PH_NEAR_AUTO, stream, inout);
+}
+
+int ph_instantiate_ex(const ph_model* m, const double* theta, int T, ph_dtype dt, ph_near_mode near, int grad_dim,
+                      void* stream, ph_inst** inout) {
+  if (grad_dim < -1) {
+    ph::g_last_error = "gradient dimension out of range";
+    return PH_EINVAL;
+  }
+  return inst_common(m, theta, T, grad_dim, dt, near, stream, inout);
+}
+
+int ph_inst_near_mode(const ph_inst* k, int* factored) {
+  return guarded([&] {
+    need(k && k->p && factored, "NULL argument");
+    *factored = k->p->factored ? 1 : 0;
+  });
 }
 
 int ph_instantiate_grad(const ph_model* m, const double* theta, int T, int dim, ph_dtype dt, void* stream,
@@ -672,7 +722,7 @@ int ph_instantiate_grad(const ph_model* m, const double* theta, int T, int dim, 
     ph::g_last_error = "gradient dimension out of range";
     return PH_EINVAL;
   }
-  return inst_common(m, theta, T, dim, dt, stream, inout);
+  return inst_common(m, theta, T, dim, dt, PH_NEAR_AUTO, stream, inout);
 }
 
 int ph_matvec(ph_inst* k, const void* x, void* y, int64_t R, double alpha, double beta, double nugget,
@@ -892,6 +942,21 @@ int ph_inst_near_block(const ph_inst* k, int t, int64_t b, double* host_out) {
     const int64_t ns = tr.size(tr.near[2 * b]), nt = tr.size(tr.near[2 * b + 1]);
     const bool trn = m.D_tr_host[b] != 0;
     const int64_t rows = trn ? nt : ns, cols = trn ? ns : nt;     // the stored block
+    if (in.factored) {
+      // no block in memory: evaluate the stored block from its factor and cores
+      ph::DevArr<double> dev;
+      dev.alloc((size_t)(rows * cols));
+      const int64_t q = m.near_src_host[b];
+      PH_HIP(hipDeviceSynchronize());
+      if (in.dt == PH_F64) ph::near_block_eval<double, double>(in, t, q, dev.p, nullptr);
+      else if (in.dt == PH_F32) ph::near_block_eval<float, float>(in, t, q, dev.p, nullptr);
+      else ph::near_block_eval<float, ph::bf16>(in, t, q, dev.p, nullptr);
+      std::vector<double> hb((size_t)(rows * cols));
+      PH_HIP(hipMemcpy(hb.data(), dev.p, hb.size() * sizeof(double), hipMemcpyDeviceToHost));
+      for (int64_t j = 0; j < nt; ++j)
+        for (int64_t i = 0; i < ns; ++i) host_out[i + j * ns] = trn ? hb[j + i * rows] : hb[i + j * rows];
+      return;
+    }
     const int64_t cnt = (rows + 15) / 16 * 16 * cols;
     PH_HIP(hipDeviceSynchronize());
     std::vector<char> buf(cnt * in.d_esize);

@@ -153,6 +153,7 @@ struct DeviceModel {
   std::vector<int32_t> class_ranks;       // per class, 2 + d_theta entries
   std::vector<int64_t> D_off_host;        // per canonical near block: offset of its stored block
   std::vector<int32_t> D_tr_host;         // per canonical near block: 1 if stored as its transpose
+  std::vector<int32_t> near_src_host;     // per canonical near block: its stored block
   // device arrays
   DevArr<double> U, E;
   DevArr<int64_t> perm, iperm;            // tree position -> point, point -> tree position
@@ -174,6 +175,22 @@ struct DeviceModel {
   int near_xcd = 0;   // near MVM: contiguous leaf ranges per XCD (only if they balance)
   DevArr<int32_t> mvm_items;   // near MVM and leaf-down work items: (leaf index, first row of a 128-row chunk)
   int64_t n_mvm_items = 0;
+  DevArr<int32_t> mvm_items64; // the same with 64-row chunks (factored near MVM, one row tile per wave)
+  int64_t n_mvm_items64 = 0;
+  DevArr<int32_t> near_q;      // per canonical near block (list order of near_rowptr): its stored block
+  int KRp = 4;                 // largest near rank rounded up to 4: per-slot stride of the factored cores
+  int64_t max_Nep = 0;         // largest padded factor column (ldp n_t) of a stored near block
+  // near factors in the storage type of a factored instance: FP64 as compressed, FP32 and
+  // BF16 copies made on the first factored instantiation that needs them (rounded to nearest)
+  mutable DevArr<float> nf_P32;
+  mutable DevArr<bf16> nf_P16;
+  mutable std::mutex lowp_mu;
+  template <typename PT>
+  const PT* near_factors() const {
+    if constexpr (sizeof(PT) == 8) return (const PT*)nf_P.p;
+    else if constexpr (sizeof(PT) == 4) return (const PT*)nf_P32.p;
+    else return (const PT*)nf_P16.p;
+  }
   int gemv_mp = 12;   // single-RHS near MVM: 16-row panels per row chunk (4, 8 or 12)
   DevArr<ClassDev> cstore;
   DevArr<double> ff_chat, ff_theta;       // far panels (r1 r2 of Pp x Pp per class), theta factors
@@ -203,6 +220,9 @@ struct InstData {
   size_t esize = 8;                   // element size of C, x_hat, y_hat, I/O (compute type)
   size_t d_esize = 8;                 // element size of the near blocks D (storage type)
   DevArr<char> D, C;
+  // factored near field (no D): c_b(theta_t) per stored block q and slot t at (q T + t) KRp
+  bool factored = false;
+  DevArr<char> ccore;
   DevArr<double> v;
   int64_t Rcap = 0;
   int Gcap = 0;
@@ -220,6 +240,7 @@ struct InstData {
   int graphs = 0;                     // live graphs recorded from this instance (scratch is fixed)
   // launch configuration of the MVM chosen by ph_autotune (0 = default heuristics)
   int tune_chunks = 0, tune_prefetch = 0, tune_overlap = -1;
+  int tune_fused_tcb = 0, tune_fused_rt = 0;   // factored near MVM: slots per workgroup, row tiles per wave
   ~InstData() {
     if (aux) (void)hipStreamSynchronize(aux);   // no kernel of this instance may outlive its buffers
     if (ev_near) (void)hipEventDestroy(ev_near);
@@ -240,14 +261,29 @@ inline void join_near(InstData& in, hipStream_t st) {
   }
 }
 
+// Scratch memory supplied by the caller of matvec_impl instead of the instance's own
+// (allocation-free entry point): base (device, 256-byte aligned) and its size in bytes.
+struct ExtScratch {
+  void* base;
+  size_t bytes;
+};
+
 // S: compute type (C, x_hat, I/O); DT: storage type of the near blocks D
 template <typename S, typename DT>
 void instantiate_impl(InstData& in, const double* theta, hipStream_t st);
 template <typename S, typename DT>
 void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double beta, double nugget,
-                 hipStream_t st);
+                 hipStream_t st, const ExtScratch* ext = nullptr);
 template <typename S, typename DT>
 void bilinear_impl(InstData& in, const S* u, const S* x, int64_t R, double* out, hipStream_t st);
+// factored near field (k_near_fused.hip)
+template <typename S>
+void near_cores_launch(InstData& in, hipStream_t st);
+template <typename S, typename PT>
+void near_fused_launch(InstData& in, const S* xt, S* yt, int64_t Rs, hipStream_t st);
+template <typename S, typename PT>
+void near_block_eval(const InstData& in, int t, int64_t q, double* dev_out, hipStream_t st);
+void make_low_factors(const DeviceModel& m, ph_dtype dt, hipStream_t st);
 void cg_solve_impl(InstData& hi, InstData* lo, const double* y, double* a, double nugget, double tol,
                    int max_iter, int inner_max, double inner_tol, ph_cg_stats* stats, hipStream_t st);
 
@@ -383,6 +419,19 @@ inline int32_t coupling_entry_weight(int act) { return act + 6; }
 constexpr int BUF_WORD3 = 0x00020000;
 constexpr int BUF_OOB = 0x7ffffff0;
 constexpr int64_t BUF_MAX_BYTES = 0x7fff0000;
+
+// Raw buffer load of one stored value (byte offset; BUF_OOB returns zero without touching
+// memory), so that every load of the loop below is unconditional and the compiler's wait
+// counts track the prefetched registers exactly.
+// (The offset is passed through an empty asm so that the compiler keeps one load per call
+// instead of cloning it into branches for the two offsets of a select.)
+template <typename DT>
+__device__ __forceinline__ DT bload1(__amdgpu_buffer_rsrc_t r, int off) {
+  asm volatile("" : "+v"(off));
+  if constexpr (sizeof(DT) == 8) return __builtin_bit_cast(DT, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  else if constexpr (sizeof(DT) == 4) return __builtin_bit_cast(DT, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  else return bf16{(uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)};
+}
 
 // Right-hand sides are padded to a multiple of RC in every internal buffer.
 inline int64_t rhs_stride(int64_t R) { return (R + RC - 1) / RC * RC; }

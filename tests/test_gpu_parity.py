@@ -7,8 +7,11 @@ rounding: different SVD algorithms (LAPACK in the oracle, Householder QR + one-s
 Jacobi in the library) and summation orders.  A backward-stable SVD of A_b perturbs
 the result by O(eps ||A_b||_F), a norm-wise quantity that grows with the block size
 relative to any single entry, so the comparison is norm-wise; the max-norm error is
-reported as well and must stay below 1e-10 of the largest entry.  Ranks are integers
-and must agree exactly.
+reported as well and must stay below 1e-11 of the largest entry (observed: at most
+2.6e-12 for blocks of up to 128 x 128 points).  For larger blocks the bound grows with the
+square root of the block's entry count N_e (the rounding of a Householder QR of an N_e-row
+unfolding grows like sqrt(N_e) eps per entry): 1e-11 sqrt(N_e / 128^2), observed 4.2e-11 for
+750 x 750 blocks.  Ranks are integers and must agree exactly.
 """
 
 from fractions import Fraction
@@ -41,15 +44,27 @@ def _setup(X, kernel, lo, hi, p_s, p_theta, tol, l_max, eta2, num_threads=0):
     return lt, lm, om
 
 
-def _close(a, b, tol=TOL64, what=""):
+def _close(a, b, tol=TOL64, what="", max_entries=128 * 128):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
     emax = np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
-    print(f"[parity] {what} norm-wise {err:.3e} max-norm {emax:.3e} (tol {tol:.1e})", flush=True)
+    etol = max(10 * tol, 1e-11 * max(1.0, np.sqrt(max_entries / (128 * 128))))
+    print(f"[parity] {what} norm-wise {err:.3e} max-norm {emax:.3e} (tol {tol:.1e}, max-norm {etol:.1e})", flush=True)
     assert err <= tol, f"{what}: relative norm-wise error {err:.3e} > {tol:.1e}"
-    assert emax <= max(100 * tol, 1e-10), f"{what}: relative max-norm error {emax:.3e}"
+    assert emax <= etol, f"{what}: relative max-norm error {emax:.3e} > {etol:.1e}"
     return err
+
+
+def _close_scalar(a, b, scale, what):
+    """A bilinear form u^T A x from the library against the oracle.  The MVM parity bound
+    ||A_gpu x - A_oracle x|| <= 1e-12 ||A x|| carries over by Cauchy-Schwarz:
+    |u^T (A_gpu - A_oracle) x| <= 1e-12 ||u|| ||A x||.  (Relative to |u^T A x| itself the error
+    can be larger when the sum cancels.)"""
+    err = abs(float(a) - float(b))
+    print(f"[parity] {what}: |gpu - oracle| = {err:.3e}, relative to ||u|| ||A x|| {err / scale:.3e}, "
+          f"relative to the value {err / max(abs(b), 1e-300):.3e}", flush=True)
+    assert err <= TOL64 * scale, f"{what}: {err:.3e} > 1e-12 ||u|| ||A x|| = {TOL64 * scale:.3e}"
 
 
 def _check_ranks(lm, om):
@@ -72,10 +87,12 @@ def _mvm_case(X, kernel, lo, hi, p_s, p_theta, tol, l_max, eta2, theta, R, nugge
     from paper_2511_03109_amd import api
     inst = api.Instance(lm, theta)
     oi = om.instantiate(theta)
+    sizes = [len(om.tree.idx[s]) for s in om.tree.leaves]
+    ne_max = max(sizes) ** 2
     if check_blocks:
         Dg = np.concatenate([inst.near_block(b).ravel() for b in range(len(om.near))])
         Do = np.concatenate([oi["D"][b].ravel() for b in range(len(om.near))])
-        _close(Dg, Do, what="near blocks")
+        _close(Dg, Do, what="near blocks", max_entries=ne_max)
         if len(om.classes):
             Cg = np.stack([inst.coupling(c) for c in range(len(om.classes))])
             Co = np.stack([oi["C"][c] for c in range(len(om.classes))])
@@ -85,7 +102,7 @@ def _mvm_case(X, kernel, lo, hi, p_s, p_theta, tol, l_max, eta2, theta, R, nugge
     y_o = om.matvec(oi, x, nugget=nugget)
     xd = torch.tensor(np.ascontiguousarray(x.T), device="cuda")
     y_g = inst.matvec(xd, nugget=nugget).cpu().numpy().T
-    return _close(y_g, y_o, what="mvm")
+    return _close(y_g, y_o, what="mvm", max_entries=ne_max)
 
 
 def test_workload1_full():
@@ -117,15 +134,15 @@ def test_ragged_and_degenerate(d, n, l, eta2, R):
     _mvm_case(X, "matern12", [0.05], [0.5], 4, 7, 1e-8, l, eta2, [0.31], R=R, nugget=0.01)
 
 
-@pytest.mark.parametrize("d,n,p_s,p_theta,l,eta2,T", [(3, 2000, 5, 11, 2, (3, 1), 3), (3, 1500, 4, 7, 2, (3, 1), 1),
-                                                      (2, 1800, 9, 7, 3, (2, 1), 1)])
+@pytest.mark.parametrize("d,n,p_s,p_theta,l,eta2,T", [(3, 2000, 5, 11, 2, (3, 1), 3), (3, 2000, 5, 7, 2, (3, 1), 3),
+                                                      (3, 1500, 4, 7, 2, (3, 1), 1), (2, 1800, 9, 7, 3, (2, 1), 1)])
 def test_single_rhs_packed_coupling(d, n, p_s, p_theta, l, eta2, T):
     """One right-hand side: the coupling packs the 16 targets of a box into the matrix-core
     columns.  Row-tile counts Pp / 16 = 8 (with 3 parameter slots), 4 and 6 (a partial
-    last row group) against the oracle, slot by slot.  (With p_theta = 7 the 3-D p_s = 5
-    case has far classes whose truncated factors differ between the two sides' SVD
-    routines by up to 4e-7 of the instantiated coupling at l = 0.07, with equal ranks: the
-    truncation is ill-conditioned there.  That case uses the benchmark's p_theta = 11.)"""
+    last row group) against the oracle, slot by slot.  The 3-D p_s = 5, p_theta = 7 case
+    has far classes with exactly degenerate pairs of singular values (offsets symmetric
+    under swapping two axes); the rank rule keeps such a cluster whole on both sides, so
+    the kept subspaces agree and so do the couplings."""
     torch = _torch()
     from paper_2511_03109_amd import api
     X = np.random.default_rng([11, d, n]).random((n, d))
@@ -166,6 +183,72 @@ def test_polynomial_kernel_against_dense_product():
         K = kernels.poly_test(X[:, None, :], X[None, :, :], [th])
         y = api.Instance(lm, [th]).matvec(torch.tensor(np.ascontiguousarray(x.T), device="cuda"))
         _close(y.cpu().numpy().T, K @ x, 1e-11)
+
+
+@pytest.mark.parametrize("p_theta", [7, 11])
+def test_untruncated_benchmark_geometry(p_theta):
+    """tol = 0 (nothing truncated): the kernels against the oracle independently of how well
+    conditioned a truncation is.  Benchmark recipe (3-D Matern-3/2, p_s = 5, eta = sqrt 3) at
+    n = 3000, l_max = 2, T = 8 slots, 16 right-hand sides; every near block and coupling of
+    two slots and every output element of all eight."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    n, T, R = 3000, 8, 16
+    X = inputs.points_for(2, n)
+    lt, lm, om = _setup(X, "matern32", [0.05], [0.5], 5, p_theta, 0.0, 2, (3, 1))
+    thetas = inputs.theta_samples(T, [0.05], [0.5], 2)
+    inst = api.Instance(lm, thetas)
+    x = inputs.normal_vectors(n, T * R, 31).T.reshape(T, R, n)
+    y = inst.matvec(torch.tensor(np.ascontiguousarray(x), device="cuda")).cpu().numpy()
+    for t in range(T):
+        oi = om.instantiate(thetas[t])
+        if t in (0, T - 1):
+            Dg = np.concatenate([inst.near_block(b, t).ravel() for b in range(len(om.near))])
+            Do = np.concatenate([oi["D"][b].ravel() for b in range(len(om.near))])
+            _close(Dg, Do, what=f"tol 0 near blocks slot {t}")
+            Cg = np.stack([inst.coupling(c, t) for c in range(len(om.classes))])
+            Co = np.stack([oi["C"][c] for c in range(len(om.classes))])
+            _close(Cg, Co, what=f"tol 0 couplings slot {t}")
+        _close(y[t], om.matvec(oi, x[t].T).T, what=f"tol 0 mvm slot {t}")
+
+
+@pytest.mark.parametrize("case", ["3d_T8_R16", "3d_T5_R20", "3d_T3_R1", "mixture_T4_R3"])
+def test_factored_near_field(case):
+    """Factored near field (blocks formed from the factors inside the MVM, never written)
+    against the near-block form and the oracle.  In FP64 both forms form every block with the
+    same arithmetic, so the blocks must be bit-identical; the MVM must match the oracle.
+    Cases: the benchmark recipe with 8 slots (one batch of 8) and with 5 slots and 20
+    right-hand sides (a partial slot batch, two RHS tiles, the second ragged), one right-hand
+    side, and the uneven two-parameter mixture (near ranks up to 49, leaves above 128 points)."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    if case.startswith("3d"):
+        n = 3000
+        X = inputs.points_for(2, n)
+        lt, lm, om = _setup(X, "matern32", [0.05], [0.5], 5, 11, 1e-8, 2, (3, 1))
+        T, R = {"3d_T8_R16": (8, 16), "3d_T5_R20": (5, 20), "3d_T3_R1": (3, 1)}[case]
+        thetas = inputs.theta_samples(T, [0.05], [0.5], 7)
+    else:
+        n = 3000
+        X = inputs.points_for(3, n)
+        lt, lm, om = _setup(X, "aniso_gaussian", [0.05, 0.05], [0.5, 0.5], 5, 7, 1e-8, 4, (2, 1))
+        T, R = 4, 3
+        thetas = np.random.default_rng(8).uniform(0.05, 0.5, (T, 2))
+    fi = api.Instance(lm, thetas, near="factored")
+    bi = api.Instance(lm, thetas, near="blocks")
+    assert fi.factored and not bi.factored
+    for t in (0, T - 1):
+        for b in range(0, len(om.near), 5):
+            assert np.array_equal(fi.near_block(b, t), bi.near_block(b, t)), f"slot {t} block {b}"
+    x = inputs.normal_vectors(n, T * R, 41).T.reshape(T, R, n)
+    xd = torch.tensor(np.ascontiguousarray(x), device="cuda")
+    yf = fi.matvec(xd, nugget=0.01).cpu().numpy()
+    yb = bi.matvec(xd, nugget=0.01).cpu().numpy()
+    sizes = [len(om.tree.idx[s]) for s in om.tree.leaves]
+    for t in range(T):
+        ref = om.matvec(om.instantiate(thetas[t]), x[t].T, nugget=0.01).T
+        _close(yf[t], ref, what=f"factored slot {t}", max_entries=max(sizes) ** 2)
+        _close(yb[t], ref, what=f"blocks slot {t}", max_entries=max(sizes) ** 2)
 
 
 def test_two_parameter_mixture():
@@ -288,18 +371,19 @@ def test_autograd_function_theta_and_x():
     (y * ud).sum().backward()
     gth = theta.grad.numpy()
     gx = xd.grad.cpu().numpy().T
-    dth_o = np.sum(u * om.matvec(om.instantiate(l0, deriv_dim=0), x))
-    _close(gth, [dth_o], what="dL/dtheta")
+    dKx_o = om.matvec(om.instantiate(l0, deriv_dim=0), x)
+    dth_o = np.sum(u * dKx_o)
+    _close_scalar(gth[0], dth_o, np.linalg.norm(u) * np.linalg.norm(dKx_o), "dL/dtheta")
     _close(gx, om.matvec(om.instantiate(l0), u), what="dL/dx")
     # Central difference, h = 1e-5.  Error budget: truncation h^2 |L'''| / 6 (relative ~1e-9
-    # here) plus cancellation: each L(theta +- h) carries the MVM's rounding, at most
-    # 1e-13 ||u|| ||y|| (norm-wise error of the FP64 path, observed ~1e-14), divided by h.
+    # here) plus cancellation: each L(theta +- h) carries the MVM's rounding, about
+    # 1e-14 ||u|| ||y|| (the norm-wise error of the FP64 path against the oracle), divided by h.
     h = 1e-5
     yp = api.Instance(lm, [l0 + h]).matvec(xd.detach())
     Lp = float((yp * ud).sum())
     Lm = float((api.Instance(lm, [l0 - h]).matvec(xd.detach()) * ud).sum())
     fd = (Lp - Lm) / (2 * h)
-    bound = 1e-7 * abs(fd) + 1e-13 * float(ud.norm() * yp.norm()) / h
+    bound = 1e-7 * abs(fd) + 1e-14 * float(ud.norm() * yp.norm()) / h
     print(f"[parity] dL/dtheta vs central difference: {abs(gth[0] - fd):.3e} (bound {bound:.3e}, "
           f"relative {abs(gth[0] - fd) / abs(fd):.3e})", flush=True)
     assert abs(gth[0] - fd) <= bound
@@ -321,11 +405,11 @@ def test_autograd_two_parameters_and_slots():
     xd = torch.tensor(np.ascontiguousarray(x), device="cuda", requires_grad=True)
     ud = torch.tensor(np.ascontiguousarray(u), device="cuda")
     (api.k_theta_matvec(lm, theta, xd) * ud).sum().backward()
-    ref = np.empty((2, 2))
     for t in range(2):
         for i in range(2):
-            ref[t, i] = np.sum(u[t].T * om.matvec(om.instantiate(th[t], deriv_dim=i), x[t].T))
-    _close(theta.grad.numpy(), ref, what="dL/dtheta (T=2, d_theta=2)")
+            dKx = om.matvec(om.instantiate(th[t], deriv_dim=i), x[t].T)
+            _close_scalar(theta.grad.numpy()[t, i], np.sum(u[t].T * dKx), np.linalg.norm(u[t]) * np.linalg.norm(dKx),
+                          f"dL/dtheta slot {t} dim {i}")
     gx_ref = np.stack([om.matvec(om.instantiate(th[t]), u[t].T).T for t in range(2)])
     _close(xd.grad.cpu().numpy(), gx_ref, what="dL/dx (T=2)")
 
@@ -343,8 +427,9 @@ def test_bilinear_is_deterministic():
     a = inst.bilinear(u, x).cpu().numpy()
     b = inst.bilinear(u, x).cpu().numpy()
     assert np.array_equal(a, b)
-    ref = np.sum(u.cpu().numpy().T * om.matvec(om.instantiate(0.25), x.cpu().numpy().T))
-    _close(a, [ref], what="bilinear")
+    Kx = om.matvec(om.instantiate(0.25), x.cpu().numpy().T)
+    un = u.cpu().numpy().T
+    _close_scalar(a[0], np.sum(un * Kx), np.linalg.norm(un) * np.linalg.norm(Kx), "bilinear")
 
 
 def _bf16_round(a):
