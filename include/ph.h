@@ -257,6 +257,20 @@ int ph_instantiate_grad(const ph_model* m, const double* theta, int T, int dim, 
 int ph_matvec(ph_inst* k, const void* x, void* y, int64_t R, double alpha, double beta,
               double nugget, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid device allocation): ph_matvec with the same arguments, result and
+ * errors, whose scratch (x, y in tree order, the upward / downward coefficients, coupling
+ * partial sums, single-RHS pair buffers) comes from a fixed array of 64 MiB that the
+ * library holds on each GPU it runs on (in its code object, until the process ends)
+ * instead of from the instance.  It calls no device allocation: a product that needs more
+ * scratch than 64 MiB fails with PH_EINVAL before anything is launched (about
+ * T (2 n + (2 + G) n_nodes Pp) R doubles; Pp = P rounded up to 16, G = 4 or 8 coupling
+ * chunks, R rounded up to 16 when above 1).  Every call on one GPU uses the same array and
+ * leaves its contents behind; calls that overlap on one GPU (concurrent streams or
+ * threads) race, so callers serialise them. */
+int ph_matvec_noalloc(ph_inst* k, const void* x, void* y, int64_t R, double alpha, double beta,
+                      double nugget, void* stream);
+
 /* Bilinear form per parameter slot:  out[t] = sum_r u_t[:, r]^T K~(theta_t) x_t[:, r]
  * (nugget excluded).  With an instance of ph_instantiate_grad(dim) this is
  * dL/dtheta_dim of L = sum_r u_r^T K~(theta) x_r, the parameter gradient of the

@@ -81,6 +81,7 @@ SIGNATURES = {
     "ph_instantiate_ex": ([_P, _DP, C.c_int, C.c_int, C.c_int, C.c_int, _P, C.POINTER(_P)], C.c_int),
     "ph_inst_near_mode": ([_P, C.POINTER(C.c_int)], C.c_int),
     "ph_matvec": ([_P, _P, _P, C.c_int64, C.c_double, C.c_double, C.c_double, _P], C.c_int),
+    "ph_matvec_noalloc": ([_P, _P, _P, C.c_int64, C.c_double, C.c_double, C.c_double, _P], C.c_int),
     "ph_bilinear": ([_P, _P, _P, C.c_int64, _P, _P], C.c_int),
     "ph_cg_solve": ([_P, _P, _P, _P, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
                      C.POINTER(CgStats), _P], C.c_int),

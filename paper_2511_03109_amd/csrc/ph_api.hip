@@ -743,6 +743,48 @@ int ph_matvec(ph_inst* k, const void* x, void* y, int64_t R, double alpha, doubl
   });
 }
 
+// Scratch of ph_matvec_noalloc: one array per GPU, in the code object (no allocation at
+// call time).  Its device address is looked up once per device with hipGetSymbolAddress;
+// host code uses only that address, never the array's name.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64] = {};
+
+static void* noalloc_scratch() {
+  int dev = -1;
+  PH_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) ph::fail(PH_EUNSUPPORTED, "ph_matvec_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* q = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || q == nullptr)
+      ph::fail(PH_EHIP, std::string("ph_matvec_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = q;
+  }
+  return g_scratch_ptr[dev];
+}
+
+int ph_matvec_noalloc(ph_inst* k, const void* x, void* y, int64_t R, double alpha, double beta, double nugget,
+                      void* stream) {
+  return guarded([&] {
+    need(k && k->p, "instance is NULL");
+    need(R >= 0, "R must be >= 0");
+    if (R == 0) return;
+    need(x && y, "x or y is NULL");
+    ph::InstData& in = *k->p;
+    hipStream_t st = (hipStream_t)stream;
+    const ph::ExtScratch ext{noalloc_scratch(), NOALLOC_SCRATCH_BYTES};
+    if (in.dt == PH_F64)
+      ph::matvec_impl<double, double>(in, (const double*)x, (double*)y, R, alpha, beta, nugget, st, &ext);
+    else if (in.dt == PH_F32)
+      ph::matvec_impl<float, float>(in, (const float*)x, (float*)y, R, alpha, beta, nugget, st, &ext);
+    else
+      ph::matvec_impl<float, ph::bf16>(in, (const float*)x, (float*)y, R, alpha, beta, nugget, st, &ext);
+  });
+}
+
 int ph_bilinear(ph_inst* k, const void* u, const void* x, int64_t R, double* out, void* stream) {
   return guarded([&] {
     need(k && k->p, "instance is NULL");
