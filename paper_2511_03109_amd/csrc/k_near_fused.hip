@@ -12,17 +12,23 @@
 
 namespace ph {
 
-// c[(q T + t) KRp + k] = (core_q x_theta (Theta_k^T v_k(theta_t)))[k] for stored block q,
-// slot t, k < r_e (zero for r_e <= k < KRp).  The sums run in the same order as in the
-// near-block instantiation, so both forms use identical coefficients.
+// c[((q nch + c) T + t) KM + kk] = (core_q x_theta (Theta_k^T v_k(theta_t)))[k] for stored
+// block q, slot t and rank k = c KM + kk (rank chunks of KM, nch = KRp / KM chunks; zero for
+// r_e <= k < KRp), so that the KM coefficients of the TCB slots a unit of the MVM needs are
+// contiguous at compile-time offsets.  The sums run in the same order as in the near-block
+// instantiation, so both forms use identical coefficients.
 template <typename S>
 __global__ void __launch_bounds__(NT) k_near_cores(const NearDev* __restrict__ blocks, const double* __restrict__ core,
                                                    const double* __restrict__ th, const double* __restrict__ v,
-                                                   S* __restrict__ cc, int64_t nq, int T, int p, int dth, int KRp) {
+                                                   S* __restrict__ cc, int64_t nq, int T, int p, int dth, int KRp,
+                                                   int KM) {
   const int64_t total = nq * T * KRp;
+  const int nch = KRp / KM;
   for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < total; o += (int64_t)gridDim.x * blockDim.x) {
-    const int k = (int)(o % KRp);
-    const int t = (int)((o / KRp) % T);
+    const int kk = (int)(o % KM);
+    const int t = (int)((o / KM) % T);
+    const int ch = (int)((o / ((int64_t)KM * T)) % nch);
+    const int k = ch * KM + kk;
     const NearDev b = blocks[o / ((int64_t)KRp * T)];
     double s = 0.0;
     if (k < b.r_e) {
@@ -106,7 +112,7 @@ __global__ void __launch_bounds__(NT) k_near_fused(
     const NearDev* __restrict__ blocks, const int64_t* __restrict__ nbegin, const int64_t* __restrict__ nend,
     const int64_t* __restrict__ rowptr, const int32_t* __restrict__ nq, const int32_t* __restrict__ ntr,
     const int64_t* __restrict__ ntb, const int32_t* __restrict__ items, int32_t leaf0, int64_t n, int64_t R,
-    int T, int KRp, int xcd) {
+    int T, int nch, int xcd) {
   typedef NearApply<S> MF;
   constexpr int CH = 64 * RT;
   constexpr int SP = (int)sizeof(PT), SS = (int)sizeof(S);
@@ -131,9 +137,10 @@ __global__ void __launch_bounds__(NT) k_near_fused(
     rok[r] = (wave + 4 * r) * 16 + m16 < cn;
   }
   const bool colok = r0 + m16 < R;
-  // x of all slots, T n R values (byte range checked on the host)
-  const __amdgpu_buffer_rsrc_t xr =
-      __builtin_amdgcn_make_buffer_rsrc((void*)xt, (short)0, (int)((int64_t)T * n * R * SS), BUF_WORD3);
+  // x of this workgroup's tc slots (T n R values in all, byte range checked on the host):
+  // slots past tc fall outside the range
+  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(xt + (int64_t)slot0 * n * R), (short)0, (int)((int64_t)tc * n * R * SS), BUF_WORD3);
   typename MF::acc_t acc[RT][TCB];
 #pragma unroll
   for (int r = 0; r < RT; ++r)
@@ -148,7 +155,7 @@ __global__ void __launch_bounds__(NT) k_near_fused(
     __amdgpu_buffer_rsrc_t pr;   // factor of the stored block, all r_e ranks
     int nepb;                    // bytes of one rank (padded factor column)
     int xo;                      // byte offset of x(first point of t, r0 + m16) in slot 0
-    CPtr cb;                     // c_b(theta_slot0), KRp per slot
+    CPtr cb;                     // c_b(theta_slot0) of rank chunk 0 (chunks T KM apart)
     int ldp, tr, nt, re;
   };
   auto meta = [&](int64_t fb) {
@@ -159,16 +166,16 @@ __global__ void __launch_bounds__(NT) k_near_fused(
     M.nepb = B.ldp * B.nt * SP;
     M.pr = __builtin_amdgcn_make_buffer_rsrc((void*)(Pf + B.P_off), (short)0, B.r_e * M.nepb, BUF_WORD3);
     M.xo = (int)((ntb[fc] * R + r0 + m16) * SS);
-    M.cb = (CPtr)(cc + ((int64_t)q * T + slot0) * KRp);
+    M.cb = (CPtr)(cc + ((int64_t)q * nch * T + slot0) * KM);
     M.ldp = B.ldp;
     M.re = B.r_e;
     M.tr = ntr[fc];
     M.nt = M.tr ? B.ns : B.nt;
     return M;
   };
-  S pv[RT][KM], pn[RT][KM], xv[TCB], xn[TCB];
   const int xslot = (int)(n * R * SS);   // bytes of one slot of x
-  auto fetch = [&](const Meta& M, int fg, int fu, int fk) {
+  // loads of one unit into the register set (p, x); x only at the first rank chunk
+  auto fetch = [&](const Meta& M, int fg, int fu, int fk, S (&p)[RT][KM], S (&x)[TCB]) {
     const int j = 16 * fg + 4 * fu + kq;
     const bool jok = j < M.nt;
     // masked lanes start at BUF_OOB; adding rank offsets (below 2 GiB in all, checked on
@@ -180,73 +187,77 @@ __global__ void __launch_bounds__(NT) k_near_fused(
 #pragma unroll
     for (int kk = 0; kk < KM; ++kk)
 #pragma unroll
-      for (int r = 0; r < RT; ++r) pn[r][kk] = widen<S, PT>(bload1<PT>(M.pr, off[r] + kk * M.nepb));
+      for (int r = 0; r < RT; ++r) p[r][kk] = widen<S, PT>(bload1<PT>(M.pr, off[r] + kk * M.nepb));
     if (fk == 0) {
-      const int xo = jok && colok ? M.xo + (int)(slot0 * (int64_t)n * R * SS) + j * (int)(R * SS) : BUF_OOB;
+      const int xo = jok && colok ? M.xo + j * (int)(R * SS) : BUF_OOB;
 #pragma unroll
-      for (int tt = 0; tt < TCB; ++tt) xn[tt] = bload1<S>(xr, tt < tc ? xo + tt * xslot : BUF_OOB);
+      for (int tt = 0; tt < TCB; ++tt) x[tt] = bload1<S>(xr, xo + tt * xslot);
     }
+  };
+  // a unit of the leaf's sequence: block bb (its metadata M), 16-column group g, K-step u,
+  // rank chunk kc; valid while bb < bb1
+  struct Unit {
+    int64_t bb;
+    int g, u, kc;
+    Meta M;
+  };
+  auto next = [&](const Unit& a) {
+    Unit b = a;
+    if (KM == 16 && ++b.kc * KM < a.M.re) return b;   // below 16 ranks one chunk holds them all
+    b.kc = 0;
+    if (++b.u < 4) return b;
+    b.u = 0;
+    if (16 * ++b.g < a.M.nt) return b;
+    b.g = 0;
+    if (++b.bb < bb1) b.M = meta(b.bb);
+    return b;
   };
 
   if (bb0 < bb1) {
-    int64_t bb = bb0;
-    int g = 0, u = 0, kc = 0;
-    Meta M = meta(bb0);
-    Meta Mn = bb0 + 1 < bb1 ? meta(bb0 + 1) : M;
+    // two units in flight: the current one is computed while the next one's loads are
+    // outstanding (the register sets alternate, so the loop is unrolled twice)
+    S p0[RT][KM], p1[RT][KM], x0[TCB], x1[TCB], xv[TCB];
     S d[RT][TCB];
-    fetch(M, g, u, kc);
-    while (true) {
+    Unit u0{bb0, 0, 0, 0, meta(bb0)};
+    Unit u1 = next(u0);
+    fetch(u0.M, u0.g, u0.u, u0.kc, p0, x0);
+    auto step = [&](S (&pc)[RT][KM], S (&xc)[TCB], S (&pf)[RT][KM], S (&xf)[TCB]) {
+      if (u1.bb < bb1) fetch(u1.M, u1.g, u1.u, u1.kc, pf, xf);
+      if (KM < 16 || u0.kc == 0) {
 #pragma unroll
-      for (int r = 0; r < RT; ++r)
-#pragma unroll
-        for (int kk = 0; kk < KM; ++kk) pv[r][kk] = pn[r][kk];
-      if (kc == 0) {
-#pragma unroll
-        for (int tt = 0; tt < TCB; ++tt) xv[tt] = xn[tt];
+        for (int tt = 0; tt < TCB; ++tt) xv[tt] = xc[tt];
 #pragma unroll
         for (int r = 0; r < RT; ++r)
 #pragma unroll
           for (int tt = 0; tt < TCB; ++tt) d[r][tt] = (S)0;
       }
-      // the next unit: next rank chunk, K-step, 16-column group or block
-      int64_t nb = bb;
-      int ng = g, nu = u, nk = kc + 1;
-      if (nk * KM >= M.re) {
-        nk = 0;
-        if (++nu == 4) {
-          nu = 0;
-          if (16 * ++ng >= M.nt) {
-            ng = 0;
-            ++nb;
-          }
-        }
+      // coefficients slot by slot, the next slot's loads in flight while the current one's
+      // FMAs run: two slots of KM scalars at a time (all TCB KM of them would overflow the
+      // scalar registers); the empty asm statements keep the compiler from hoisting them
+      const CPtr cbk = u0.M.cb + (int64_t)u0.kc * T * KM;
+#pragma unroll
+      for (int tt = 0; tt < TCB; ++tt) {
+        S cv[KM];
+#pragma unroll
+        for (int kk = 0; kk < KM; ++kk) cv[kk] = cbk[tt * KM + kk];   // zero for r_e <= k < KRp
+#pragma unroll
+        for (int kk = 0; kk < KM; ++kk)
+#pragma unroll
+          for (int r = 0; r < RT; ++r) d[r][tt] += pc[r][kk] * cv[kk];
+        asm volatile("" ::: "memory");
       }
-      if (nb < bb1) fetch(nb == bb ? M : Mn, ng, nu, nk);
-      const int k0 = kc * KM;
-#pragma unroll
-      for (int kk = 0; kk < KM; ++kk) {
-#pragma unroll
-        for (int tt = 0; tt < TCB; ++tt) {
-          const S c = M.cb[tt * KRp + k0 + kk];   // zero for r_e <= k < KRp
-#pragma unroll
-          for (int r = 0; r < RT; ++r) d[r][tt] += pv[r][kk] * c;
-        }
-      }
-      if (nk == 0) {   // last rank chunk of this K-step
+      if (KM < 16 || u1.bb >= bb1 || u1.kc == 0) {   // last rank chunk of this K-step
 #pragma unroll
         for (int tt = 0; tt < TCB; ++tt)
 #pragma unroll
           for (int r = 0; r < RT; ++r) acc[r][tt] = MF::mac(d[r][tt], xv[tt], acc[r][tt]);
       }
-      if (nb >= bb1) break;
-      if (nb != bb) {
-        M = Mn;
-        if (nb + 1 < bb1) Mn = meta(nb + 1);
-      }
-      bb = nb;
-      g = ng;
-      u = nu;
-      kc = nk;
+      if (u1.bb >= bb1) return false;
+      u0 = u1;
+      u1 = next(u1);
+      return true;
+    };
+    while (step(p0, x0, p1, x1) && step(p1, x1, p0, x0)) {
     }
   }
 #pragma unroll
@@ -268,14 +279,16 @@ __global__ void __launch_bounds__(NT) k_near_fused(
 template <typename S, typename PT>
 __global__ void __launch_bounds__(NT) k_near_block_eval(const NearDev* __restrict__ blocks,
                                                         const PT* __restrict__ Pf, const S* __restrict__ cc,
-                                                        int64_t q, int T, int t, int KRp, double* __restrict__ out) {
+                                                        int64_t q, int T, int t, int KRp, int KM,
+                                                        double* __restrict__ out) {
   const NearDev B = blocks[q];
   const int64_t Ne = (int64_t)B.ns * B.nt, Nep = (int64_t)B.ldp * B.nt;
-  const S* c = cc + ((int64_t)q * T + t) * KRp;
+  const int nch = KRp / KM;
   for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < Ne; o += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = o % B.ns, j = o / B.ns;
     S dv = (S)0;
-    for (int k = 0; k < B.r_e; ++k) dv += widen<S, PT>(Pf[B.P_off + k * Nep + i + j * B.ldp]) * c[k];
+    for (int k = 0; k < B.r_e; ++k)
+      dv += widen<S, PT>(Pf[B.P_off + k * Nep + i + j * B.ldp]) * cc[((q * nch + k / KM) * T + t) * KM + k % KM];
     out[o] = (double)dv;
   }
 }
@@ -313,7 +326,7 @@ void near_cores_launch(InstData& in, hipStream_t st) {
   const int64_t total = m.n_stored_near * in.T * m.KRp;
   launch(PH_STAGE_NEAR_INST, k_near_cores<S>, dim3((unsigned)grid_for(total)), dim3(NT), st,
          (const NearDev*)m.nstore.p, (const double*)m.nf_core.p, (const double*)m.nf_theta.p, (const double*)in.v.p,
-         (S*)in.ccore.p, m.n_stored_near, in.T, m.p_theta, m.d_theta, m.KRp);
+         (S*)in.ccore.p, m.n_stored_near, in.T, m.p_theta, m.d_theta, m.KRp, m.KM);
 }
 template void near_cores_launch<double>(InstData&, hipStream_t);
 template void near_cores_launch<float>(InstData&, hipStream_t);
@@ -353,11 +366,11 @@ void near_fused_launch(InstData& in, const S* xt, S* yt, int64_t Rs, hipStream_t
     launch(PH_STAGE_NEAR_MVM, kern, grid, dim3(NT), st, xt, yt, Pf, (const S*)in.ccore.p,
            (const NearDev*)m.nstore.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
            (const int64_t*)m.near_rowptr.p, (const int32_t*)m.near_q.p, (const int32_t*)m.near_tr.p,
-           (const int64_t*)m.near_tb.p, items, t.leaves.front(), m.n, Rs, in.T, m.KRp, m.near_xcd);
+           (const int64_t*)m.near_tb.p, items, t.leaves.front(), m.n, Rs, in.T, m.KRp / m.KM, m.near_xcd);
   };
   // rank chunk KM: the largest near rank rounded up to 4 when it is at most 16 (one chunk
   // per K-step), else chunks of 16
-  const int km = m.KRp <= 16 ? m.KRp : 16;
+  const int km = m.KM;
   auto by_km = [&](auto tcbc, auto rtc) {
     constexpr int A = decltype(tcbc)::value, B = decltype(rtc)::value;
     if (km == 4) go(k_near_fused<S, PT, A, B, 4>);
@@ -389,7 +402,7 @@ template <typename S, typename PT>
 void near_block_eval(const InstData& in, int t, int64_t q, double* dev_out, hipStream_t st) {
   const DeviceModel& m = *in.m;
   hipLaunchKernelGGL((k_near_block_eval<S, PT>), dim3(64), dim3(NT), 0, st, (const NearDev*)m.nstore.p,
-                     (const PT*)m.near_factors<PT>(), (const S*)in.ccore.p, q, in.T, t, m.KRp, dev_out);
+                     (const PT*)m.near_factors<PT>(), (const S*)in.ccore.p, q, in.T, t, m.KRp, m.KM, dev_out);
   PH_HIP(hipGetLastError());
 }
 template void near_block_eval<double, double>(const InstData&, int, int64_t, double*, hipStream_t);

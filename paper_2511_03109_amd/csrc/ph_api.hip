@@ -144,6 +144,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
     m->max_Nep = std::max(m->max_Nep, (int64_t)q.ldp * q.nt);
   }
   m->KRp = rmax <= 16 ? (rmax + 3) / 4 * 4 : (rmax + 15) / 16 * 16;
+  m->KM = rmax <= 16 ? m->KRp : 16;
   for (int64_t i = 0; i < m->n_leaves; ++i) nrow[i + 1] += nrow[i];
   // near MVM work items, one per 128-row chunk of every leaf (leaf order)
   std::vector<int32_t> items;

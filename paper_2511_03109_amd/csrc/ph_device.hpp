@@ -178,7 +178,8 @@ struct DeviceModel {
   DevArr<int32_t> mvm_items64; // the same with 64-row chunks (factored near MVM, one row tile per wave)
   int64_t n_mvm_items64 = 0;
   DevArr<int32_t> near_q;      // per canonical near block (list order of near_rowptr): its stored block
-  int KRp = 4;                 // largest near rank rounded up to 4: per-slot stride of the factored cores
+  int KRp = 4;                 // largest near rank rounded up to 4 (to 16 above 16)
+  int KM = 4;                  // rank chunk of the factored near MVM: KRp up to 16, else 16
   int64_t max_Nep = 0;         // largest padded factor column (ldp n_t) of a stored near block
   // near factors in the storage type of a factored instance: FP64 as compressed, FP32 and
   // BF16 copies made on the first factored instantiation that needs them (rounded to nearest)
@@ -220,7 +221,8 @@ struct InstData {
   size_t esize = 8;                   // element size of C, x_hat, y_hat, I/O (compute type)
   size_t d_esize = 8;                 // element size of the near blocks D (storage type)
   DevArr<char> D, C;
-  // factored near field (no D): c_b(theta_t) per stored block q and slot t at (q T + t) KRp
+  // factored near field (no D): c_b(theta_t) per stored block q, rank chunk c and slot t at
+  // ((q KRp / KM + c) T + t) KM
   bool factored = false;
   DevArr<char> ccore;
   DevArr<double> v;
