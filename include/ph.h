@@ -225,7 +225,8 @@ int ph_instantiate(const ph_model* m, const double* theta, int T, ph_dtype dt, v
  *                     factors are streamed as an FP32 / BF16 copy (rounded to nearest, made
  *                     once per model on the first such instance) and the blocks are formed in
  *                     FP32.  Near ranks above 64: PH_EUNSUPPORTED.
- *   PH_NEAR_AUTO      FACTORED when T >= 4 and the largest near rank is at most 64, else BLOCKS.
+ *   PH_NEAR_AUTO      FACTORED when 4 <= T <= 8 and the largest near rank is at most 64, else
+ *                     BLOCKS (beyond 8 slots the factors are streamed once per batch of 8).
  * ph_instantiate and ph_instantiate_grad use PH_NEAR_AUTO. */
 typedef enum { PH_NEAR_AUTO = 0, PH_NEAR_BLOCKS = 1, PH_NEAR_FACTORED = 2 } ph_near_mode;
 
@@ -309,13 +310,17 @@ int ph_cg_solve(ph_inst* hi, ph_inst* lo, const double* y, double* a, double nug
  * T slots and R right-hand sides, every combination of coupling class-list chunks
  * (1, 2, 4, 8, 16, at most the longest class list of a target box), register prefetch
  * depth of the coupling pipeline (1, 2) and near field overlapped on a second stream or
- * not is timed (3 runs after a warm-up, HIP events on `stream`), and the fastest is kept
- * in the instance for all later ph_matvec calls.  x, y: as ph_matvec (y is overwritten).
+ * not is timed (3 runs after a warm-up, HIP events on `stream`), then, for a factored
+ * instance, the launch shape of its near-field kernel (8, 4 or 2 parameter slots per
+ * workgroup, 1 or 2 row tiles of 16 per wavefront) with the chosen configuration; the
+ * fastest is kept in the instance for all later ph_matvec calls.  x, y: as ph_matvec (y is overwritten).
  * Synchronises `stream`.  Must precede ph_graph_create (PH_ESTATE after it).  On any
  * failure the instance keeps the configuration it had before the call. */
 typedef struct {
   int chunks, prefetch, overlap;
   double ms;              /* measured time of one ph_matvec with this configuration */
+  int fused_tcb;          /* factored near field: parameter slots per workgroup (0: default) */
+  int fused_rt;           /* factored near field: 16-row tiles per wavefront (0: default) */
 } ph_tune_info;
 int ph_autotune(ph_inst* k, const void* x, void* y, int64_t R, void* stream, ph_tune_info* info);
 

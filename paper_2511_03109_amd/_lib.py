@@ -36,7 +36,8 @@ class CgStats(C.Structure):
 
 
 class TuneInfo(C.Structure):
-    _fields_ = [("chunks", C.c_int), ("prefetch", C.c_int), ("overlap", C.c_int), ("ms", C.c_double)]
+    _fields_ = [("chunks", C.c_int), ("prefetch", C.c_int), ("overlap", C.c_int), ("ms", C.c_double),
+                ("fused_tcb", C.c_int), ("fused_rt", C.c_int)]
 
 
 class ModelInfo(C.Structure):

@@ -913,7 +913,11 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
   // selects whole boxes; quarters measured 5.4-5.6 ms)
   int hb = 2;
   if (const char* env = std::getenv("PH_COUPLING_HALF")) hb = std::atoi(env) == 0 ? 1 : 2;
-  if (Rs == 1 || m.Pp / 16 != 8) hb = 1;
+  // BF16 instances with right-hand-side tiles: the coupling on the BF16 matrix cores (whole
+  // boxes); PH_BF16_COUPLING=0 keeps the FP32 products
+  bool bf16_mc = sizeof(DT) == 2 && Rs >= RC;
+  if (const char* env = std::getenv("PH_BF16_COUPLING")) bf16_mc = bf16_mc && std::atoi(env) != 0;
+  if (Rs == 1 || m.Pp / 16 != 8 || bf16_mc) hb = 1;
   int G = 1;   // a power of two <= 64 (half boxes double the workgroups: 4 chunks)
   if (use_far && m.n_groups > 0) G = m.max_group_entries >= 16 ? 8 / hb : (m.max_group_entries >= 4 ? 2 : 1);
   if (in.tune_chunks > 0) G = in.tune_chunks;
@@ -1056,6 +1060,9 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
                (const int32_t*)m.ent_tau.p, (const int32_t*)m.chunk_first.p + m.chunk_off[ilog2(G)], m.Pp,
                m.n_nodes, Rs, G, Cps, part_stride, (int)ngr);
     };
+    if (bf16_mc) {
+      coupling_bf16_launch(in, (const float*)xh, (float*)cout, G, Rs, nrc, st);
+    } else {
     // 8 waves (4 row groups x 2 target halves) for Pp > 64, else 4 waves over the targets;
     // register prefetch depth 2 (PH_COUPLING_PD or the autotuner may select 1)
     // (half boxes: depth 1 measured 0.5% faster)
@@ -1090,6 +1097,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
       run(k_coupling<S, 4, 1, 2, 1, true>, 4);
     } else {
       run(k_coupling<S, 4, 1, 1, 1, true>, 4);
+    }
     }
     if (G > 1) {
       const int64_t a0 = t.level_start[m.min_far];

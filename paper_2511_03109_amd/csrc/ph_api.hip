@@ -521,7 +521,11 @@ int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype
     const ph::DeviceModel& md = *m->p;
     if (near == PH_NEAR_FACTORED && md.KRp > 64)
       ph::fail(PH_EUNSUPPORTED, "factored near field supports near ranks up to 64");
-    const bool factored = near == PH_NEAR_FACTORED || (near == PH_NEAR_AUTO && T >= 4 && md.KRp <= 64);
+    // automatic form: factored for one batch of 4..8 slots, where each factor entry read
+    // serves every slot (8 slots: 4.4 vs 5.2 ms for the benchmark's near field); from 9 slots
+    // on the factors are streamed once per batch of 8, and the written blocks win (64-slot
+    // mixture sweep: 20 vs 40 ms per MVM)
+    const bool factored = near == PH_NEAR_FACTORED || (near == PH_NEAR_AUTO && T >= 4 && T <= 8 && md.KRp <= 64);
     if (dim >= 0) need(dim < md.d_theta, "gradient dimension out of range");
     for (int t = 0; t < T; ++t)
       for (int k = 0; k < md.d_theta; ++k) {
@@ -844,15 +848,17 @@ int ph_autotune(ph_inst* k, const void* x, void* y, int64_t R, void* stream, ph_
     } ev;
     struct Restore {
       ph::InstData& in;
-      int chunks, prefetch, overlap;
+      int chunks, prefetch, overlap, tcb, rt;
       bool done = false;
       ~Restore() {
         if (done) return;
         in.tune_chunks = chunks;
         in.tune_prefetch = prefetch;
         in.tune_overlap = overlap;
+        in.tune_fused_tcb = tcb;
+        in.tune_fused_rt = rt;
       }
-    } restore{in, in.tune_chunks, in.tune_prefetch, in.tune_overlap};
+    } restore{in, in.tune_chunks, in.tune_prefetch, in.tune_overlap, in.tune_fused_tcb, in.tune_fused_rt};
     PH_HIP(hipEventCreate(&ev.a));
     PH_HIP(hipEventCreate(&ev.b));
     hipEvent_t a = ev.a, b = ev.b;
@@ -868,6 +874,16 @@ int ph_autotune(ph_inst* k, const void* x, void* y, int64_t R, void* stream, ph_
     for (int g : {2, 4, 8, 16})
       if (g <= m.max_group_entries) chunks.push_back(g);
     const int reps = 3;
+    auto time_it = [&] {
+      run();   // warm-up (allocates scratch for this configuration)
+      PH_HIP(hipEventRecord(a, st));
+      for (int r = 0; r < reps; ++r) run();
+      PH_HIP(hipEventRecord(b, st));
+      PH_HIP(hipEventSynchronize(b));
+      float ms = 0;
+      PH_HIP(hipEventElapsedTime(&ms, a, b));
+      return ms / reps;
+    };
     float best = 1e30f;
     ph_tune_info bi{};
     for (int ov : {1, 0})
@@ -876,22 +892,34 @@ int ph_autotune(ph_inst* k, const void* x, void* y, int64_t R, void* stream, ph_
           in.tune_chunks = g;
           in.tune_prefetch = pd;
           in.tune_overlap = ov;
-          run();   // warm-up (allocates scratch for this configuration)
-          PH_HIP(hipEventRecord(a, st));
-          for (int r = 0; r < reps; ++r) run();
-          PH_HIP(hipEventRecord(b, st));
-          PH_HIP(hipEventSynchronize(b));
-          float ms = 0;
-          PH_HIP(hipEventElapsedTime(&ms, a, b));
-          ms /= reps;
+          const float ms = time_it();
           if (ms < best) {
             best = ms;
-            bi = ph_tune_info{g, pd, ov, (double)ms};
+            bi = ph_tune_info{g, pd, ov, (double)ms, in.tune_fused_tcb, in.tune_fused_rt};
           }
         }
     in.tune_chunks = bi.chunks;
     in.tune_prefetch = bi.prefetch;
     in.tune_overlap = bi.overlap;
+    if (in.factored) {
+      // then the factored near MVM's launch shape with that configuration: slots per
+      // workgroup (each factor entry is read once per batch of them) and row tiles per wave
+      for (int tcb : {8, 4, 2})
+        for (int rt : {1, 2}) {
+          if (tcb > 2 && tcb / 2 >= in.T) continue;   // the launch would clamp it
+          in.tune_fused_tcb = tcb;
+          in.tune_fused_rt = rt;
+          const float ms = time_it();
+          if (ms < best) {
+            best = ms;
+            bi.fused_tcb = tcb;
+            bi.fused_rt = rt;
+            bi.ms = ms;
+          }
+        }
+      in.tune_fused_tcb = bi.fused_tcb;
+      in.tune_fused_rt = bi.fused_rt;
+    }
     restore.done = true;
     if (info) *info = bi;
   });

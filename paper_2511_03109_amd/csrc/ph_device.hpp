@@ -286,6 +286,10 @@ void near_fused_launch(InstData& in, const S* xt, S* yt, int64_t Rs, hipStream_t
 template <typename S, typename PT>
 void near_block_eval(const InstData& in, int t, int64_t q, double* dev_out, hipStream_t st);
 void make_low_factors(const DeviceModel& m, ph_dtype dt, hipStream_t st);
+// coupling of a PH_BF16 instance on the BF16 matrix cores (k_coupling_bf16.hip): whole
+// target boxes, class-list chunks G, Rs a multiple of 16, output to the partials or y_hat
+void coupling_bf16_launch(const InstData& in, const float* xh, float* out, int G, int64_t Rs, int64_t nrc,
+                          hipStream_t st);
 void cg_solve_impl(InstData& hi, InstData* lo, const double* y, double* a, double nugget, double tol,
                    int max_iter, int inner_max, double inner_tol, ph_cg_stats* stats, hipStream_t st);
 

@@ -453,25 +453,137 @@ def test_bf16_near_blocks_are_rounded_fp64_blocks():
         assert np.array_equal(i16.near_block(b), _bf16_round(i64.near_block(b))), f"block {b}"
 
 
+U_BF16 = 2.0 ** -8   # unit roundoff of BF16 (8 significant bits, round to nearest)
+
+
+def _far_magnitude(om, oi, x):
+    """The far field applied to magnitudes: |U| (|E| ... (sum over far blocks |C| |x_hat|)) with
+    x_hat from the exact upward pass.  Rounding C and x_hat to BF16 (relative u each) perturbs
+    the coupling by at most 2u |C| |x_hat| to first order, and the FP32 downward pass carries
+    that to y at most as this magnitude."""
+    t = om.tree
+    xt = x[t.perm]
+    xh = om._upward(xt)
+    yh = {s: np.zeros((om.P, x.shape[1])) for s in range(t.n_nodes)}
+    for bi, (s, u) in enumerate(om.far):
+        yh[s] += np.abs(oi["C"][om.far_key(bi)]) @ np.abs(xh[u])
+    yt = np.zeros_like(xt)
+    for s in range(t.n_nodes):
+        if t.children[s]:
+            for c in t.children[s]:
+                yh[c] += np.abs(om.transfer(c)) @ yh[s]
+        else:
+            yt[t.begin[s]:t.end[s]] += np.abs(om.cluster_basis(s)) @ yh[s]
+    y = np.empty_like(x)
+    y[t.perm] = yt
+    return y
+
+
+def _near_factor_magnitude(om, theta, x):
+    """The near field formed from magnitudes of its factors, sum_k |P_b[k]| |c_b[k]| applied
+    to |x|: the bound on the blocks formed from BF16 factors (each factor entry relative u)."""
+    vs = om.theta_vectors(theta)
+    D = {}
+    for bi, (s, u) in enumerate(om.near):
+        core, facs = om.near_factors(bi)
+        c = core
+        for i in range(om.d_theta):
+            c = np.tensordot(c, facs[1 + i].T @ vs[i], axes=([1], [0]))
+        ns, nt = len(om.tree.idx[s]), len(om.tree.idx[u])
+        D[bi] = (np.abs(facs[0]) @ np.abs(c)).reshape(nt, ns).T
+    return om.matvec({"D": D, "C": {k: np.zeros((om.P, om.P)) for k in range(len(om.classes))}}, np.abs(x))
+
+
+def _bf16_emulated(om, oi, x, D):
+    """The BF16 instance's arithmetic emulated in FP64: near blocks D as given (rounded by the
+    caller), C and x_hat rounded to BF16 before the coupling, everything else exact.  The GPU
+    differs from it by its FP32 arithmetic (and by the rare x_hat value whose FP32 and FP64
+    forms round to different BF16 neighbours)."""
+    t = om.tree
+    xt = x[t.perm]
+    xh = {s: _bf16_round(v) for s, v in om._upward(xt).items()}
+    yh = {s: np.zeros((om.P, x.shape[1])) for s in range(t.n_nodes)}
+    for bi, (s, u) in enumerate(om.far):
+        yh[s] += _bf16_round(oi["C"][om.far_key(bi)]) @ xh[u]
+    yt = np.zeros_like(xt)
+    for bi, (s, u) in enumerate(om.near):
+        yt[t.begin[s]:t.end[s]] += D[bi] @ xt[t.begin[u]:t.end[u]]
+    for s in range(t.n_nodes):
+        if t.children[s]:
+            for c in t.children[s]:
+                yh[c] += om.transfer(c) @ yh[s]
+        else:
+            yt[t.begin[s]:t.end[s]] += om.cluster_basis(s) @ yh[s]
+    y = np.empty_like(x)
+    y[t.perm] = yt
+    return y
+
+
 def test_bf16_mvm_error_bound():
-    """BF16 near blocks: ||y - y_oracle|| <= 2^-8 || |D| |x| || (unit roundoff of BF16 times the
-    near field applied to magnitudes) + 2e-6 ||y_oracle|| (the FP32 arithmetic, as the FP32 test)."""
+    """BF16 near blocks (T = 1: written blocks, each entry of the FP64 instantiation rounded) and
+    the coupling on the BF16 matrix cores (R = 4, one RHS tile: C and x_hat rounded to BF16,
+    FP32 accumulation):  ||y - y_oracle|| <= u || |D| |x| || + 2u || far magnitude ||
+    + 2e-6 ||y_oracle|| (the FP32 arithmetic, as the FP32 test), u = 2^-8."""
     torch = _torch()
     from paper_2511_03109_amd import api
     X = inputs.points_for(2, 4096)
     lt, lm, om = _setup(X, "matern32", [0.05], [0.5], 5, 11, 1e-8, 2, (3, 1))
     x = inputs.normal_vectors(4096, 4, 9)
-    y = api.Instance(lm, [0.3], dtype="bf16").matvec(
-        torch.tensor(np.ascontiguousarray(x.T), device="cuda", dtype=torch.float32)).cpu().numpy().T
+    inst = api.Instance(lm, [0.3], dtype="bf16")
+    assert not inst.factored
+    y = inst.matvec(torch.tensor(np.ascontiguousarray(x.T), device="cuda", dtype=torch.float32)).cpu().numpy().T
     oi = om.instantiate(0.3)
     y_o = om.matvec(oi, x)
     mag = om.matvec({"D": {b: np.abs(D) for b, D in oi["D"].items()},
                      "C": {k: np.zeros_like(C) for k, C in oi["C"].items()}}, np.abs(x))
+    far = _far_magnitude(om, oi, x)
     err = np.linalg.norm(y - y_o)
-    bound = 2.0 ** -8 * np.linalg.norm(mag) + 2e-6 * np.linalg.norm(y_o)
+    bound = U_BF16 * np.linalg.norm(mag) + 2 * U_BF16 * np.linalg.norm(far) + 2e-6 * np.linalg.norm(y_o)
     print(f"[parity] bf16 mvm: relative error {err / np.linalg.norm(y_o):.3e}, bound {bound / np.linalg.norm(y_o):.3e}",
           flush=True)
     assert err <= bound
+    # against the emulated BF16 arithmetic: the FP32 bound of the FP32 instance (2e-6) with
+    # room for rounding-boundary flips of x_hat
+    y_e = _bf16_emulated(om, oi, x, {b: _bf16_round(D) for b, D in oi["D"].items()})
+    _close(y, y_e, 1e-5, what="bf16 mvm vs emulated BF16 arithmetic")
+
+
+def test_bf16_factored_mvm_error_bound():
+    """BF16 factored near field (T = 4: blocks formed in FP32 from the BF16 copy of the factors)
+    and the BF16 coupling, 16 RHS:  ||y_t - y_oracle,t|| <= u || sum_k |P_k| |c_k| |x| ||
+    + 2u || far magnitude || + 2e-6 ||y_oracle,t|| for every slot."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    n, T, R = 4096, 4, 16
+    X = inputs.points_for(2, n)
+    lt, lm, om = _setup(X, "matern32", [0.05], [0.5], 5, 11, 1e-8, 2, (3, 1))
+    thetas = np.array([[0.07], [0.19], [0.3], [0.44]])
+    inst = api.Instance(lm, thetas, dtype="bf16")
+    assert inst.factored
+    x = inputs.normal_vectors(n, T * R, 19).T.reshape(T, R, n)
+    y = inst.matvec(torch.tensor(np.ascontiguousarray(x), device="cuda", dtype=torch.float32)).cpu().numpy()
+    for t in range(T):
+        oi = om.instantiate(thetas[t])
+        y_o = om.matvec(oi, x[t].T)
+        near = _near_factor_magnitude(om, thetas[t], x[t].T)
+        far = _far_magnitude(om, oi, x[t].T)
+        err = np.linalg.norm(y[t].T - y_o)
+        bound = U_BF16 * np.linalg.norm(near) + 2 * U_BF16 * np.linalg.norm(far) + 2e-6 * np.linalg.norm(y_o)
+        print(f"[parity] bf16 factored slot {t}: relative error {err / np.linalg.norm(y_o):.3e}, "
+              f"bound {bound / np.linalg.norm(y_o):.3e}", flush=True)
+        assert err <= bound
+        # emulated: blocks formed from the BF16-rounded factor (the oracle's factor equals the
+        # library's up to column signs, which rounding preserves)
+        vs = om.theta_vectors(thetas[t])
+        D = {}
+        for bi, (s_, u_) in enumerate(om.near):
+            core, facs = om.near_factors(bi)
+            c = core
+            for i in range(om.d_theta):
+                c = np.tensordot(c, facs[1 + i].T @ vs[i], axes=([1], [0]))
+            ns, nt = len(om.tree.idx[s_]), len(om.tree.idx[u_])
+            D[bi] = (_bf16_round(facs[0]) @ c).reshape(nt, ns).T
+        _close(y[t].T, _bf16_emulated(om, oi, x[t].T, D), 1e-5, what=f"bf16 factored slot {t} vs emulated")
 
 
 def _solve_case(kernel, theta, nugget, dtype_lo, tol):
@@ -535,6 +647,7 @@ def test_autotune_and_graph_replays():
     print(f"[parity] autotune: {cfg}", flush=True)
     assert cfg["chunks"] in (1, 2, 4, 8, 16) and cfg["prefetch"] in (1, 2) and cfg["overlap"] in (0, 1)
     assert cfg["ms"] > 0
+    assert inst.factored and cfg["fused_tcb"] in (2, 4, 8) and cfg["fused_rt"] in (1, 2)
     s = torch.cuda.Stream()
     g = inst.record(x, y, stream=s)
     ref = torch.empty_like(x)
