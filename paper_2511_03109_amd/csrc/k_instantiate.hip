@@ -260,6 +260,7 @@ void instantiate_impl(InstData& in, const double* theta, hipStream_t st) {
            (unsigned)m.n_stored_cls), dim3(NT), st, (const ClassDev*)m.cstore.p, (const double*)m.ff_chat.p,
            (const double*)m.ff_theta.p, (const double*)in.v.p, (S*)in.C.p, Cps, m.Pp, in.T, m.p_theta, m.d_theta);
   }
+  if (in.Cb.n > 0) coupling_bf16_pack_c(in, st);   // BF16 copy of C for the BF16 coupling
   if (in.factored) {
     // factored near field: only c_b(theta_t) per stored block (the MVM forms the blocks)
     near_cores_launch<S>(in, st);

@@ -915,7 +915,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
   if (const char* env = std::getenv("PH_COUPLING_HALF")) hb = std::atoi(env) == 0 ? 1 : 2;
   // BF16 instances with right-hand-side tiles: the coupling on the BF16 matrix cores (whole
   // boxes); PH_BF16_COUPLING=0 keeps the FP32 products
-  bool bf16_mc = sizeof(DT) == 2 && Rs >= RC;
+  bool bf16_mc = sizeof(DT) == 2 && in.Cb.n > 0 && use_far && coupling_bf16_supported(m, Rs);
   if (const char* env = std::getenv("PH_BF16_COUPLING")) bf16_mc = bf16_mc && std::atoi(env) != 0;
   if (Rs == 1 || m.Pp / 16 != 8 || bf16_mc) hb = 1;
   int G = 1;   // a power of two <= 64 (half boxes double the workgroups: 4 chunks)
@@ -938,6 +938,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
                   m.n_classes * m.Pp * m.Pp * (int64_t)sizeof(S) > BUF_MAX_BYTES))
     fail(PH_EUNSUPPORTED, "ph_matvec: per-slot coupling buffers exceed 2 GiB (reduce R)");
   S *xt, *yt, *xh, *yh, *partp = nullptr, *zbp = nullptr;
+  void* xbp = nullptr;
   if (ext) {
     // caller-provided scratch (no allocation): the same buffers carved at 256-byte offsets
     size_t off = 0;
@@ -952,6 +953,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     yh = carve((size_t)T * m.n_nodes * m.Pp * Rs * sizeof(S));
     if (G > 1) partp = carve((size_t)G * T * m.n_nodes * m.Pp * Rs * sizeof(S));
     if (need_zb) zbp = carve((size_t)T * m.Zt * sizeof(S));
+    if (bf16_mc) xbp = carve((size_t)T * coupling_bf16_x_bytes(m, Rs));
     if (off > ext->bytes)
       fail(PH_EINVAL, "ph_matvec_noalloc: this MVM needs " + std::to_string(off) + " bytes of scratch, more than the " +
                           std::to_string(ext->bytes) + " the library reserves per GPU");
@@ -978,6 +980,14 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
   yh = (S*)in.yh.p;
   partp = (S*)in.part.p;
   zbp = (S*)in.zb.p;
+  if (bf16_mc) {
+    const size_t need = (size_t)T * coupling_bf16_x_bytes(m, Rs);
+    if (in.xb.n < need) {
+      if (in.graphs > 0) fail(PH_ESTATE, "ph_matvec: the instance has recorded graphs, its scratch cannot grow");
+      in.xb.alloc(need);
+    }
+    xbp = in.xb.p;
+  }
   }
   const int32_t leaf0 = t.leaves.front();
   const int64_t Cps = m.n_classes * m.Pp * m.Pp;
@@ -1061,7 +1071,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
                m.n_nodes, Rs, G, Cps, part_stride, (int)ngr);
     };
     if (bf16_mc) {
-      coupling_bf16_launch(in, (const float*)xh, (float*)cout, G, Rs, nrc, st);
+      coupling_bf16_launch(in, (const float*)xh, xbp, (float*)cout, G, Rs, nrc, t.level_start[m.min_far], st);
     } else {
     // 8 waves (4 row groups x 2 target halves) for Pp > 64, else 4 waves over the targets;
     // register prefetch depth 2 (PH_COUPLING_PD or the autotuner may select 1)

@@ -417,6 +417,10 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   m->grp_entry.upload(gptr.data(), gptr.size(), st);
   m->ent_cls.upload(ecls.data(), ecls.size(), st);
   m->ent_tau.upload(etau.data(), etau.size(), st);
+  std::vector<int32_t> emask(ecls.size(), 0);
+  for (size_t e = 0; e < ecls.size(); ++e)
+    for (int sl = 0; sl < NTG; ++sl) emask[e] |= (etau[e * NTG + sl] >= 0 ? 1 : 0) << sl;
+  m->ent_mask.upload(emask.data(), emask.size(), st);
   m->hgrp_targets.upload(hgt.data(), hgt.size(), st);
   m->hent_cls.upload(hecls.data(), hecls.size(), st);
   m->hent_tau.upload(hetau.data(), hetau.size(), st);
@@ -453,7 +457,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
                               m->up_rowptr.bytes() + m->up_tb.bytes() + m->up_D.bytes() + m->up_z.bytes() +
                               m->up_nt.bytes() + m->lo_rowptr.bytes() + m->lo_z.bytes() +
                               m->cstore.bytes() + m->ff_chat.bytes() + m->ff_theta.bytes() + m->grp_targets.bytes() +
-                              m->grp_entry.bytes() + m->ent_cls.bytes() + m->ent_tau.bytes() +
+                              m->grp_entry.bytes() + m->ent_cls.bytes() + m->ent_tau.bytes() + m->ent_mask.bytes() +
                               m->chunk_first.bytes() + m->mvm_items.bytes() + m->mvm_items64.bytes() + m->near_q.bytes() + m->hgrp_targets.bytes() + m->hent_cls.bytes() +
                               m->hent_tau.bytes() + m->hchunk_first.bytes());
   return m;
@@ -561,6 +565,8 @@ int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype
         in->D.alloc((size_t)T * md.N_nf_pad * in->d_esize);
       }
       in->C.alloc((size_t)T * md.n_classes * md.Pp * md.Pp * in->esize);
+      if (dt == PH_BF16 && md.min_far >= 0 && md.n_groups > 0 && ph::coupling_bf16_supported(md, ph::RC))
+        in->Cb.alloc((size_t)T * ph::coupling_bf16_c_bytes(md));
       in->v.alloc((size_t)T * md.d_theta * md.p_theta);
       in->theta_d.alloc((size_t)T * md.d_theta);
       PH_HIP(hipHostMalloc((void**)&in->theta_pin, (size_t)T * md.d_theta * sizeof(double), hipHostMallocDefault));

@@ -200,6 +200,7 @@ struct DeviceModel {
   DevArr<int32_t> grp_entry;              // n_groups + 1
   DevArr<int32_t> ent_cls;                // per entry: class
   DevArr<int32_t> ent_tau;                // per entry: NTG source nodes (-1 = target unused)
+  DevArr<int32_t> ent_mask;               // per entry: bit s set if target s uses the class
   // class-list chunks of equal estimated work: for G = 2^c (c = 0..6), box b's chunk g
   // is entries [chunk_first[chunk_off[c] + b (G + 1) + g], ... + g + 1)
   DevArr<int32_t> chunk_first;
@@ -221,6 +222,9 @@ struct InstData {
   size_t esize = 8;                   // element size of C, x_hat, y_hat, I/O (compute type)
   size_t d_esize = 8;                 // element size of the near blocks D (storage type)
   DevArr<char> D, C;
+  // BF16 instances: C in the operand order of the BF16 coupling ([slot][class][32-wide K
+  // panel][row tile][lane][8]); xb: the matching BF16 copy of x_hat (MVM scratch)
+  DevArr<char> Cb, xb;
   // factored near field (no D): c_b(theta_t) per stored block q, rank chunk c and slot t at
   // ((q KRp / KM + c) T + t) KM
   bool factored = false;
@@ -286,10 +290,17 @@ void near_fused_launch(InstData& in, const S* xt, S* yt, int64_t Rs, hipStream_t
 template <typename S, typename PT>
 void near_block_eval(const InstData& in, int t, int64_t q, double* dev_out, hipStream_t st);
 void make_low_factors(const DeviceModel& m, ph_dtype dt, hipStream_t st);
-// coupling of a PH_BF16 instance on the BF16 matrix cores (k_coupling_bf16.hip): whole
-// target boxes, class-list chunks G, Rs a multiple of 16, output to the partials or y_hat
-void coupling_bf16_launch(const InstData& in, const float* xh, float* out, int G, int64_t Rs, int64_t nrc,
-                          hipStream_t st);
+// Coupling of a PH_BF16 instance on the BF16 matrix cores (k_coupling_bf16.hip; whole target
+// boxes, class-list chunks G, Rs a multiple of 16, output to the partials or y_hat): operand
+// sizes per slot, whether the model's shape is supported, the C repacking after
+// instantiation, and the coupling launch (x_hat repacked into xb for the nodes >= a0, then
+// the matrix-core pass)
+int64_t coupling_bf16_c_bytes(const DeviceModel& m);
+int64_t coupling_bf16_x_bytes(const DeviceModel& m, int64_t Rs);
+bool coupling_bf16_supported(const DeviceModel& m, int64_t Rs);
+void coupling_bf16_pack_c(const InstData& in, hipStream_t st);
+void coupling_bf16_launch(const InstData& in, const float* xh, void* xb, float* out, int G, int64_t Rs, int64_t nrc,
+                          int64_t a0, hipStream_t st);
 void cg_solve_impl(InstData& hi, InstData* lo, const double* y, double* a, double nugget, double tol,
                    int max_iter, int inner_max, double inner_tol, ph_cg_stats* stats, hipStream_t st);
 

@@ -494,6 +494,52 @@ def _near_factor_magnitude(om, theta, x):
     return om.matvec({"D": D, "C": {k: np.zeros((om.P, om.P)) for k in range(len(om.classes))}}, np.abs(x))
 
 
+def _far_from(om, oi, xh_abs):
+    """|U| (|E| ... (sum over far blocks |C| xh_abs)) for non-negative per-node vectors xh_abs."""
+    t = om.tree
+    R = next(iter(xh_abs.values())).shape[1]
+    yh = {s: np.zeros((om.P, R)) for s in range(t.n_nodes)}
+    for bi, (s, u) in enumerate(om.far):
+        yh[s] += np.abs(oi["C"][om.far_key(bi)]) @ xh_abs[u]
+    yt = np.zeros((t.end[0] - t.begin[0], R))
+    for s in range(t.n_nodes):
+        if t.children[s]:
+            for c in t.children[s]:
+                yh[c] += np.abs(om.transfer(c)) @ yh[s]
+        else:
+            yt[t.begin[s]:t.end[s]] += np.abs(om.cluster_basis(s)) @ yh[s]
+    y = np.empty_like(yt)
+    y[t.perm] = yt
+    return y
+
+
+def _bf16_flip_bound(om, oi, x):
+    """What rounding-boundary flips of x_hat can add to the BF16 coupling.  The library forms
+    x_hat in FP32: it differs from the exact x_hat by at most delta = gamma (|U|^T ... |x|)
+    (the upward pass on magnitudes), gamma = (largest leaf + levels P) 2^-24.  Where
+    [x_hat - delta, x_hat + delta] holds a BF16 rounding boundary, the library may round to
+    the other neighbour: such entries contribute up to the gap between the two roundings,
+    carried to y by the far field on magnitudes."""
+    t = om.tree
+    xt = np.abs(x[t.perm])
+    xh = om._upward(x[t.perm])
+    mag = {}
+    for s in reversed(range(t.n_nodes)):
+        if not t.children[s]:
+            mag[s] = np.abs(om.cluster_basis(s)).T @ xt[t.begin[s]:t.end[s]]
+        else:
+            mag[s] = sum(np.abs(om.transfer(c)).T @ mag[c] for c in t.children[s])
+    leaf_max = max(t.end[s] - t.begin[s] for s in range(t.n_nodes) if not t.children[s])
+    levels = 1
+    s = 0
+    while t.children[s]:
+        s = t.children[s][0]
+        levels += 1
+    gamma = (leaf_max + levels * om.P) * 2.0 ** -24
+    gap = {s: np.abs(_bf16_round(xh[s] + gamma * mag[s]) - _bf16_round(xh[s] - gamma * mag[s])) for s in xh}
+    return _far_from(om, oi, gap)
+
+
 def _bf16_emulated(om, oi, x, D):
     """The BF16 instance's arithmetic emulated in FP64: near blocks D as given (rounded by the
     caller), C and x_hat rounded to BF16 before the coupling, everything else exact.  The GPU
@@ -519,6 +565,16 @@ def _bf16_emulated(om, oi, x, D):
     return y
 
 
+def _close_emulated(y, y_e, y_o, flips, what):
+    """The library against the emulated BF16 arithmetic: ||y - y_e|| <= 2e-6 ||y_oracle|| (the
+    FP32 arithmetic, the bound of the FP32 instance) + ||flips|| (_bf16_flip_bound)."""
+    err = np.linalg.norm(y - y_e)
+    bound = 2e-6 * np.linalg.norm(y_o) + np.linalg.norm(flips)
+    print(f"[parity] {what}: {err / np.linalg.norm(y_o):.3e} of the result, bound {bound / np.linalg.norm(y_o):.3e} "
+          f"(flips {np.linalg.norm(flips) / np.linalg.norm(y_o):.1e})", flush=True)
+    assert err <= bound, f"{what}: {err:.3e} > {bound:.3e}"
+
+
 def test_bf16_mvm_error_bound():
     """BF16 near blocks (T = 1: written blocks, each entry of the FP64 instantiation rounded) and
     the coupling on the BF16 matrix cores (R = 4, one RHS tile: C and x_hat rounded to BF16,
@@ -542,10 +598,10 @@ def test_bf16_mvm_error_bound():
     print(f"[parity] bf16 mvm: relative error {err / np.linalg.norm(y_o):.3e}, bound {bound / np.linalg.norm(y_o):.3e}",
           flush=True)
     assert err <= bound
-    # against the emulated BF16 arithmetic: the FP32 bound of the FP32 instance (2e-6) with
-    # room for rounding-boundary flips of x_hat
+    # against the emulated BF16 arithmetic: the FP32 bound of the FP32 instance (2e-6) plus
+    # what rounding-boundary flips of x_hat can add
     y_e = _bf16_emulated(om, oi, x, {b: _bf16_round(D) for b, D in oi["D"].items()})
-    _close(y, y_e, 1e-5, what="bf16 mvm vs emulated BF16 arithmetic")
+    _close_emulated(y, y_e, y_o, _bf16_flip_bound(om, oi, x), "bf16 mvm vs emulated BF16 arithmetic")
 
 
 def test_bf16_factored_mvm_error_bound():
@@ -583,7 +639,42 @@ def test_bf16_factored_mvm_error_bound():
                 c = np.tensordot(c, facs[1 + i].T @ vs[i], axes=([1], [0]))
             ns, nt = len(om.tree.idx[s_]), len(om.tree.idx[u_])
             D[bi] = (_bf16_round(facs[0]) @ c).reshape(nt, ns).T
-        _close(y[t].T, _bf16_emulated(om, oi, x[t].T, D), 1e-5, what=f"bf16 factored slot {t} vs emulated")
+        _close_emulated(y[t].T, _bf16_emulated(om, oi, x[t].T, D), y_o, _bf16_flip_bound(om, oi, x[t].T),
+                        f"bf16 factored slot {t} vs emulated")
+
+
+@pytest.mark.parametrize("case", ["2d_ps6_R20", "2d_ps4_T3_R16", "2d_ps7_R17"])
+def test_bf16_coupling_shapes(case):
+    """The BF16 coupling at node counts whose padded size Pp is not a multiple of the 32-wide
+    K panel or of four row tiles, and with more than one RHS tile: Pp = 48 (p_s = 6 in 2-D: 3
+    row tiles, a K panel half padding), Pp = 16 (p_s = 4: one row tile, three slots) and
+    Pp = 64 with R = 17 (two RHS tiles, the second holding one column).  Every slot against
+    the emulated BF16 arithmetic (near blocks, C and x_hat rounded to BF16) within the FP32
+    bound, and against the oracle within the BF16 error bound."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    p_s, T, R = {"2d_ps6_R20": (6, 1, 20), "2d_ps4_T3_R16": (4, 3, 16), "2d_ps7_R17": (7, 2, 17)}[case]
+    n = 3000
+    X = inputs.points_for(1, n)
+    lt, lm, om = _setup(X, "gaussian", [0.05], [0.5], p_s, 9, 1e-8, 3, (2, 1))
+    thetas = inputs.theta_samples(T, [0.05], [0.5], 23)
+    inst = api.Instance(lm, thetas, dtype="bf16")
+    assert not inst.factored
+    x = inputs.normal_vectors(n, T * R, 29).T.reshape(T, R, n)
+    y = inst.matvec(torch.tensor(np.ascontiguousarray(x), device="cuda", dtype=torch.float32)).cpu().numpy()
+    for t in range(T):
+        oi = om.instantiate(thetas[t])
+        y_o = om.matvec(oi, x[t].T)
+        mag = om.matvec({"D": {b: np.abs(D) for b, D in oi["D"].items()},
+                         "C": {k: np.zeros_like(C) for k, C in oi["C"].items()}}, np.abs(x[t].T))
+        far = _far_magnitude(om, oi, x[t].T)
+        err = np.linalg.norm(y[t].T - y_o)
+        bound = U_BF16 * np.linalg.norm(mag) + 2 * U_BF16 * np.linalg.norm(far) + 2e-6 * np.linalg.norm(y_o)
+        print(f"[parity] bf16 coupling {case} slot {t}: relative error {err / np.linalg.norm(y_o):.3e}, "
+              f"bound {bound / np.linalg.norm(y_o):.3e}", flush=True)
+        assert err <= bound
+        y_e = _bf16_emulated(om, oi, x[t].T, {b: _bf16_round(D) for b, D in oi["D"].items()})
+        _close_emulated(y[t].T, y_e, y_o, _bf16_flip_bound(om, oi, x[t].T), f"bf16 coupling {case} slot {t} vs emulated")
 
 
 def _solve_case(kernel, theta, nugget, dtype_lo, tol):
