@@ -52,6 +52,13 @@ enum {
  *   ANISO_GAUSSIAN  exp(-sum_k (x_k - y_k)^2 / (2 l_k^2))         d_theta = d (d <= 2)
  *   POLY_TEST       theta^2 r^2 + theta (test kernel; reproduced exactly by p >= 3)
  *   POLY2_TEST      theta_1 r^2 + theta_2^2 (test kernel, d_theta = 2)
+ *   MATERN          2^(1 - nu) / Gamma(nu) z^nu K_nu(z), z = sqrt(2 nu) r / lambda, value 1 at
+ *                   r = 0; d_theta = 2, theta = (lambda, nu), lambda > 0, nu > 0 (Table "Kernel
+ *                   functions", MN, with parameter space (lambda, nu) as in Sec. "Numerical
+ *                   Experiments"; K_nu is the modified Bessel function of the second kind,
+ *                   evaluated by the library's own routine: Temme's series for z <= 2, the
+ *                   minimal solution of the confluent-hypergeometric recurrence above; within
+ *                   1.4e-14 relative of quadrature for 0.5 <= nu <= 3).  nu = 1/2 and 3/2 give MATERN12 and MATERN32.
  */
 typedef enum {
   PH_KERNEL_GAUSSIAN = 0,
@@ -59,8 +66,19 @@ typedef enum {
   PH_KERNEL_MATERN12 = 2,
   PH_KERNEL_ANISO_GAUSSIAN = 3,
   PH_KERNEL_POLY_TEST = 4,
-  PH_KERNEL_POLY2_TEST = 5
+  PH_KERNEL_POLY2_TEST = 5,
+  PH_KERNEL_MATERN = 6
 } ph_kernel;
+
+/* Kernel values on the host (Table "Kernel functions"): out[i] = kappa(x_i, y_i; theta) for
+ * i < n, with x, y host arrays of n points (row-major n x d) and theta the d_theta parameters
+ * of the kernel (d_theta as for ph_offline_compress).  For exact reference values, e.g. the
+ * rows of K(X, X; theta) x that the paper's error estimate compares against.  Errors:
+ * PH_EINVAL for a NULL pointer, n < 0 or d outside 1..3, PH_EUNSUPPORTED for an unknown
+ * kernel or a kernel / d combination the offline stage rejects, PH_EDOMAIN for a
+ * non-positive length scale or nu. */
+int ph_kernel_eval(ph_kernel kernel, int d, const double* x, const double* y, int64_t n, const double* theta,
+                   double* out);
 
 /* Arithmetic of an instance.  PH_F64: FP64 storage and arithmetic, I/O in double.
  * PH_F32: FP32 storage of the instantiated blocks, FP32 arithmetic (matrix cores with

@@ -3,7 +3,8 @@
 The workloads use closed-form kernels (the paper's Table "kernel functions"
 lists E = exp(-r/lambda), which is Matern-1/2; the Gaussian and Matern-3/2 are
 the standard closed forms with length scale l, and the anisotropic Gaussian has
-one length scale per axis).  All are stationary and symmetric, which is what the
+one length scale per axis), and the table's Matern kernel with free smoothness nu
+(two parameters, lambda and nu).  All are stationary and symmetric, which is what the
 translation-invariance argument of Sec. 5.2 needs.
 
 Each kernel takes broadcastable arrays x (..., d), y (..., d), theta (..., d_theta)
@@ -44,6 +45,26 @@ def aniso_gaussian(x, y, theta):
     return np.exp(-np.sum(diff * diff / (2.0 * l * l), axis=-1))
 
 
+def matern(x, y, theta):
+    """Matern kernel with free smoothness (Table "Kernel functions", MN), theta = (lambda, nu):
+    2^(1 - nu) / Gamma(nu) z^nu K_nu(z), z = sqrt(2 nu) r / lambda, K_nu the modified Bessel
+    function of the second kind (scipy.special.kv), and the limit 1 at r = 0.  The table
+    prints Gamma(lambda) in the prefactor; the normalising constant of the Matern family is
+    Gamma(nu), which is what makes the value 1 at r = 0."""
+    from scipy.special import gammaln, kv
+    th = np.asarray(theta, dtype=np.float64)
+    lam, nu = th[..., 0], th[..., 1]
+    r = np.sqrt(_r2(x, y))
+    z = np.sqrt(2.0 * nu) * r / lam
+    z, nu = np.broadcast_arrays(z, nu)
+    out = np.ones(z.shape)
+    pos = z > 0
+    zp, nup = z[pos], nu[pos]
+    with np.errstate(under="ignore"):
+        out[pos] = np.exp((1.0 - nup) * np.log(2.0) - gammaln(nup) + nup * np.log(zp)) * kv(nup, zp)
+    return out
+
+
 def poly_test(x, y, theta):
     """Test-only polynomial kernel theta^2 |x - y|^2 + theta, theta = (t,).
 
@@ -73,6 +94,7 @@ KERNELS = {
     "matern32": (matern32, 1),
     "matern12": (matern12, 1),
     "aniso_gaussian": (aniso_gaussian, None),  # d_theta = d
+    "matern": (matern, 2),
     "poly_test": (poly_test, 1),
     "poly2_test": (poly2_test, 2),
     "theta_free_test": (theta_free_test, 1),

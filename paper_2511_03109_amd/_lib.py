@@ -8,7 +8,7 @@ LIB_PATH = os.path.join(_HERE, "libph.so")
 
 PH_OK, PH_EINVAL, PH_EDOMAIN, PH_ENOMEM, PH_EHIP, PH_ESTATE, PH_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 KERNELS = {"gaussian": 0, "matern32": 1, "matern12": 2, "aniso_gaussian": 3, "poly_test": 4,
-           "poly2_test": 5}
+           "poly2_test": 5, "matern": 6}
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2}
 NEAR_MODES = {"auto": 0, "blocks": 1, "factored": 2}
 
@@ -72,6 +72,7 @@ SIGNATURES = {
     "ph_tree_blocks": ([_P, _I32P, _I32P, _I32P], C.c_int),
     "ph_tree_classes": ([_P, _I32P, _I32P], C.c_int),
     "ph_tree_free": ([_P], None),
+    "ph_kernel_eval": ([C.c_int, C.c_int, _DP, _DP, C.c_int64, _DP, _DP], C.c_int),
     "ph_offline_compress": ([_P, C.POINTER(OfflineOpts), _P, C.POINTER(_P)], C.c_int),
     "ph_model_info_get": ([_P, C.POINTER(ModelInfo)], C.c_int),
     "ph_model_near_ranks": ([_P, _I32P], C.c_int),

@@ -286,6 +286,20 @@ class Graph:
             L._lib.ph_graph_free(h)
 
 
+def kernel_eval(kernel, x, y, theta):
+    """kappa(x_i, y_i; theta) for the rows of x and y (ph_kernel_eval, host arrays): x, y of
+    shape (n, d), theta the kernel's d_theta parameters.  Returns a float64 array of n values."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    th = np.ascontiguousarray(np.atleast_1d(theta), dtype=np.float64)
+    if x.ndim != 2 or x.shape != y.shape:
+        raise ValueError("x and y must have the same shape (n, d)")
+    out = np.empty(x.shape[0])
+    L.check(L.lib().ph_kernel_eval(L.KERNELS[kernel], x.shape[1], _dptr(x), _dptr(y), x.shape[0], _dptr(th),
+                                   _dptr(out)), "ph_kernel_eval")
+    return out
+
+
 def cg_solve(inst64, y, *, nugget, tol=1e-6, lo=None, max_iter=100000, inner_max=1000, inner_tol=1e-4,
              stream=None):
     """Solve (K~ + nugget I) a = y (ph_cg_solve).  inst64: FP64 instance with T = 1; y: device

@@ -344,6 +344,7 @@ int kernel_dtheta(ph_kernel k, int d) {
     case PH_KERNEL_ANISO_GAUSSIAN:
       return d;
     case PH_KERNEL_POLY2_TEST:
+    case PH_KERNEL_MATERN:
       return 2;
   }
   return -1;
@@ -370,6 +371,8 @@ double kernel_value(ph_kernel k, int d, const double* x, const double* y, const 
       return th[0] * th[0] * r2 + th[0];
     case PH_KERNEL_POLY2_TEST:
       return th[0] * r2 + th[1] * th[1];
+    case PH_KERNEL_MATERN:
+      return matern_value(std::sqrt(r2), th[0], th[1]);
   }
   return 0.0;
 }
@@ -386,6 +389,8 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
   if (o.d_theta != dth) fail(PH_EUNSUPPORTED, "ph_offline_compress: d_theta does not match the kernel");
   for (int k = 0; k < dth; ++k)
     if (!(o.theta_lo[k] < o.theta_hi[k])) fail(PH_EINVAL, "ph_offline_compress: need theta_lo < theta_hi");
+  if (o.kernel == PH_KERNEL_MATERN && !(o.theta_lo[0] > 0 && o.theta_lo[1] > 0))
+    fail(PH_EINVAL, "ph_offline_compress: the Matern kernel needs lambda > 0 and nu > 0 on all of Theta");
   int P = 1;
   for (int k = 0; k < d; ++k) P *= o.p_s;
   if (P > 128) fail(PH_EUNSUPPORTED, "ph_offline_compress: p_s^d must be <= 128");

@@ -659,6 +659,22 @@ int ph_tree_classes(const ph_tree* t, int32_t* level, int32_t* offset) {
 
 void ph_tree_free(ph_tree* t) { delete t; }
 
+int ph_kernel_eval(ph_kernel kernel, int d, const double* x, const double* y, int64_t n, const double* theta,
+                   double* out) {
+  return guarded([&] {
+    need(x && y && theta && out && n >= 0 && d >= 1 && d <= 3, "NULL argument, n < 0 or d outside 1..3");
+    const int dth = ph::kernel_dtheta(kernel, d);
+    if (dth < 0 || (kernel == PH_KERNEL_ANISO_GAUSSIAN && d > 2))
+      ph::fail(PH_EUNSUPPORTED, "ph_kernel_eval: unknown kernel or unsupported kernel / d combination");
+    const bool scale = kernel == PH_KERNEL_GAUSSIAN || kernel == PH_KERNEL_MATERN32 || kernel == PH_KERNEL_MATERN12 ||
+                       kernel == PH_KERNEL_ANISO_GAUSSIAN || kernel == PH_KERNEL_MATERN;
+    if (scale)
+      for (int k = 0; k < dth; ++k)
+        if (!(theta[k] > 0)) ph::fail(PH_EDOMAIN, "ph_kernel_eval: length scales and nu must be positive");
+    for (int64_t i = 0; i < n; ++i) out[i] = ph::kernel_value(kernel, d, x + i * d, y + i * d, theta);
+  });
+}
+
 int ph_offline_compress(const ph_tree* t, const ph_offline_opts* opts, void* stream, ph_model** out) {
   return guarded([&] {
     need(t && t->p && opts && out, "NULL argument");

@@ -100,5 +100,9 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
 // kernel value kappa(x, y; theta) on the host
 double kernel_value(ph_kernel k, int d, const double* x, const double* y, const double* th);
 int kernel_dtheta(ph_kernel k, int d);
+// e^x K_nu(x) (modified Bessel function of the second kind, nu >= 0, x > 0) and the Matern
+// kernel 2^(1 - nu) / Gamma(nu) z^nu K_nu(z), z = sqrt(2 nu) r / lambda (special.cpp)
+double bessel_k_scaled(double nu, double x);
+double matern_value(double r, double lambda, double nu);
 
 }  // namespace ph

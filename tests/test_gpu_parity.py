@@ -257,6 +257,20 @@ def test_two_parameter_mixture():
     _mvm_case(X, "aniso_gaussian", [0.05, 0.05], [0.5, 0.5], 5, 7, 1e-8, 4, (2, 1), [0.21, 0.09], R=4)
 
 
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_matern_free_nu(case):
+    """Matern kernel with free smoothness, theta = (lambda, nu), on the paper's parameter space
+    [0.25, 1] x [0.5, 3] (2-D, 6 x 6 nodes, 7 x 7 parameter grid) and its larger range
+    [0.1, 1] x [0.5, 3] (3-D, 4^3 nodes): ranks, near blocks, couplings and the MVM against the
+    oracle (whose K_nu is scipy's; the library evaluates its own)."""
+    if case == "2d":
+        X = inputs.points_for(1, 2500)
+        _mvm_case(X, "matern", [0.25, 0.5], [1.0, 3.0], 6, 7, 1e-8, 3, (2, 1), [0.41, 1.83], R=4)
+    else:
+        X = inputs.points_for(2, 1200)
+        _mvm_case(X, "matern", [0.1, 0.5], [1.0, 3.0], 4, 7, 1e-8, 2, (3, 1), [0.17, 0.71], R=3)
+
+
 def test_multi_theta_slots_and_alpha_beta():
     torch = _torch()
     from paper_2511_03109_amd import api

@@ -134,7 +134,7 @@ def test_entry_points_reject_null_handles():
 @pytest.mark.parametrize("bad,code", [("p_s", _lib.PH_EINVAL), ("p_theta", _lib.PH_EINVAL),
                                       ("tol", _lib.PH_EINVAL), ("box", _lib.PH_EINVAL),
                                       ("d_theta", _lib.PH_EUNSUPPORTED), ("P", _lib.PH_EUNSUPPORTED),
-                                      ("aniso3d", _lib.PH_EUNSUPPORTED)])
+                                      ("aniso3d", _lib.PH_EUNSUPPORTED), ("matern_nu0", _lib.PH_EINVAL)])
 def test_offline_rejects_bad_options(bad, code):
     """The offline stage validates its options on the host before any work or upload."""
     d = 3 if bad in ("P", "aniso3d") else 2
@@ -153,6 +153,8 @@ def test_offline_rejects_bad_options(bad, code):
         lo, hi = [0.1, 0.1], [0.5, 0.5]
     elif bad == "P":
         kw["p_s"] = 6                     # 6^3 = 216 > 128
+    elif bad == "matern_nu0":
+        kernel, lo, hi = "matern", [0.1, 0.0], [0.5, 2.0]   # nu must stay positive on Theta
     else:
         kernel, lo, hi = "aniso_gaussian", [0.1] * 2, [0.5] * 2
     import ctypes as C
@@ -167,6 +169,53 @@ def test_offline_rejects_bad_options(bad, code):
     # NULL stream: the call must fail in the option checks, before anything is uploaded
     assert lib.ph_offline_compress(t._h, C.byref(opts), None, C.byref(out)) == code
     assert lib.ph_last_error() and not out.value
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_kernel_eval_matches_oracle(d):
+    """ph_kernel_eval (the library's host kernel values, the ones its offline stage uses)
+    against the oracle's kernels.  Closed forms: 8 ulp of 1 (same formulas, different
+    rounding order).  Matern with free nu (Bessel K_nu of the library's own routine against
+    scipy's): relative 1e-12 over nu in [0.5, 3] and z = sqrt(2 nu) r / lambda from 0 to 40
+    (scipy's K_nu is itself accurate to about 1e-13 there); the value 1 at r = 0."""
+    from oracle import kernels
+    g = np.random.default_rng(40 + d)
+    X = g.random((400, d))
+    Y = np.concatenate([g.random((399, d)), X[-1:]])     # the last pair at r = 0
+    atol = 8 * np.finfo(float).eps
+    for name, th in (("gaussian", [0.21]), ("matern32", [0.13]), ("matern12", [0.4])):
+        np.testing.assert_allclose(api.kernel_eval(name, X, Y, th), kernels.KERNELS[name][0](X, Y, np.array(th)),
+                                   rtol=0, atol=atol)
+    if d <= 2:
+        th = np.array([0.2, 0.35][:d])
+        np.testing.assert_allclose(api.kernel_eval("aniso_gaussian", X, Y, th), kernels.aniso_gaussian(X, Y, th),
+                                   rtol=0, atol=atol)
+    for lam, nu in ((0.1, 0.5), (0.25, 0.77), (0.3, 1.0), (0.5, 1.5), (0.7, 2.03), (1.0, 2.5), (0.4, 3.0)):
+        got = api.kernel_eval("matern", X, Y, [lam, nu])
+        ref = kernels.matern(X, Y, np.array([lam, nu]))
+        assert got[-1] == 1.0 and ref[-1] == 1.0
+        big = ref > 1e-300
+        assert np.max(np.abs(got[big] / ref[big] - 1)) <= 1e-12, (lam, nu)
+        assert np.all(np.abs(got[~big]) <= 1e-290)
+
+
+def test_kernel_eval_rejects_bad_input():
+    import ctypes as C
+    lib = _lib.lib()
+    x = np.zeros((2, 2))
+    out = np.zeros(2)
+    dp = C.POINTER(C.c_double)
+    th = np.array([0.5, 1.5])
+    call = lambda k, d, thv, n=2: lib.ph_kernel_eval(k, d, x.ctypes.data_as(dp), x.ctypes.data_as(dp), n,
+                                                     thv.ctypes.data_as(dp), out.ctypes.data_as(dp))
+    assert call(_lib.KERNELS["matern"], 2, th) == _lib.PH_OK
+    assert lib.ph_kernel_eval(6, 2, None, None, 2, None, None) == _lib.PH_EINVAL
+    assert call(_lib.KERNELS["matern"], 4, th) == _lib.PH_EINVAL
+    assert call(_lib.KERNELS["matern"], 2, th, n=-1) == _lib.PH_EINVAL
+    assert call(99, 2, th) == _lib.PH_EUNSUPPORTED
+    assert call(_lib.KERNELS["matern"], 2, np.array([0.5, 0.0])) == _lib.PH_EDOMAIN
+    assert call(_lib.KERNELS["gaussian"], 2, np.array([-0.5])) == _lib.PH_EDOMAIN
+    assert lib.ph_last_error()
 
 
 def test_counter_records_key_on_each_kernel_definition():

@@ -91,6 +91,48 @@ def test_workload_kernels_match_sklearn(l):
                                rtol=0, atol=atol)
 
 
+def test_matern_free_nu_half_integer_closed_forms():
+    """The Matern kernel with free nu at the half-integer orders, where K_nu is elementary:
+    nu = 1/2 gives exp(-r / lambda), nu = 3/2 gives (1 + s) exp(-s) with s = sqrt3 r / lambda,
+    nu = 5/2 gives (1 + s + s^2 / 3) exp(-s) with s = sqrt5 r / lambda (textbook forms).  These
+    fix the prefactor 2^(1 - nu) / Gamma(nu), the argument sqrt(2 nu) r / lambda and the value 1
+    at r = 0; a wrong one moves the value by 1e-2 or more.  Bound: 1e-14 absolute."""
+    g = np.random.default_rng(5)
+    X = g.random((30, 2))
+    Y = np.concatenate([g.random((29, 2)), X[:1]])
+    r = np.sqrt(((X[:, None, :] - Y[None, :, :]) ** 2).sum(-1))
+    for lam in (0.1, 0.25, 0.6, 1.0):
+        k = lambda nu: kernels.matern(X[:, None, :], Y[None, :, :], np.array([lam, nu]))
+        s1, s3, s5 = r / lam, np.sqrt(3) * r / lam, np.sqrt(5) * r / lam
+        np.testing.assert_allclose(k(0.5), np.exp(-s1), rtol=0, atol=1e-14)
+        np.testing.assert_allclose(k(1.5), (1 + s3) * np.exp(-s3), rtol=0, atol=1e-14)
+        np.testing.assert_allclose(k(2.5), (1 + s5 + s5 * s5 / 3) * np.exp(-s5), rtol=0, atol=1e-14)
+        assert k(1.7)[0, -1] == 1.0
+
+
+@pytest.mark.parametrize("nu", [0.6, 1.0, 1.3, 2.0, 2.7, 3.0])
+def test_matern_free_nu_matches_bessel_integral(nu):
+    """Other orders against the integral K_nu(z) = int_0^inf exp(-z cosh t) cosh(nu t) dt,
+    evaluated by adaptive quadrature (independent of the Bessel routine the oracle calls):
+    relative 1e-11 (quadrature to 1e-13 and the Bessel routine's own accuracy).  Also the
+    monotone decay in r and the limit 1 as r -> 0."""
+    from math import cosh, exp, lgamma, log, sqrt
+    from scipy.integrate import quad
+    lam = 0.45
+    for r in (1e-6, 0.01, 0.1, 0.3, 0.7, 1.4, 3.0):
+        z = sqrt(2 * nu) * r / lam
+        tmax = 1.0
+        while z * (cosh(tmax) - 1) - nu * tmax < 60:
+            tmax *= 1.5
+        kz, _ = quad(lambda t: exp(-z * (cosh(t) - 1)) * cosh(nu * t), 0, tmax, epsabs=0, epsrel=1e-13, limit=1000)
+        ref = exp((1 - nu) * log(2) - lgamma(nu) + nu * log(z) - z) * kz
+        got = kernels.matern(np.zeros(1), np.array([r]), np.array([lam, nu]))
+        assert abs(got / ref - 1) <= 1e-11, (nu, r, got, ref)
+    rr = np.linspace(0, 2, 41)[:, None]
+    v = kernels.matern(np.zeros((41, 1)), rr, np.array([lam, nu]))
+    assert v[0] == 1.0 and np.all(np.diff(v) < 0) and abs(v[1] - 1) < 0.2
+
+
 # ---------------------------------------------------------------- cluster tree
 def _pts(n, d, seed=0):
     return np.random.default_rng(seed).random((n, d))
