@@ -365,7 +365,44 @@ def mode_sweep(args):
                       "ms_per_theta_eager_tuned": ms_eager / T, "model": model.info}))
 
 
-MODES = {"precision": mode_precision, "cg": mode_cg, "grad": mode_grad, "sweep": mode_sweep}
+def mode_matern(args):
+    """Matern kernel with free smoothness, theta = (lambda, nu) on [0.1, 1] x [0.5, 3], n = 8^4 in
+    [0,1]^3 (the paper's larger-parameter-range setting): offline time, then 8 (lambda, nu)
+    instantiated and applied to 16 RHS each, timed like the headline, with per-stage times."""
+    import torch
+    from paper_2511_03109_amd import _lib, api, inputs
+    t0 = time.time()
+    w, X, tree, model = _model(6)
+    offline_s = time.time() - t0
+    n, T, R = w["n"], w["T"], w["R"]
+    thetas = inputs.theta_samples(T, w["theta_lo"], w["theta_hi"], 6)
+    x = torch.tensor(np.ascontiguousarray(inputs.normal_vectors(n, T * R, 6).T.reshape(T, R, n)), device="cuda")
+    y = torch.empty_like(x)
+    inst = api.Instance(model, thetas)
+    ms = _timed(lambda: (inst.reinstantiate(thetas), inst.matvec(x, y)), args.steps, args.warmup)
+    lib = _lib.lib()
+    stats = _lib.TraceStats()
+    lib.ph_trace_read(stats, 1)
+    lib.ph_trace_enable(1)
+    for _ in range(5):
+        inst.reinstantiate(thetas)
+        inst.matvec(x, y)
+    torch.cuda.synchronize()
+    lib.ph_trace_enable(0)
+    _lib.check(lib.ph_trace_read(stats, 1), "ph_trace_read")
+    stages = {nm: stats.ms[i] / 5 for i, nm in enumerate(_lib.STAGES) if stats.count[i]}
+    print(json.dumps({"metric": "ms per (lambda, nu)-instantiate + H-MVM, Matern with free nu",
+                      "value": ms / T, "unit": "ms per theta (16 RHS)", "higher_is_better": False,
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+                      "config": {"workload": w["name"], "n": n, "theta_box": [w["theta_lo"], w["theta_hi"]],
+                                 "p_s": w["p_s"], "p_theta": w["p_theta"], "T": T, "R": R,
+                                 "near_field": "factored" if inst.factored else "blocks"},
+                      "data": "synthetic", "offline_s": offline_s, "stage_ms_per_step": stages,
+                      "model": model.info}))
+
+
+MODES = {"precision": mode_precision, "cg": mode_cg, "grad": mode_grad, "sweep": mode_sweep,
+         "matern": mode_matern}
 
 
 def main():
@@ -377,7 +414,7 @@ def main():
     ap.add_argument("--cpu-sample-leaves", type=int, default=160)
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the comparison legs (per-theta FP64, near blocks in memory, FP32, BF16)")
-    ap.add_argument("--mode", default="step", choices=["step", "precision", "cg", "grad", "sweep"],
+    ap.add_argument("--mode", default="step", choices=["step", "precision", "cg", "grad", "sweep", "matern"],
                     help="step (default): the benchmark step; precision: FP64 / FP32 / BF16 instances of "
                          "the same step; cg: (K + 1e-2 I) a = y at n = 262144 by FP64 CG and by FP64 "
                          "refinement around FP32 / BF16; grad: forward + backward of y = K(l) x at "

@@ -82,6 +82,9 @@ WORKLOADS = {
     5: dict(name="matern12_2d_n262144_cg", n=262144, d=2, points="uniform", kernel="matern12",
             theta_lo=[0.05], theta_hi=[0.5], p_s=6, p_theta=9, leaf=64, eta2=(2, 1),
             tol=1e-8, theta=[0.1], nugget=1e-2, R=1),
+    6: dict(name="matern_nu_3d_n4096", n=4096, d=3, points="uniform", kernel="matern",
+            theta_lo=[0.1, 0.5], theta_hi=[1.0, 3.0], p_s=5, p_theta=7, leaf=64, eta2=(3, 1),
+            tol=1e-8, T=8, R=16),
 }
 
 
