@@ -21,6 +21,9 @@ Paper passages followed:
   ``dedup=False`` compresses every far block separately, as the algorithm is
   written.
 * Sec. 6 "Error Calculation": sampled-row relative error against the exact kernel.
+* Def. "Parametric H-matrix", App. PTTK offline phase 3 and Alg. "H-matrix MVM" with the
+  parametric far-field substitution: the H-matrix variant (``h_far_factors``,
+  ``instantiate_h``, ``matvec_h``), sharing the near field and the far tensors.
 
 Compression is the truncated HOSVD of ``oracle.tucker`` (see there for the reading
 of the tolerance).  The nugget of a regularised system is not part of kappa; it
@@ -190,6 +193,62 @@ class PH2:
         D = {bi: self.near_block(bi, vs) for bi in near_blocks}
         C = {k: self.coupling(k, vs) for k in far_keys}
         return {"D": D, "C": C}
+
+    # ---------------------------------------------------------------- parametric H-matrix
+    def h_far_factors(self, bi):
+        """Far block b = (s, t) in the parametric H-matrix format (Def. "Parametric H-matrix";
+        App. PTTK, offline phase 3): S_b = U_s L_b and T_b = U_t R_b, with U_s and U_t the
+        Chebyshev bases of the block's own clusters evaluated at their points (not through
+        transfer matrices) and L_b, R_b the outer factors of the block's compressed far tensor."""
+        if not hasattr(self, "_hST"):
+            self._hST = {}
+        if bi not in self._hST:
+            s, u = self.far[bi]
+            core, facs = self.far_factors(self.far_key(bi))
+            self._hST[bi] = (self._tree_order_basis(s) @ facs[0], self._tree_order_basis(u) @ facs[-1])
+        return self._hST[bi]
+
+    def _tree_order_basis(self, s):
+        """U_s evaluated at the points of cluster s in tree order (rows begin_s .. end_s - 1 of the
+        permuted vector; for an inner cluster the concatenation of its children's ranges)."""
+        t = self.tree
+        return cheb.tensor_lagrange(t.lo[s], t.hi[s], self.p_s, self.X[t.perm[t.begin[s]:t.end[s]]])
+
+    def h_core(self, key, vs):
+        """H_b(theta): the far core contracted with Θ_i^T v_i(theta_i) (Alg. PTTK online)."""
+        core, facs = self.far_factors(key)
+        H = core
+        for i in range(self.d_theta):
+            H = np.tensordot(H, facs[1 + i].T @ vs[i], axes=([1], [0]))
+        return H
+
+    def instantiate_h(self, theta, deriv_dim=None):
+        """Alg. "Online Stage" for the parametric H-matrix: D_b for near blocks, H_b for far keys."""
+        vs = self.theta_vectors(theta, deriv_dim)
+        keys = range(len(self.classes)) if self.dedup else range(len(self.far))
+        return {"D": {bi: self.near_block(bi, vs) for bi in range(len(self.near))},
+                "H": {k: self.h_core(k, vs) for k in keys}}
+
+    def matvec_h(self, inst, x, nugget=0.0):
+        """Alg. "H-matrix MVM" with the parametric far field (Sec. "MVM", parametric H-matrices):
+        y_s += S_b (H_b(theta) (T_b^T x_t)) for every far block, y_s += D_b x_t for every near
+        block; y = (K~(theta) + nugget I) x, x of shape (n, R) in original order."""
+        t = self.tree
+        x = np.asarray(x, dtype=np.float64)
+        squeeze = x.ndim == 1
+        if squeeze:
+            x = x[:, None]
+        xt = x[t.perm]
+        yt = np.zeros_like(xt)
+        for bi, (s, u) in enumerate(self.far):
+            S, T = self.h_far_factors(bi)
+            yt[t.begin[s]:t.end[s]] += S @ (inst["H"][self.far_key(bi)] @ (T.T @ xt[t.begin[u]:t.end[u]]))
+        for bi, (s, u) in enumerate(self.near):
+            yt[t.begin[s]:t.end[s]] += inst["D"][bi] @ xt[t.begin[u]:t.end[u]]
+        y = np.empty_like(x)
+        y[t.perm] = yt
+        y += nugget * x
+        return y[:, 0] if squeeze else y
 
     # ---------------------------------------------------------------- MVM
     def _upward(self, xt):

@@ -386,6 +386,33 @@ def test_polynomial_kernel_reproduced_exactly(tol):
             assert np.max(np.abs(y - ref)) <= 1e-11 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("tol", [0.0, 1e-9])
+def test_h_matrix_variant_reproduces_polynomial_kernel(tol):
+    """The parametric H-matrix variant (S_b H_b T_b^T per far block, Alg. "H-matrix MVM") on a
+    kernel of degree 2 in x, y and theta: interpolation is exact, so its MVM equals the dense
+    K(theta) x (a dropped factor, a transposed S_b / T_b or a wrong core contraction fails)."""
+    for d, l, eta2 in ((2, 3, 2), (3, 2, 3)):
+        m = _model("poly_test", n=700, d=d, l=l, eta2=eta2, p_s=3, p_theta=3, tol=tol)
+        x = np.random.default_rng(4).standard_normal((700, 2))
+        for th in (0.12, 0.44):
+            ref = m.exact_dense(th) @ x
+            y = m.matvec_h(m.instantiate_h(th), x, nugget=0.3)
+            assert np.max(np.abs(y - ref - 0.3 * x)) <= 1e-11 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("kernel,lo,hi,th", [("matern32", (0.05,), (0.5,), [0.21]),
+                                             ("matern", (0.25, 0.5), (1.0, 3.0), [0.4, 1.7])])
+def test_h_matrix_variant_equals_h2_through_nestedness(kernel, lo, hi, th):
+    """S_b H_b T_b^T = U_s C_b U_t^T with U_s evaluated directly on each cluster, while the H^2
+    MVM reaches inner clusters through transfer matrices; the two agree because the Chebyshev
+    bases are nested exactly (lemma of App. "Transfer Matrices").  Bound: 1e-13 of the result."""
+    m = _model(kernel, n=900, d=2, l=3, eta2=2, p_s=5, p_theta=5, lo=lo, hi=hi)
+    x = np.random.default_rng(6).standard_normal((900, 3))
+    y2 = m.matvec(m.instantiate(np.array(th)), x)
+    yh = m.matvec_h(m.instantiate_h(np.array(th)), x)
+    assert np.max(np.abs(yh - y2)) <= 1e-13 * np.max(np.abs(y2))
+
+
 def test_polynomial_kernel_two_parameters():
     X = _pts(500, 2, 12)
     m = hmat.PH2(X, l_max=3, eta2=2, kernel=kernels.poly2_test, theta_lo=[0.1, 0.2],
