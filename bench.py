@@ -401,8 +401,56 @@ def mode_matern(args):
                       "model": model.info}))
 
 
+def mode_hmatrix(args):
+    """The parametric H-matrix format against the H^2 format on the same workload (E kernel,
+    lambda in [0.25, 1], n = 8^5 in [0,1]^3, the paper's parameter space): offline time of each,
+    then 8 lambda instantiated and applied to 16 RHS each, timed like the headline, with
+    per-stage times; relative difference of the two outputs."""
+    import torch
+    from paper_2511_03109_amd import _lib, api, inputs
+    w = inputs.WORKLOADS[7]
+    n, T, R = w["n"], w["T"], w["R"]
+    X = inputs.points_for(7)
+    tree = api.Tree(X, leaf_size=w["leaf"], l_max=-1, eta2=tuple(w["eta2"]))
+    thetas = inputs.theta_samples(T, w["theta_lo"], w["theta_hi"], 7)
+    x = torch.tensor(np.ascontiguousarray(inputs.normal_vectors(n, T * R, 7).T.reshape(T, R, n)), device="cuda")
+    lib = _lib.lib()
+    res, ys = {}, {}
+    for fmt in ("h", "h2"):
+        t0 = time.time()
+        model = api.Model(tree, w["kernel"], w["theta_lo"], w["theta_hi"], p_s=w["p_s"], p_theta=w["p_theta"],
+                          tol=w["tol"], format=fmt)
+        torch.cuda.synchronize()
+        offline_s = time.time() - t0
+        y = torch.empty_like(x)
+        inst = api.Instance(model, thetas)
+        ms = _timed(lambda: (inst.reinstantiate(thetas), inst.matvec(x, y)), args.steps, args.warmup)
+        stats = _lib.TraceStats()
+        lib.ph_trace_read(stats, 1)
+        lib.ph_trace_enable(1)
+        for _ in range(3):
+            inst.reinstantiate(thetas)
+            inst.matvec(x, y)
+        torch.cuda.synchronize()
+        lib.ph_trace_enable(0)
+        _lib.check(lib.ph_trace_read(stats, 1), "ph_trace_read")
+        res[fmt] = {"ms_per_theta": ms / T, "offline_s": offline_s,
+                    "stage_ms_per_step": {nm: stats.ms[i] / 3 for i, nm in enumerate(_lib.STAGES) if stats.count[i]},
+                    "device_bytes": model.info["device_bytes"]}
+        ys[fmt] = y.clone()
+        del inst, model
+        torch.cuda.empty_cache()
+    diff = float(torch.linalg.vector_norm(ys["h"] - ys["h2"]) / torch.linalg.vector_norm(ys["h2"]))
+    print(json.dumps({"metric": "ms per lambda-instantiate + MVM, parametric H-matrix vs H^2 format",
+                      "value": res["h"]["ms_per_theta"], "unit": "ms per theta (16 RHS)", "higher_is_better": False,
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "config": {"workload": w["name"], "n": n, "T": T, "R": R, "p_s": w["p_s"],
+                                 "p_theta": w["p_theta"], "theta_box": [w["theta_lo"], w["theta_hi"]]},
+                      "data": "synthetic", "results": res, "rel_diff_h_vs_h2": diff}))
+
+
 MODES = {"precision": mode_precision, "cg": mode_cg, "grad": mode_grad, "sweep": mode_sweep,
-         "matern": mode_matern}
+         "matern": mode_matern, "hmatrix": mode_hmatrix}
 
 
 def main():
@@ -414,7 +462,7 @@ def main():
     ap.add_argument("--cpu-sample-leaves", type=int, default=160)
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the comparison legs (per-theta FP64, near blocks in memory, FP32, BF16)")
-    ap.add_argument("--mode", default="step", choices=["step", "precision", "cg", "grad", "sweep", "matern"],
+    ap.add_argument("--mode", default="step", choices=["step", "precision", "cg", "grad", "sweep", "matern", "hmatrix"],
                     help="step (default): the benchmark step; precision: FP64 / FP32 / BF16 instances of "
                          "the same step; cg: (K + 1e-2 I) a = y at n = 262144 by FP64 CG and by FP64 "
                          "refinement around FP32 / BF16; grad: forward + backward of y = K(l) x at "

@@ -80,6 +80,14 @@ typedef enum {
 int ph_kernel_eval(ph_kernel kernel, int d, const double* x, const double* y, int64_t n, const double* theta,
                    double* out);
 
+/* Hierarchical format of a model (Sec. "Parametric H-matrices and H²-matrices").
+ *   PH_FORMAT_H2  parametric H²-matrix: nested cluster bases, one coupling matrix
+ *                 C_b(theta) = L H(theta) R^T per far block (Def. "Parametric H²-matrix")
+ *   PH_FORMAT_H   parametric H-matrix: explicit factors S_b = U_s L_b, T_b = U_t R_b per far
+ *                 block and the far core H_b(theta) (Def. "Parametric H-matrix"; App. PTTK
+ *                 offline phase 3); MVM by Alg. "H-matrix MVM" with the parametric far field */
+typedef enum { PH_FORMAT_H2 = 0, PH_FORMAT_H = 1 } ph_format;
+
 /* Arithmetic of an instance.  PH_F64: FP64 storage and arithmetic, I/O in double.
  * PH_F32: FP32 storage of the instantiated blocks, FP32 arithmetic (matrix cores with
  * FP32 accumulation), I/O in float.  PH_BF16: as PH_F32, but the near-field blocks D_b
@@ -198,6 +206,18 @@ typedef struct {
  * freed right after this call. */
 int ph_offline_compress(const ph_tree* t, const ph_offline_opts* opts, void* stream,
                         ph_model** out);
+
+/* Offline stage of the parametric H-matrix format (Alg. "Offline Stage: Parametric H-matrix";
+ * App. PTTK offline, phases 1-3): the same near field and far tensors as ph_offline_compress,
+ * then S_b = U_s L_b and T_b = U_t R_b for every far block (U_s evaluated on the block's own
+ * clusters; (L_b, R_b) swapped for blocks whose class is the mirror of a stored one).  The model
+ * supports PH_F64 instances only (PH_EUNSUPPORTED for other dtypes); ph_instantiate forms
+ * H_q(theta) per stored class, ph_matvec applies S_b H_b T_b^T per far block.  Errors as
+ * ph_offline_compress.  *out is owned by the caller (ph_model_free). */
+int ph_offline_compress_h(const ph_tree* t, const ph_offline_opts* opts, void* stream, ph_model** out);
+
+/* The hierarchical format of a model (ph_format). */
+int ph_model_format(const ph_model* m, int* format);
 
 int ph_model_info_get(const ph_model* m, ph_model_info* info);
 
@@ -366,7 +386,8 @@ void ph_graph_free(ph_graph* g);
 /* Inspection (tests): copy the instantiated near block of canonical near index b for
  * slot t (n_s x n_t column-major, as double; for a factored instance the block is formed
  * by a kernel in the arithmetic of the MVM) or the coupling matrix of class c (P x P
- * column-major, as double) to host memory.  Synchronises the device. */
+ * column-major, as double) to host memory.  Synchronises the device.  A parametric H-matrix
+ * instance forms no coupling matrices: ph_inst_coupling returns PH_EUNSUPPORTED for it. */
 int ph_inst_near_block(const ph_inst* k, int t, int64_t b, double* host_out);
 int ph_inst_coupling(const ph_inst* k, int t, int64_t c, double* host_out);
 

@@ -11,6 +11,7 @@ KERNELS = {"gaussian": 0, "matern32": 1, "matern12": 2, "aniso_gaussian": 3, "po
            "poly2_test": 5, "matern": 6}
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2}
 NEAR_MODES = {"auto": 0, "blocks": 1, "factored": 2}
+FORMATS = {"h2": 0, "h": 1}
 
 
 class TreeOpts(C.Structure):
@@ -74,6 +75,8 @@ SIGNATURES = {
     "ph_tree_free": ([_P], None),
     "ph_kernel_eval": ([C.c_int, C.c_int, _DP, _DP, C.c_int64, _DP, _DP], C.c_int),
     "ph_offline_compress": ([_P, C.POINTER(OfflineOpts), _P, C.POINTER(_P)], C.c_int),
+    "ph_offline_compress_h": ([_P, C.POINTER(OfflineOpts), _P, C.POINTER(_P)], C.c_int),
+    "ph_model_format": ([_P, C.POINTER(C.c_int)], C.c_int),
     "ph_model_info_get": ([_P, C.POINTER(ModelInfo)], C.c_int),
     "ph_model_near_ranks": ([_P, _I32P], C.c_int),
     "ph_model_class_ranks": ([_P, _I32P], C.c_int),

@@ -82,10 +82,11 @@ class Tree:
 
 
 class Model:
-    """Offline stage output on the device (ph_offline_compress)."""
+    """Offline stage output on the device: ph_offline_compress (format "h2", the parametric
+    H^2-matrix) or ph_offline_compress_h (format "h", the parametric H-matrix)."""
 
     def __init__(self, tree, kernel, theta_lo, theta_hi, *, p_s, p_theta, tol, num_threads=0,
-                 stream=None):
+                 stream=None, format="h2"):
         lo = np.atleast_1d(np.asarray(theta_lo, dtype=np.float64))
         hi = np.atleast_1d(np.asarray(theta_hi, dtype=np.float64))
         opts = L.OfflineOpts()
@@ -96,9 +97,12 @@ class Model:
             opts.theta_hi[k] = hi[k]
         opts.p_s, opts.p_theta, opts.tol, opts.num_threads = p_s, p_theta, tol, num_threads
         h = C.c_void_p()
-        L.check(L.lib().ph_offline_compress(tree._h, C.byref(opts), _stream(stream), C.byref(h)),
-                "ph_offline_compress")
+        entry = {"h2": "ph_offline_compress", "h": "ph_offline_compress_h"}[format]
+        L.check(getattr(L.lib(), entry)(tree._h, C.byref(opts), _stream(stream), C.byref(h)), entry)
         self._h = h
+        fmt = C.c_int()
+        L.check(L.lib().ph_model_format(h, C.byref(fmt)), "ph_model_format")
+        self.format = {v: k for k, v in L.FORMATS.items()}[fmt.value]
         self.tree = tree
         info = L.ModelInfo()
         L.check(L.lib().ph_model_info_get(h, C.byref(info)), "ph_model_info_get")

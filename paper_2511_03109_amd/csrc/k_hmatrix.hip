@@ -1,0 +1,185 @@
+// Parametric H-matrix format (Def. "Parametric H-matrix"): the online stage forms the far cores
+// H_q(theta) (Alg. PTTK online) and the MVM applies every far block as S_b (H_b (T_b^T x_t))
+// (Alg. "H-matrix MVM" with the parametric substitution of Sec. "MVM").  The near field is the
+// one of the H^2 format.
+#include "ph_device.hpp"
+
+namespace ph {
+
+// H_q(theta_t) = sum_{k1, k2} w_1[k1] w_2[k2] core_q[:, k1, k2, :], w_i = Theta_i^T v_i(theta_t),
+// column-major rL x rR at Hc[t h_tot + h_off].  One workgroup per (stored class, slot).
+__global__ void __launch_bounds__(NT) k_h_core(const HClsDev* __restrict__ cls, const double* __restrict__ core,
+                                               const double* __restrict__ th, const double* __restrict__ v,
+                                               double* __restrict__ Hc, int64_t h_tot, int p, int dth) {
+  __shared__ double w1[16], w2[16];
+  const HClsDev c = cls[blockIdx.x];
+  const int64_t t = blockIdx.y;
+  const double* vt = v + t * dth * p;
+  if ((int)threadIdx.x < c.r1) {
+    double s = 0;
+    for (int q = 0; q < p; ++q) s += th[c.th1_off + q + (int64_t)p * threadIdx.x] * vt[q];
+    w1[threadIdx.x] = s;
+  } else if ((int)threadIdx.x >= 32 && (int)threadIdx.x < 32 + c.r2) {
+    const int a = threadIdx.x - 32;
+    double s = 1.0;
+    if (dth == 2) {
+      s = 0;
+      for (int q = 0; q < p; ++q) s += th[c.th2_off + q + (int64_t)p * a] * vt[p + q];
+    }
+    w2[a] = s;
+  }
+  __syncthreads();
+  double* H = Hc + t * h_tot + c.h_off;
+  const int ne = c.rL * c.rR;
+  for (int e = threadIdx.x; e < ne; e += NT) {
+    const int a = e % c.rL, b = e / c.rL;
+    double s = 0;
+    for (int k2 = 0; k2 < c.r2; ++k2) {
+      double s1 = 0;
+      for (int k1 = 0; k1 < c.r1; ++k1)
+        s1 += w1[k1] * core[c.core_off + a + (int64_t)c.rL * (k1 + (int64_t)c.r1 * (k2 + (int64_t)c.r2 * b))];
+      s += w2[k2] * s1;
+    }
+    H[e] = s;
+  }
+}
+
+constexpr int HCH = 32;   // rows of T_b staged per step
+
+// w_b = H_b (T_b^T x_t) for far block b, slot, 16-column RHS tile; W[(slot nrc + tile) hw_tot
+// + w_off + a 16 + c].  Thread (g, c) = (tid / 16, tid % 16) owns ranks g, g + 16, ... and RHS
+// column c.  Rows of T_b and x_t go through LDS in chunks of HCH.
+__global__ void __launch_bounds__(NT) k_h_proj(const double* __restrict__ xt, double* __restrict__ W,
+                                               const HBlkDev* __restrict__ blks, const double* __restrict__ hT,
+                                               const double* __restrict__ Hc, int64_t h_tot, int64_t hw_tot,
+                                               int64_t n, int64_t Rs, int nrc) {
+  __shared__ double Ts[HCH][129];
+  __shared__ double xs[HCH][16];
+  __shared__ double zs[128][17];
+  const HBlkDev b = blks[blockIdx.x];
+  const int tile = blockIdx.y;
+  const int64_t slot = blockIdx.z;
+  const int r0 = tile * RC;
+  const int rc = (int)min<int64_t>(RC, Rs - r0);
+  const int c = threadIdx.x % 16, g = threadIdx.x / 16;
+  const double* x = xt + (slot * n + b.t_begin) * Rs + r0;
+  const double* T = hT + b.T_off;
+  double acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] = 0;
+  for (int64_t i0 = 0; i0 < b.nt; i0 += HCH) {
+    const int cn = (int)min<int64_t>(HCH, b.nt - i0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < HCH * 16; e += NT) {
+      const int ii = e / 16, cc = e % 16;
+      xs[ii][cc] = (ii < cn && cc < rc) ? x[(i0 + ii) * Rs + cc] : 0.0;
+    }
+    for (int e = threadIdx.x; e < HCH * b.rt; e += NT) {
+      const int ii = e % HCH, a = e / HCH;
+      Ts[ii][a] = ii < cn ? T[i0 + ii + (int64_t)b.ldt * a] : 0.0;
+    }
+    __syncthreads();
+    for (int ii = 0; ii < cn; ++ii) {
+      const double xv = xs[ii][c];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int a = g + 16 * j;
+        if (a < b.rt) acc[j] += Ts[ii][a] * xv;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int a = g + 16 * j;
+    if (a < b.rt) zs[a][c] = acc[j];
+  }
+  __syncthreads();
+  // w[a'] = sum_a H'[a'][a] z[a]; H' = H_q (rows rs) or H_q^T for a mirrored class
+  const double* H = Hc + slot * h_tot + b.h_off;
+  double* w = W + (slot * nrc + tile) * hw_tot + b.w_off;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int ap = g + 16 * j;
+    if (ap >= b.rs) continue;
+    double s = 0;
+    for (int a = 0; a < b.rt; ++a) s += (b.tr ? H[a + (int64_t)b.rt * ap] : H[ap + (int64_t)b.rs * a]) * zs[a][c];
+    w[ap * 16 + c] = s;
+  }
+}
+
+// yt[rows] += sum over the far blocks b whose target contains the rows of S_b[rows] w_b, for one
+// (leaf, 128-row chunk) item, slot and RHS tile.  Thread (g, c) owns rows g, g + 16, ... of the
+// chunk and RHS column c; each w_b goes through LDS.
+__global__ void __launch_bounds__(NT) k_h_apply(double* __restrict__ yt, const double* __restrict__ W,
+                                                const HBlkDev* __restrict__ blks, const double* __restrict__ hS,
+                                                const int32_t* __restrict__ leaf_ptr,
+                                                const int32_t* __restrict__ leaf_blk, const int64_t* __restrict__ nbegin,
+                                                const int64_t* __restrict__ nend, const int32_t* __restrict__ items,
+                                                int32_t leaf0, int64_t hw_tot, int64_t n, int64_t Rs, int nrc) {
+  constexpr int CH = 128;
+  __shared__ double ws[128][17];
+  const int li = items[2 * blockIdx.x], cstart = items[2 * blockIdx.x + 1];
+  const int32_t leaf = leaf0 + li;
+  const int tile = blockIdx.y;
+  const int64_t slot = blockIdx.z;
+  const int r0 = tile * RC;
+  const int rc = (int)min<int64_t>(RC, Rs - r0);
+  const int c = threadIdx.x % 16, g = threadIdx.x / 16;
+  const int64_t lb = nbegin[leaf], ln = nend[leaf] - lb;
+  const int cn = (int)min<int64_t>(CH, ln - cstart);
+  double acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] = 0;
+  const double* Wt = W + (slot * nrc + tile) * hw_tot;
+  for (int e = leaf_ptr[li]; e < leaf_ptr[li + 1]; ++e) {
+    const HBlkDev b = blks[leaf_blk[e]];
+    __syncthreads();
+    for (int q = threadIdx.x; q < b.rs * 16; q += NT) ws[q / 16][q % 16] = Wt[b.w_off + q];
+    __syncthreads();
+    // rows of the chunk relative to the block's target cluster
+    const double* S = hS + b.S_off + (lb + cstart - b.s_begin);
+    for (int a = 0; a < b.rs; ++a) {
+      const double wv = ws[a][c];
+      const double* Sa = S + (int64_t)b.lds * a;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int r = g + 16 * j;
+        if (r < cn) acc[j] += Sa[r] * wv;
+      }
+    }
+  }
+  if (c >= rc) return;
+  double* y = yt + (slot * n + lb + cstart) * Rs + r0 + c;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int r = g + 16 * j;
+    if (r < cn) y[(int64_t)r * Rs] += acc[j];
+  }
+}
+
+void h_core_launch(const InstData& in, hipStream_t st) {
+  const DeviceModel& m = *in.m;
+  if (m.n_hcls == 0) return;
+  launch(PH_STAGE_FAR_INST, k_h_core, dim3((unsigned)m.n_hcls, (unsigned)in.T), dim3(NT), st,
+         (const HClsDev*)m.hcls.p, (const double*)m.hcore.p, (const double*)m.ff_theta.p, (const double*)in.v.p,
+         (double*)in.C.p, m.h_tot, m.p_theta, m.d_theta);
+}
+
+void h_far_launch(const InstData& in, const double* xt, double* yt, double* W, int64_t Rs, int64_t nrc,
+                  hipStream_t st, int phase) {
+  const DeviceModel& m = *in.m;
+  if (m.n_hblk == 0) return;
+  if (in.T > 65535 || nrc > 65535) fail(PH_EUNSUPPORTED, "ph_matvec: too many parameter slots or RHS tiles");
+  if (phase == 0)
+    launch(PH_STAGE_COUPLING, k_h_proj, dim3((unsigned)m.n_hblk, (unsigned)nrc, (unsigned)in.T), dim3(NT), st, xt, W,
+           (const HBlkDev*)m.hblk.p, (const double*)m.hT.p, (const double*)in.C.p, m.h_tot, m.hw_tot, m.n, Rs,
+           (int)nrc);
+  else
+    launch(PH_STAGE_LEAF_DOWN, k_h_apply, dim3((unsigned)m.n_mvm_items, (unsigned)nrc, (unsigned)in.T), dim3(NT),
+           st, yt, (const double*)W, (const HBlkDev*)m.hblk.p, (const double*)m.hS.p, (const int32_t*)m.hl_ptr.p,
+           (const int32_t*)m.hl_blk.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
+           (const int32_t*)m.mvm_items.p, m.tree->leaves.front(), m.hw_tot, m.n, Rs, (int)nrc);
+}
+
+}  // namespace ph

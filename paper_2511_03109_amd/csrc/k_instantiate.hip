@@ -254,7 +254,9 @@ void instantiate_impl(InstData& in, const double* theta, hipStream_t st) {
          box, in.v.p, in.T, m.d_theta, m.p_theta, in.grad_dim);
   const int64_t Cps = m.n_classes * m.Pp * m.Pp;
   const int nMt = m.Pp / 16;
-  {
+  if (m.format == PH_FORMAT_H) {
+    h_core_launch(in, st);   // far cores H_q(theta_t) of the parametric H-matrix format
+  } else {
     constexpr int FT = 4;
     launch(PH_STAGE_FAR_INST, k_far_instantiate<S, FT>, dim3((unsigned)((nMt * nMt + FT - 1) / FT),
            (unsigned)m.n_stored_cls), dim3(NT), st, (const ClassDev*)m.cstore.p, (const double*)m.ff_chat.p,

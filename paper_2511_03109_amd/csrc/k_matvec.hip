@@ -902,7 +902,11 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
   // one right-hand side is stored unpadded (the coupling packs box targets instead)
   const int64_t Rs = R == 1 ? 1 : rhs_stride(R);
   const int64_t nrc = (Rs + RC - 1) / RC;
-  const bool use_far = m.min_far >= 0;
+  // parametric H-matrix format: explicit far factors per block instead of the H^2 far chain
+  const bool hfmt = m.format == PH_FORMAT_H;
+  const bool use_far = m.min_far >= 0 && !hfmt;
+  const bool use_hfar = hfmt && m.n_hblk > 0;
+  if (hfmt && sizeof(S) != sizeof(double)) fail(PH_EUNSUPPORTED, "ph_matvec: H-matrix models are FP64 only");
   // class-list chunks per target box: 8 (one per XCD) unless the lists are too short;
   // PH_COUPLING_CHUNKS overrides (tuning)
   // launch configuration: environment override (tuning sweeps), else ph_autotune's
@@ -939,6 +943,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     fail(PH_EUNSUPPORTED, "ph_matvec: per-slot coupling buffers exceed 2 GiB (reduce R)");
   S *xt, *yt, *xh, *yh, *partp = nullptr, *zbp = nullptr;
   void* xbp = nullptr;
+  double* hwp = nullptr;   // H-matrix format: w_b = H_b T_b^T x_t per far block
   if (ext) {
     // caller-provided scratch (no allocation): the same buffers carved at 256-byte offsets
     size_t off = 0;
@@ -954,6 +959,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     if (G > 1) partp = carve((size_t)G * T * m.n_nodes * m.Pp * Rs * sizeof(S));
     if (need_zb) zbp = carve((size_t)T * m.Zt * sizeof(S));
     if (bf16_mc) xbp = carve((size_t)T * coupling_bf16_x_bytes(m, Rs));
+    if (use_hfar) hwp = (double*)carve((size_t)T * nrc * m.hw_tot * sizeof(double));
     if (off > ext->bytes)
       fail(PH_EINVAL, "ph_matvec_noalloc: this MVM needs " + std::to_string(off) + " bytes of scratch, more than the " +
                           std::to_string(ext->bytes) + " the library reserves per GPU");
@@ -987,6 +993,14 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
       in.xb.alloc(need);
     }
     xbp = in.xb.p;
+  }
+  if (use_hfar) {
+    const size_t need = (size_t)T * nrc * m.hw_tot * sizeof(double);
+    if (in.hw.n < need) {
+      if (in.graphs > 0) fail(PH_ESTATE, "ph_matvec: the instance has recorded graphs, its scratch cannot grow");
+      in.hw.alloc(need);
+    }
+    hwp = (double*)in.hw.p;
   }
   }
   const int32_t leaf0 = t.leaves.front();
@@ -1124,7 +1138,9 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
              m.d, m.p_s, m.P, m.Pp, m.n_nodes, Rs);
     }
   }
+  if (use_hfar) h_far_launch(in, (const double*)xt, nullptr, hwp, Rs, nrc, st, 0);
   if (!serial) PH_HIP(hipStreamWaitEvent(st, in.ev_join, 0));
+  if (use_hfar) h_far_launch(in, nullptr, (double*)yt, hwp, Rs, nrc, st, 1);
   if (use_far)
     launch(PH_STAGE_LEAF_DOWN, k_leaf_down<S>, dim3((unsigned)m.n_mvm_items, (unsigned)nrc, (unsigned)T),
            dim3(NT), st, yt, (const S*)yh, (const double*)m.U.p, (const int64_t*)m.nbegin.p,

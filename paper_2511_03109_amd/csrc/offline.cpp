@@ -654,4 +654,74 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
   return m;
 }
 
+// Parametric H-matrix far field (Def. "Parametric H-matrix"; App. PTTK, offline phase 3).
+// For far block b = (s, t) of class c with stored class q: S_b = U_s A and T_b = U_t B, where
+// (A, B) = (L_q, R_q), or (R_q, L_q) when c is the mirror of q (its far tensor is the transpose),
+// and U_s is the tensor Chebyshev basis of cluster s (nodes on its own box, index little-endian
+// over the axes) evaluated at the cluster's points in tree order.  The block's coupling is then
+// S_b H_q(theta) T_b^T, or S_b H_q(theta)^T T_b^T for a mirrored class.
+void hmatrix_far_host(const TreeData& t, HostModel& m, int num_threads) {
+  const int d = t.d, ps = m.p_s, P = m.P;
+  const int64_t nfar = t.n_far();
+  const int nthreads = num_threads > 0 ? num_threads : omp_get_max_threads();
+  m.hblk.assign(nfar, HBlock{});
+  int64_t offS = 0, offT = 0;
+  for (int64_t b = 0; b < nfar; ++b) {
+    HBlock& h = m.hblk[b];
+    h.s = t.far[2 * b];
+    h.t = t.far[2 * b + 1];
+    const int32_t c = t.far_class[b];
+    h.q = m.class_src[c];
+    h.tr = m.class_tr[c];
+    const ClassStored& cs = m.cstore[h.q];
+    h.rs = h.tr ? cs.rR : cs.rL;
+    h.rt = h.tr ? cs.rL : cs.rR;
+    h.s_begin = t.begin[h.s];
+    h.t_begin = t.begin[h.t];
+    h.ns = t.size(h.s);
+    h.nt = t.size(h.t);
+    h.lds = (int32_t)((h.ns + 15) / 16 * 16);
+    h.ldt = (int32_t)((h.nt + 15) / 16 * 16);
+    h.S_off = offS;
+    h.T_off = offT;
+    offS += (int64_t)h.lds * h.rs;
+    offT += (int64_t)h.ldt * h.rt;
+  }
+  m.hS.assign((size_t)offS, 0.0);
+  m.hT.assign((size_t)offT, 0.0);
+  // rows of U_node A for the points [begin, begin + np) of a node, into out (column-major, ld)
+  auto project = [&](int32_t node, int64_t begin, int64_t np, const double* A, int r, double* out, int64_t ld) {
+    double nodes[3][16], lk[3][16];
+    for (int k = 0; k < d; ++k) cheb_nodes(t.box_lo[node * d + k], t.box_hi[node * d + k], ps, nodes[k]);
+    std::vector<double> u(P);
+    for (int64_t i = 0; i < np; ++i) {
+      for (int k = 0; k < d; ++k) lagrange_all(nodes[k], ps, t.pts_t[(begin + i) * d + k], lk[k]);
+      for (int mi = 0; mi < P; ++mi) {
+        double v = 1.0;
+        int rem = mi;
+        for (int k = 0; k < d; ++k) {
+          v *= lk[k][rem % ps];
+          rem /= ps;
+        }
+        u[mi] = v;
+      }
+      for (int a = 0; a < r; ++a) {
+        double acc = 0.0;
+        for (int mi = 0; mi < P; ++mi) acc += u[mi] * A[(size_t)mi + (size_t)P * a];
+        out[(size_t)i + (size_t)ld * a] = acc;
+      }
+    }
+  };
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 4)
+  for (int64_t b = 0; b < nfar; ++b) {
+    const HBlock& h = m.hblk[b];
+    const ClassStored& cs = m.cstore[h.q];
+    const double* L = m.ff_L.data() + cs.L_off;   // P x rL
+    const double* R = m.ff_R.data() + cs.R_off;   // P x rR
+    project(h.s, h.s_begin, h.ns, h.tr ? R : L, h.rs, m.hS.data() + h.S_off, h.lds);
+    project(h.t, h.t_begin, h.nt, h.tr ? L : R, h.rt, m.hT.data() + h.T_off, h.ldt);
+  }
+  m.hformat = true;
+}
+
 }  // namespace ph

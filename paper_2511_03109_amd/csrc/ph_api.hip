@@ -30,6 +30,49 @@ hipEvent_t pooled_event() {
 }
 
 // ------------------------------------------------------------------ model upload
+// The far field of the parametric H-matrix format: per far block its factors and offsets, per
+// stored class its core, and per leaf the far blocks whose target cluster contains the leaf.
+static void upload_hmatrix(DeviceModel& m, const TreeData& t, const HostModel& hm, hipStream_t st) {
+  m.format = PH_FORMAT_H;
+  std::vector<HClsDev> hc(hm.cstore.size());
+  int64_t hoff = 0;
+  for (size_t q = 0; q < hm.cstore.size(); ++q) {
+    const ClassStored& c = hm.cstore[q];
+    hc[q] = HClsDev{c.core_off, c.th1_off, c.th2_off, hoff, c.rL, c.r1, c.r2, c.rR};
+    hoff += (int64_t)c.rL * c.rR;
+  }
+  m.h_tot = hoff;
+  std::vector<HBlkDev> hb(hm.hblk.size());
+  int64_t woff = 0;
+  std::vector<std::vector<int32_t>> by_target(t.n_nodes());
+  for (size_t b = 0; b < hm.hblk.size(); ++b) {
+    const HBlock& h = hm.hblk[b];
+    hb[b] = HBlkDev{h.s_begin, h.t_begin, h.S_off, h.T_off, hc[h.q].h_off, woff,
+                    (int32_t)h.ns, (int32_t)h.nt, h.rs, h.rt, h.lds, h.ldt, h.tr, h.q};
+    woff += (int64_t)h.rs * 16;
+    by_target[h.s].push_back((int32_t)b);
+  }
+  m.hw_tot = woff;
+  std::vector<int32_t> lptr{0}, lblk;
+  for (int32_t leaf : t.leaves) {
+    for (int32_t s = leaf; s >= 0; s = t.parent[s])
+      lblk.insert(lblk.end(), by_target[s].begin(), by_target[s].end());
+    lptr.push_back((int32_t)lblk.size());
+  }
+  m.n_hblk = (int64_t)hb.size();
+  m.n_hcls = (int64_t)hc.size();
+  m.hblk.upload(hb.data(), hb.size(), st);
+  m.hcls.upload(hc.data(), hc.size(), st);
+  m.hcore.upload(hm.ff_core.data(), hm.ff_core.size(), st);
+  m.hS.upload(hm.hS.data(), hm.hS.size(), st);
+  m.hT.upload(hm.hT.data(), hm.hT.size(), st);
+  m.hl_ptr.upload(lptr.data(), lptr.size(), st);
+  m.hl_blk.upload(lblk.data(), lblk.size(), st);
+  PH_HIP(hipStreamSynchronize(st));   // host staging buffers die with this call
+  m.device_bytes += (int64_t)(m.hblk.bytes() + m.hcls.bytes() + m.hcore.bytes() + m.hS.bytes() + m.hT.bytes() +
+                              m.hl_ptr.bytes() + m.hl_blk.bytes());
+}
+
 static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData> tp, HostModel& hm,
                                                  hipStream_t st) {
   const TreeData& t = *tp;
@@ -460,6 +503,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
                               m->grp_entry.bytes() + m->ent_cls.bytes() + m->ent_tau.bytes() + m->ent_mask.bytes() +
                               m->chunk_first.bytes() + m->mvm_items.bytes() + m->mvm_items64.bytes() + m->near_q.bytes() + m->hgrp_targets.bytes() + m->hent_cls.bytes() +
                               m->hent_tau.bytes() + m->hchunk_first.bytes());
+  if (hm.hformat) upload_hmatrix(*m, t, hm, st);
   return m;
 }
 
@@ -523,6 +567,8 @@ int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype
     need(dt == PH_F64 || dt == PH_F32 || dt == PH_BF16, "dtype must be PH_F64, PH_F32 or PH_BF16");
     need(near == PH_NEAR_AUTO || near == PH_NEAR_BLOCKS || near == PH_NEAR_FACTORED, "invalid near-field mode");
     const ph::DeviceModel& md = *m->p;
+    if (md.format == PH_FORMAT_H && dt != PH_F64)
+      ph::fail(PH_EUNSUPPORTED, "parametric H-matrix models support PH_F64 instances only");
     if (near == PH_NEAR_FACTORED && md.KRp > 64)
       ph::fail(PH_EUNSUPPORTED, "factored near field supports near ranks up to 64");
     // automatic form: factored for one batch of 4..8 slots, where each factor entry read
@@ -564,8 +610,9 @@ int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype
       } else {
         in->D.alloc((size_t)T * md.N_nf_pad * in->d_esize);
       }
-      in->C.alloc((size_t)T * md.n_classes * md.Pp * md.Pp * in->esize);
-      if (dt == PH_BF16 && md.min_far >= 0 && md.n_groups > 0 && ph::coupling_bf16_supported(md, ph::RC))
+      if (md.format == PH_FORMAT_H) in->C.alloc((size_t)T * md.h_tot * sizeof(double));   // H_q(theta_t)
+      else in->C.alloc((size_t)T * md.n_classes * md.Pp * md.Pp * in->esize);
+      if (md.format == PH_FORMAT_H2 && dt == PH_BF16 && md.min_far >= 0 && md.n_groups > 0 && ph::coupling_bf16_supported(md, ph::RC))
         in->Cb.alloc((size_t)T * ph::coupling_bf16_c_bytes(md));
       in->v.alloc((size_t)T * md.d_theta * md.p_theta);
       in->theta_d.alloc((size_t)T * md.d_theta);
@@ -681,6 +728,23 @@ int ph_offline_compress(const ph_tree* t, const ph_offline_opts* opts, void* str
     auto hm = ph::offline_host(*t->p, *opts);
     auto dm = ph::upload_model(t->p, *hm, (hipStream_t)stream);
     *out = new ph_model{dm};
+  });
+}
+
+int ph_offline_compress_h(const ph_tree* t, const ph_offline_opts* opts, void* stream, ph_model** out) {
+  return guarded([&] {
+    need(t && t->p && opts && out, "NULL argument");
+    auto hm = ph::offline_host(*t->p, *opts);
+    ph::hmatrix_far_host(*t->p, *hm, opts->num_threads);
+    auto dm = ph::upload_model(t->p, *hm, (hipStream_t)stream);
+    *out = new ph_model{dm};
+  });
+}
+
+int ph_model_format(const ph_model* m, int* format) {
+  return guarded([&] {
+    need(m && m->p && format, "NULL argument");
+    *format = m->p->format;
   });
 }
 
@@ -1073,6 +1137,8 @@ int ph_inst_coupling(const ph_inst* k, int t, int64_t c, double* host_out) {
     const ph::DeviceModel& m = *in.m;
     need(t >= 0 && t < in.T, "slot out of range");
     need(c >= 0 && c < m.n_classes, "class index out of range");
+    if (m.format == PH_FORMAT_H)
+      ph::fail(PH_EUNSUPPORTED, "ph_inst_coupling: a parametric H-matrix instance forms no coupling matrices");
     const int64_t cnt = (int64_t)m.Pp * m.Pp;
     PH_HIP(hipDeviceSynchronize());
     std::vector<char> buf(cnt * in.esize);

@@ -138,6 +138,17 @@ constexpr int MAXT = 64;   // parameter values per theta-vector launch
 constexpr int RC = 16;     // right-hand sides per MFMA column tile
 constexpr int NTG = 16;    // coupling targets per work group (one box of nodes of a level)
 
+// Parametric H-matrix format: a far block (explicit factors S_b, T_b) and a stored class (its
+// core, theta factors and the offset of H_q(theta) in the instance's far buffer).
+struct HBlkDev {
+  int64_t s_begin, t_begin, S_off, T_off, h_off, w_off;
+  int32_t ns, nt, rs, rt, lds, ldt, tr, q;
+};
+struct HClsDev {
+  int64_t core_off, th1_off, th2_off, h_off;
+  int32_t rL, r1, r2, rR;
+};
+
 struct DeviceModel {
   std::shared_ptr<const TreeData> tree;
   int d = 0, p_s = 0, P = 0, Pp = 0, p_theta = 0, d_theta = 0, l_max = 0, min_far = -1;
@@ -195,6 +206,16 @@ struct DeviceModel {
   int gemv_mp = 12;   // single-RHS near MVM: 16-row panels per row chunk (4, 8 or 12)
   DevArr<ClassDev> cstore;
   DevArr<double> ff_chat, ff_theta;       // far panels (r1 r2 of Pp x Pp per class), theta factors
+  // parametric H-matrix format (PH_FORMAT_H): per far block S_b, T_b; per stored class the far
+  // core; per leaf the far blocks whose target cluster contains it (CSR); the instance's far
+  // buffer holds H_q(theta_t) at t h_tot + h_off (h_tot entries per slot); the MVM's scratch W
+  // holds w_b = H_b T_b^T x_t (hw_tot entries per slot and 16-column RHS tile)
+  int format = PH_FORMAT_H2;
+  int64_t n_hblk = 0, n_hcls = 0, h_tot = 0, hw_tot = 0;
+  DevArr<HBlkDev> hblk;
+  DevArr<HClsDev> hcls;
+  DevArr<double> hcore, hS, hT;
+  DevArr<int32_t> hl_ptr, hl_blk;
   // coupling work list: target boxes of NTG nodes of one level (see coupling_groups)
   DevArr<int32_t> grp_targets;            // n_groups x NTG node ids (-1 = absent)
   DevArr<int32_t> grp_entry;              // n_groups + 1
@@ -225,6 +246,7 @@ struct InstData {
   // BF16 instances: C in the operand order of the BF16 coupling ([slot][class][32-wide K
   // panel][row tile][lane][8]); xb: the matching BF16 copy of x_hat (MVM scratch)
   DevArr<char> Cb, xb;
+  DevArr<char> hw;   // parametric H-matrix format: MVM scratch w_b per far block, slot and RHS tile
   // factored near field (no D): c_b(theta_t) per stored block q, rank chunk c and slot t at
   // ((q KRp / KM + c) T + t) KM
   bool factored = false;
@@ -301,6 +323,12 @@ bool coupling_bf16_supported(const DeviceModel& m, int64_t Rs);
 void coupling_bf16_pack_c(const InstData& in, hipStream_t st);
 void coupling_bf16_launch(const InstData& in, const float* xh, void* xb, float* out, int G, int64_t Rs, int64_t nrc,
                           int64_t a0, hipStream_t st);
+// Parametric H-matrix format (k_hmatrix.hip): H_q(theta_t) for every stored class and slot
+// into the instance's far buffer; the far field of the MVM, phase 0: W = H_b T_b^T x_t for
+// every far block, phase 1: yt += S_b w_b over the far blocks containing each row
+void h_core_launch(const InstData& in, hipStream_t st);
+void h_far_launch(const InstData& in, const double* xt, double* yt, double* W, int64_t Rs, int64_t nrc,
+                  hipStream_t st, int phase);
 void cg_solve_impl(InstData& hi, InstData* lo, const double* y, double* a, double nugget, double tol,
                    int max_iter, int inner_max, double inner_tol, ph_cg_stats* stats, hipStream_t st);
 

@@ -78,6 +78,14 @@ struct ClassStored {
   int64_t L_off, R_off, core_off, th1_off, th2_off, chat_off;
 };
 
+// Far block of the parametric H-matrix format: S_b (n_s x rs) and T_b (n_t x rt), column-major
+// with leading dimensions lds, ldt (n rounded up to 16, zero rows), stored class q of the
+// block's translation class and tr = 1 when the block uses the transposed class.
+struct HBlock {
+  int32_t s, t, q, tr, rs, rt, lds, ldt;
+  int64_t s_begin, t_begin, ns, nt, S_off, T_off;
+};
+
 struct HostModel {
   int d = 0, p_s = 0, P = 0, p_theta = 0, d_theta = 0;
   ph_kernel kernel = PH_KERNEL_GAUSSIAN;
@@ -93,9 +101,16 @@ struct HostModel {
   int64_t kernel_evals = 0;
   int64_t near_factor_entries = 0;
   int svd_sweeps_max = 0;   // most one-sided Jacobi sweeps any SVD of the stage needed
+  // parametric H-matrix format (ph_offline_compress_h): explicit far factors per far block
+  bool hformat = false;
+  std::vector<HBlock> hblk;
+  std::vector<double> hS, hT;
 };
 
 std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts& o);
+// The far factors of the parametric H-matrix format from the class factors of offline_host
+// (offline_h.cpp); sets m.hformat.
+void hmatrix_far_host(const TreeData& t, HostModel& m, int num_threads);
 
 // kernel value kappa(x, y; theta) on the host
 double kernel_value(ph_kernel k, int d, const double* x, const double* y, const double* th);

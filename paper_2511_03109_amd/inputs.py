@@ -85,6 +85,9 @@ WORKLOADS = {
     6: dict(name="matern_nu_3d_n4096", n=4096, d=3, points="uniform", kernel="matern",
             theta_lo=[0.1, 0.5], theta_hi=[1.0, 3.0], p_s=5, p_theta=7, leaf=64, eta2=(3, 1),
             tol=1e-8, T=8, R=16),
+    7: dict(name="exp_3d_n32768", n=32768, d=3, points="uniform", kernel="matern12",
+            theta_lo=[0.25], theta_hi=[1.0], p_s=5, p_theta=9, leaf=64, eta2=(3, 1),
+            tol=1e-8, T=8, R=16),
 }
 
 

@@ -271,6 +271,53 @@ def test_matern_free_nu(case):
         _mvm_case(X, "matern", [0.1, 0.5], [1.0, 3.0], 4, 7, 1e-8, 2, (3, 1), [0.17, 0.71], R=3)
 
 
+@pytest.mark.parametrize("case", ["2d_R1", "2d_T3_R17", "3d_R16", "matern_nu"])
+def test_hmatrix_variant(case):
+    """The parametric H-matrix format (ph_offline_compress_h): every slot's MVM (with a nugget)
+    against the oracle's H-matrix variant, y_s += S_b (H_b (T_b^T x_t)) per far block plus the
+    near field, at the FP64 tolerance; one right-hand side, three slots with two RHS tiles (the
+    second holding one column), 3-D Matern-3/2 with 16 RHS, and Matern with free nu.  Non-FP64
+    instances and coupling inspection are rejected with PH_EUNSUPPORTED."""
+    torch = _torch()
+    from paper_2511_03109_amd import _lib, api
+    if case.startswith("2d"):
+        n = 2000
+        X = inputs.points_for(1, n)
+        args = ("gaussian", [0.05], [0.5], 6, 9, 1e-8, 3, (2, 1))
+        T, R = (1, 1) if case == "2d_R1" else (3, 17)
+    elif case == "3d_R16":
+        n = 3000
+        X = inputs.points_for(2, n)
+        args = ("matern32", [0.05], [0.5], 5, 11, 1e-8, 2, (3, 1))
+        T, R = 1, 16
+    else:
+        n = 2000
+        X = inputs.points_for(1, n)
+        args = ("matern", [0.25, 0.5], [1.0, 3.0], 6, 7, 1e-8, 3, (2, 1))
+        T, R = 2, 4
+    kernel, lo, hi, p_s, p_theta, tol, l_max, eta2 = args
+    lt = api.Tree(X, l_max=l_max, eta2=eta2)
+    lm = api.Model(lt, kernel, lo, hi, p_s=p_s, p_theta=p_theta, tol=tol, format="h")
+    assert lm.format == "h"
+    om = hmat.PH2(X, l_max=l_max, eta2=Fraction(*eta2), kernel=kernels.KERNELS[kernel][0], theta_lo=lo,
+                  theta_hi=hi, p_s=p_s, p_theta=p_theta, tol=tol)
+    _check_ranks(lm, om)
+    thetas = inputs.theta_samples(T, lo, hi, 31)
+    inst = api.Instance(lm, thetas)
+    x = inputs.normal_vectors(n, T * R, 41).T.reshape(T, R, n)
+    y = inst.matvec(torch.tensor(np.ascontiguousarray(x), device="cuda"), nugget=0.3).cpu().numpy()
+    sizes = [len(om.tree.idx[s_]) for s_ in om.tree.leaves]
+    for t in range(T):
+        y_o = om.matvec_h(om.instantiate_h(thetas[t]), x[t].T, nugget=0.3)
+        _close(y[t].T, y_o, what=f"H-matrix mvm {case} slot {t}", max_entries=max(sizes) ** 2)
+    with pytest.raises(_lib.PHError) as e:
+        api.Instance(lm, thetas, dtype="f32")
+    assert e.value.code == _lib.PH_EUNSUPPORTED
+    with pytest.raises(_lib.PHError) as e:
+        inst.coupling(0)
+    assert e.value.code == _lib.PH_EUNSUPPORTED
+
+
 def test_multi_theta_slots_and_alpha_beta():
     torch = _torch()
     from paper_2511_03109_amd import api
