@@ -289,7 +289,25 @@ def mode_cg(args):
     for k in ("f32", "bf16"):
         if res[k]["stats"]["converged"]:
             res[k]["speedup_vs_fp64_cg"] = res["f64"]["solve_s"] / res[k]["solve_s"]
-    print(json.dumps({"metric": "solve time to relative residual 1e-6, FP64 CG vs FP64-refined FP32/BF16",
+    # the batched form: 16 right-hand sides solved together (ph_cg_solve_batch), every column to
+    # the same 1e-6 FP64 residual; time per solve against the single-RHS FP64 CG
+    RB = 16
+    Yb = torch.tensor(np.ascontiguousarray(inputs.normal_vectors(n, RB, 5, inputs.STREAM_Y).T), device="cuda")
+    for lo_dt in (None, "f32"):
+        hi = api.Instance(model, [th])
+        lo = api.Instance(model, [th], dtype=lo_dt) if lo_dt else None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a, st = api.cg_solve(hi, Yb, nugget=nug, tol=1e-6, lo=lo, max_iter=20000 if lo is None else 60,
+                             inner_max=20000, inner_tol=5e-7)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t0
+        key = f"batched16_{lo_dt or 'f64'}"
+        res[key] = {"solve_s": t_solve, "solve_s_per_rhs": t_solve / RB, "stats": st,
+                    "speedup_per_rhs_vs_fp64_cg": res["f64"]["solve_s"] / (t_solve / RB) if st["converged"] else None}
+        del hi, lo, a
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "solve time to relative residual 1e-6, FP64 CG vs FP64-refined FP32/BF16, single and 16 RHS",
                       "unit": "s", "higher_is_better": False, "n_gpus": 1,
                       "config": {"workload": w["name"], "n": n, "theta": th, "nugget": nug}, "data": "synthetic",
                       "results": res}))

@@ -343,6 +343,15 @@ typedef struct {
 int ph_cg_solve(ph_inst* hi, ph_inst* lo, const double* y, double* a, double nugget, double tol, int max_iter,
                 int inner_max, double inner_tol, ph_cg_stats* stats, void* stream);
 
+/* ph_cg_solve for R right-hand sides at once (the batched form): y and a are device [R][n]
+ * arrays (column c at c n, original point order), 1 <= R <= 1024.  Every iteration applies the
+ * instance to the R search directions in one ph_matvec product, while each column keeps its own
+ * CG scalars and stops on its own (refinement: per-column residual scaling and the same FP64
+ * residual test per column).  stats: the largest iteration count and the worst final relative
+ * residual over the columns; converged when every column meets tol.  Errors as ph_cg_solve. */
+int ph_cg_solve_batch(ph_inst* hi, ph_inst* lo, const double* y, double* a, int64_t R, double nugget, double tol,
+                      int max_iter, int inner_max, double inner_tol, ph_cg_stats* stats, void* stream);
+
 /* ---- batched launches -----------------------------------------------------------------
  * Launch configuration of ph_matvec picked by measurement (autotuner): for the instance's
  * T slots and R right-hand sides, every combination of coupling class-list chunks

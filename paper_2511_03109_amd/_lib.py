@@ -90,6 +90,8 @@ SIGNATURES = {
     "ph_bilinear": ([_P, _P, _P, C.c_int64, _P, _P], C.c_int),
     "ph_cg_solve": ([_P, _P, _P, _P, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
                      C.POINTER(CgStats), _P], C.c_int),
+    "ph_cg_solve_batch": ([_P, _P, _P, _P, C.c_int64, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
+                           C.POINTER(CgStats), _P], C.c_int),
     "ph_autotune": ([_P, _P, _P, C.c_int64, _P, C.POINTER(TuneInfo)], C.c_int),
     "ph_graph_create": ([_P, _P, _P, C.c_int64, C.c_double, _P, C.POINTER(_P)], C.c_int),
     "ph_graph_launch": ([_P, _DP, _P], C.c_int),

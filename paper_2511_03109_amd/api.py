@@ -306,19 +306,27 @@ def kernel_eval(kernel, x, y, theta):
 
 def cg_solve(inst64, y, *, nugget, tol=1e-6, lo=None, max_iter=100000, inner_max=1000, inner_tol=1e-4,
              stream=None):
-    """Solve (K~ + nugget I) a = y (ph_cg_solve).  inst64: FP64 instance with T = 1; y: device
-    float64 tensor of length n; lo: optional FP32/BF16 instance of the same theta for FP64
-    iterative refinement.  Returns (a, stats dict)."""
+    """Solve (K~ + nugget I) a = y (ph_cg_solve, or ph_cg_solve_batch for several right-hand
+    sides).  inst64: FP64 instance with T = 1; y: device float64 tensor of shape (n,) or (R, n);
+    lo: optional FP32/BF16 instance of the same theta for FP64 iterative refinement.  Returns
+    (a, stats dict); for R columns the stats are the largest iteration count and the worst
+    residual."""
     import torch
-    if y.dtype != torch.float64 or not y.is_cuda or y.dim() != 1:
-        raise TypeError("y must be a 1-D float64 device tensor")
+    if y.dtype != torch.float64 or not y.is_cuda or y.dim() not in (1, 2):
+        raise TypeError("y must be a float64 device tensor of shape (n,) or (R, n)")
     y = y.contiguous()
     a = torch.empty_like(y)
     st = L.CgStats()
-    code = L.lib().ph_cg_solve(inst64._h, lo._h if lo is not None else None, C.c_void_p(y.data_ptr()),
-                               C.c_void_p(a.data_ptr()), nugget, tol, max_iter, inner_max, inner_tol,
-                               C.byref(st), _stream(stream))
-    L.check(code, "ph_cg_solve")
+    lo_h = lo._h if lo is not None else None
+    if y.dim() == 1:
+        code = L.lib().ph_cg_solve(inst64._h, lo_h, C.c_void_p(y.data_ptr()), C.c_void_p(a.data_ptr()), nugget,
+                                   tol, max_iter, inner_max, inner_tol, C.byref(st), _stream(stream))
+        L.check(code, "ph_cg_solve")
+    else:
+        code = L.lib().ph_cg_solve_batch(inst64._h, lo_h, C.c_void_p(y.data_ptr()), C.c_void_p(a.data_ptr()),
+                                         y.shape[0], nugget, tol, max_iter, inner_max, inner_tol, C.byref(st),
+                                         _stream(stream))
+        L.check(code, "ph_cg_solve_batch")
     return a, {k: getattr(st, k) for k, _ in L.CgStats._fields_}
 
 
@@ -331,14 +339,28 @@ def _autograd_function():
         theta: (d_theta,) with x of shape (n,) or (R, n), or (T, d_theta) with x of shape
         (T, R, n).  Backward: dL/dx = (K~ + nugget I) g (K~ is symmetric by construction)
         and dL/dtheta_i = sum_r g_r . (dK~/dtheta_i) x_r, the bilinear form of the
-        instance of ph_instantiate_grad, both computed by the library.
+        instance of ph_instantiate_grad, both computed by the library.  One instance per
+        (model, T, dtype) is kept and re-instantiated in place for the forward product, the
+        backward product and each derivative (no device allocation after the first call);
+        backward re-instantiates at its own theta, so other forward calls in between are safe.
         """
+
+        @staticmethod
+        def _instance(model, th, dtype):
+            cache = model.__dict__.setdefault("_autograd_instances", {})
+            key = (th.shape[0], dtype)
+            inst = cache.get(key)
+            if inst is None:
+                inst = cache[key] = Instance(model, th, dtype=dtype)
+            else:
+                inst.reinstantiate(th)
+            return inst
 
         @staticmethod
         def forward(ctx, theta, x, model, nugget=0.0):
             th = theta.detach().to("cpu", torch.float64).numpy().reshape(-1, model.d_theta)
             dtype = "f64" if x.dtype == torch.float64 else "f32"
-            inst = Instance(model, th, dtype=dtype)
+            inst = KThetaMatvec._instance(model, th, dtype)
             y = inst.matvec(x, nugget=nugget)
             ctx.save_for_backward(x)
             ctx.inst, ctx.model, ctx.nugget, ctx.th, ctx.theta_meta = inst, model, nugget, th, theta
@@ -350,12 +372,13 @@ def _autograd_function():
             g = g.contiguous()
             gtheta = gx = None
             if ctx.needs_input_grad[1]:
+                ctx.inst.reinstantiate(ctx.th)
                 gx = ctx.inst.matvec(g, nugget=ctx.nugget)
             if ctx.needs_input_grad[0]:
                 cols = []
                 for i in range(ctx.model.d_theta):
-                    gi = Instance(ctx.model, ctx.th, dtype=ctx.inst.dtype, grad_dim=i)
-                    cols.append(gi.bilinear(g, x))
+                    ctx.inst.reinstantiate(ctx.th, grad_dim=i)
+                    cols.append(ctx.inst.bilinear(g, x))
                 meta = ctx.theta_meta
                 gtheta = torch.stack(cols, dim=-1).reshape(meta.shape).to(meta.dtype).to(meta.device)
             return gtheta, gx, None, None

@@ -892,11 +892,12 @@ int ph_bilinear(ph_inst* k, const void* u, const void* x, int64_t R, double* out
   });
 }
 
-int ph_cg_solve(ph_inst* hi, ph_inst* lo, const double* y, double* a, double nugget, double tol, int max_iter,
-                int inner_max, double inner_tol, ph_cg_stats* stats, void* stream) {
+int ph_cg_solve_batch(ph_inst* hi, ph_inst* lo, const double* y, double* a, int64_t R, double nugget, double tol,
+                      int max_iter, int inner_max, double inner_tol, ph_cg_stats* stats, void* stream) {
   return guarded([&] {
     need(hi && hi->p, "FP64 instance is NULL");
     need(y && a, "y or a is NULL");
+    need(R >= 1 && R <= 1024, "R must be in 1..1024");
     ph::InstData& h = *hi->p;
     need(h.dt == PH_F64 && h.T == 1, "hi must be a PH_F64 instance with T = 1");
     need(h.grad_dim < 0, "hi must not be a gradient instance");
@@ -911,8 +912,13 @@ int ph_cg_solve(ph_inst* hi, ph_inst* lo, const double* y, double* a, double nug
            "lo must instantiate the same model at the same theta");
       need(inner_max >= 1 && inner_tol > 0, "inner_max must be >= 1 and inner_tol > 0");
     }
-    ph::cg_solve_impl(h, l, y, a, nugget, tol, max_iter, inner_max, inner_tol, stats, (hipStream_t)stream);
+    ph::cg_solve_impl(h, l, y, a, R, nugget, tol, max_iter, inner_max, inner_tol, stats, (hipStream_t)stream);
   });
+}
+
+int ph_cg_solve(ph_inst* hi, ph_inst* lo, const double* y, double* a, double nugget, double tol, int max_iter,
+                int inner_max, double inner_tol, ph_cg_stats* stats, void* stream) {
+  return ph_cg_solve_batch(hi, lo, y, a, 1, nugget, tol, max_iter, inner_max, inner_tol, stats, stream);
 }
 
 int ph_autotune(ph_inst* k, const void* x, void* y, int64_t R, void* stream, ph_tune_info* info) {

@@ -329,7 +329,8 @@ void coupling_bf16_launch(const InstData& in, const float* xh, void* xb, float* 
 void h_core_launch(const InstData& in, hipStream_t st);
 void h_far_launch(const InstData& in, const double* xt, double* yt, double* W, int64_t Rs, int64_t nrc,
                   hipStream_t st, int phase);
-void cg_solve_impl(InstData& hi, InstData* lo, const double* y, double* a, double nugget, double tol,
+// CG / iterative refinement for the R right-hand sides [R][n] of y and a (k_solve.hip)
+void cg_solve_impl(InstData& hi, InstData* lo, const double* y, double* a, int64_t R, double nugget, double tol,
                    int max_iter, int inner_max, double inner_tol, ph_cg_stats* stats, hipStream_t st);
 
 // ---- per-kernel timing with HIP events

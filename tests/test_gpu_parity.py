@@ -780,6 +780,72 @@ def test_cg_iterative_refinement_bf16_well_conditioned():
     _solve_case("matern12", 0.1, 10.0, "bf16", 1e-8)
 
 
+@pytest.mark.parametrize("dtype_lo", [None, "f32"])
+def test_cg_batched_right_hand_sides(dtype_lo):
+    """ph_cg_solve_batch with 5 right-hand sides (one zero column, one a multiple of another):
+    every column's residual under the oracle's operator meets the tolerance, the zero column
+    gives a = 0, and each column equals the single-RHS solve of that column to the accuracy the
+    tolerance allows (tol times the condition-number bound ||a|| / ||y|| / nugget scaling)."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    n, R, theta, nugget, tol = 4096, 5, 0.1, 1e-2, 1e-8
+    X = inputs.points_for(5, n)
+    lt, lm, om = _setup(X, "matern12", [0.05], [0.5], 6, 9, 1e-8, 3, (2, 1))
+    Y = inputs.normal_vectors(n, R, 5, inputs.STREAM_Y).T.copy()   # (R, n)
+    Y[2] = 0.0
+    Y[4] = -3.0 * Y[1]
+    hi = api.Instance(lm, [theta])
+    lo = api.Instance(lm, [theta], dtype=dtype_lo) if dtype_lo else None
+    kw = dict(nugget=nugget, tol=tol, lo=lo, max_iter=20000 if lo is None else 200, inner_max=2000, inner_tol=1e-3)
+    A, st = api.cg_solve(hi, torch.tensor(Y, device="cuda"), **kw)
+    A = A.cpu().numpy()
+    print(f"[parity] batched cg ({dtype_lo or 'f64'}): {st}", flush=True)
+    assert st["converged"] == 1
+    oi = om.instantiate(theta)
+    assert np.all(A[2] == 0.0)
+    for c in (0, 1, 3, 4):
+        Ka = om.matvec(oi, A[c])
+        res = np.linalg.norm(Y[c] - Ka - nugget * A[c]) / np.linalg.norm(Y[c])
+        slack = 1e-12 * np.linalg.norm(Ka) / np.linalg.norm(Y[c])
+        assert res <= 1.001 * tol + slack, (c, res)
+    a1, st1 = api.cg_solve(hi, torch.tensor(Y[1], device="cuda"), **kw)
+    # both solutions have residual <= tol ||y||; their difference is bounded by
+    # 2 tol ||y|| / lambda_min(K~ + nugget I) >= ... with lambda_min >= nugget (up to the approximation)
+    assert np.linalg.norm(A[1] - a1.cpu().numpy()) <= 2.1 * tol * np.linalg.norm(Y[1]) / nugget
+
+
+def test_graph_replay_right_after_overlapped_instantiation(monkeypatch):
+    """With the near field on the instance's second stream (PH_SERIAL_MVM=0) an eager
+    re-instantiation leaves the near-block instantiation running there; a graph replay issued
+    right after it (no MVM between) must wait for it before rewriting the theta vectors and the
+    blocks.  Every replay equals the eager instantiate + MVM at the replay's theta bit for bit."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    monkeypatch.setenv("PH_SERIAL_MVM", "0")
+    n, T, R = 3000, 2, 16
+    X = inputs.points_for(2, n)
+    lt, lm, om = _setup(X, "matern32", [0.05], [0.5], 5, 11, 1e-8, 2, (3, 1))
+    rng = np.random.default_rng(21)
+    inst = api.Instance(lm, rng.uniform(0.05, 0.5, (T, 1)), near="blocks")
+    x = torch.tensor(np.ascontiguousarray(inputs.normal_vectors(n, T * R, 5).T.reshape(T, R, n)), device="cuda")
+    y = torch.empty_like(x)
+    ref = torch.empty_like(x)
+    s = torch.cuda.Stream()
+    g = inst.record(x, y, stream=s)
+    for rep in range(3):
+        th1, th2 = rng.uniform(0.05, 0.5, (T, 1)), rng.uniform(0.05, 0.5, (T, 1))
+        with torch.cuda.stream(s):
+            inst.reinstantiate(th1, stream=s)
+            g.launch(th2)
+        s.synchronize()
+        got = y.clone()
+        inst.reinstantiate(th2)
+        inst.matvec(x, ref)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), f"replay {rep}"
+    del g
+
+
 def test_autotune_and_graph_replays():
     """Uneven mixture, two parameters, T = 4 slots, R = 3: the autotuned configuration is
     valid and matches the oracle; a recorded instantiate + MVM graph replayed with new
