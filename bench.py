@@ -467,8 +467,41 @@ def mode_hmatrix(args):
                       "data": "synthetic", "results": res, "rel_diff_h_vs_h2": diff}))
 
 
+def mode_offline(args):
+    """The offline stage with the kernel tensors evaluated on the host against on the GPU (the
+    compression runs on the host in both), for the benchmark workload and the Matern free-nu
+    workload; seconds per offline stage and the relative difference of the two models' MVMs."""
+    import torch
+    from paper_2511_03109_amd import api, inputs
+    out = {}
+    for wid in (2, 6):
+        w = inputs.WORKLOADS[wid]
+        X = inputs.points_for(wid)
+        tree = api.Tree(X, leaf_size=w["leaf"], l_max=-1, eta2=tuple(w["eta2"]))
+        thetas = inputs.theta_samples(1, w["theta_lo"], w["theta_hi"], wid)
+        x = torch.tensor(np.ascontiguousarray(inputs.normal_vectors(w["n"], 16, wid).T), device="cuda")
+        res, ys = {}, {}
+        for where in ("host", "gpu"):
+            torch.cuda.synchronize()
+            t0 = time.time()
+            model = api.Model(tree, w["kernel"], w["theta_lo"], w["theta_hi"], p_s=w["p_s"],
+                              p_theta=w["p_theta"], tol=w["tol"], offline=where)
+            torch.cuda.synchronize()
+            res[where + "_s"] = time.time() - t0
+            ys[where] = api.Instance(model, thetas).matvec(x)
+            res["kernel_evals"] = model.info["kernel_evals"]
+            del model
+        res["rel_diff_mvm"] = float(torch.linalg.vector_norm(ys["gpu"] - ys["host"]) /
+                                    torch.linalg.vector_norm(ys["host"]))
+        res["speedup"] = res["host_s"] / res["gpu_s"]
+        out[w["name"]] = res
+        log(f"[bench] offline {w['name']}: {res}")
+    print(json.dumps({"metric": "offline stage seconds, kernel tensors on the host vs on the GPU",
+                      "unit": "s", "higher_is_better": False, "n_gpus": 1, "data": "synthetic", "results": out}))
+
+
 MODES = {"precision": mode_precision, "cg": mode_cg, "grad": mode_grad, "sweep": mode_sweep,
-         "matern": mode_matern, "hmatrix": mode_hmatrix}
+         "matern": mode_matern, "hmatrix": mode_hmatrix, "offline": mode_offline}
 
 
 def main():
@@ -480,7 +513,8 @@ def main():
     ap.add_argument("--cpu-sample-leaves", type=int, default=160)
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the comparison legs (per-theta FP64, near blocks in memory, FP32, BF16)")
-    ap.add_argument("--mode", default="step", choices=["step", "precision", "cg", "grad", "sweep", "matern", "hmatrix"],
+    ap.add_argument("--mode", default="step", choices=["step", "precision", "cg", "grad", "sweep", "matern", "hmatrix",
+                                                    "offline"],
                     help="step (default): the benchmark step; precision: FP64 / FP32 / BF16 instances of "
                          "the same step; cg: (K + 1e-2 I) a = y at n = 262144 by FP64 CG and by FP64 "
                          "refinement around FP32 / BF16; grad: forward + backward of y = K(l) x at "

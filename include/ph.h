@@ -207,6 +207,14 @@ typedef struct {
 int ph_offline_compress(const ph_tree* t, const ph_offline_opts* opts, void* stream,
                         ph_model** out);
 
+/* ph_offline_compress with the kernel tensors evaluated on the GPU (the kernel-tensor
+ * generation of Alg. "Offline Stage: Parametric H²-matrix": the near tensors of the stored near
+ * blocks in batches of at most 512 MB and the far tensors of the stored classes, by the same
+ * kernel functions as the host), compressed on the host as in ph_offline_compress.  The model is
+ * the same up to the rounding of the kernel values (a few ulp).  Errors as ph_offline_compress,
+ * plus PH_EHIP / PH_ENOMEM from the GPU. */
+int ph_offline_compress_gpu(const ph_tree* t, const ph_offline_opts* opts, void* stream, ph_model** out);
+
 /* Offline stage of the parametric H-matrix format (Alg. "Offline Stage: Parametric H-matrix";
  * App. PTTK offline, phases 1-3): the same near field and far tensors as ph_offline_compress,
  * then S_b = U_s L_b and T_b = U_t R_b for every far block (U_s evaluated on the block's own

@@ -76,6 +76,7 @@ SIGNATURES = {
     "ph_kernel_eval": ([C.c_int, C.c_int, _DP, _DP, C.c_int64, _DP, _DP], C.c_int),
     "ph_offline_compress": ([_P, C.POINTER(OfflineOpts), _P, C.POINTER(_P)], C.c_int),
     "ph_offline_compress_h": ([_P, C.POINTER(OfflineOpts), _P, C.POINTER(_P)], C.c_int),
+    "ph_offline_compress_gpu": ([_P, C.POINTER(OfflineOpts), _P, C.POINTER(_P)], C.c_int),
     "ph_model_format": ([_P, C.POINTER(C.c_int)], C.c_int),
     "ph_model_info_get": ([_P, C.POINTER(ModelInfo)], C.c_int),
     "ph_model_near_ranks": ([_P, _I32P], C.c_int),

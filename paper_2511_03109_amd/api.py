@@ -83,10 +83,11 @@ class Tree:
 
 class Model:
     """Offline stage output on the device: ph_offline_compress (format "h2", the parametric
-    H^2-matrix) or ph_offline_compress_h (format "h", the parametric H-matrix)."""
+    H^2-matrix), ph_offline_compress_h (format "h", the parametric H-matrix), or
+    ph_offline_compress_gpu (offline="gpu": kernel tensors evaluated on the GPU)."""
 
     def __init__(self, tree, kernel, theta_lo, theta_hi, *, p_s, p_theta, tol, num_threads=0,
-                 stream=None, format="h2"):
+                 stream=None, format="h2", offline="host"):
         lo = np.atleast_1d(np.asarray(theta_lo, dtype=np.float64))
         hi = np.atleast_1d(np.asarray(theta_hi, dtype=np.float64))
         opts = L.OfflineOpts()
@@ -97,7 +98,11 @@ class Model:
             opts.theta_hi[k] = hi[k]
         opts.p_s, opts.p_theta, opts.tol, opts.num_threads = p_s, p_theta, tol, num_threads
         h = C.c_void_p()
+        if offline not in ("host", "gpu") or (offline == "gpu" and format != "h2"):
+            raise ValueError('offline must be "host" or "gpu" (the GPU offline stage builds the H^2 format)')
         entry = {"h2": "ph_offline_compress", "h": "ph_offline_compress_h"}[format]
+        if offline == "gpu":
+            entry = "ph_offline_compress_gpu"
         L.check(getattr(L.lib(), entry)(tree._h, C.byref(opts), _stream(stream), C.byref(h)), entry)
         self._h = h
         fmt = C.c_int()

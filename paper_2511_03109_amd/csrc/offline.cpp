@@ -33,6 +33,7 @@
 #include <map>
 #include <numeric>
 
+#include "kernel_fn.hpp"
 #include "ph_host.hpp"
 
 namespace ph {
@@ -351,33 +352,11 @@ int kernel_dtheta(ph_kernel k, int d) {
 }
 
 double kernel_value(ph_kernel k, int d, const double* x, const double* y, const double* th) {
-  double r2 = 0;
-  for (int i = 0; i < d; ++i) r2 += (x[i] - y[i]) * (x[i] - y[i]);
-  switch (k) {
-    case PH_KERNEL_GAUSSIAN:
-      return std::exp(-r2 / (2.0 * th[0] * th[0]));
-    case PH_KERNEL_MATERN32: {
-      double s = std::sqrt(3.0) * std::sqrt(r2) / th[0];
-      return (1.0 + s) * std::exp(-s);
-    }
-    case PH_KERNEL_MATERN12:
-      return std::exp(-std::sqrt(r2) / th[0]);
-    case PH_KERNEL_ANISO_GAUSSIAN: {
-      double e = 0;
-      for (int i = 0; i < d; ++i) e += (x[i] - y[i]) * (x[i] - y[i]) / (2.0 * th[i] * th[i]);
-      return std::exp(-e);
-    }
-    case PH_KERNEL_POLY_TEST:
-      return th[0] * th[0] * r2 + th[0];
-    case PH_KERNEL_POLY2_TEST:
-      return th[0] * r2 + th[1] * th[1];
-    case PH_KERNEL_MATERN:
-      return matern_value(std::sqrt(r2), th[0], th[1]);
-  }
-  return 0.0;
+  if (k == PH_KERNEL_MATERN) return kernel_eval(k, d, x, y, th, bessel_order(th[1]));
+  return kernel_eval(k, d, x, y, th, BesselOrder{});
 }
 
-std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts& o) {
+std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts& o, bool gpu) {
   const int d = t.d;
   if (o.p_s < 1 || o.p_s > 16 || o.p_theta < 1 || o.p_theta > 16)
     fail(PH_EINVAL, "ph_offline_compress: p_s and p_theta must be in 1..16");
@@ -473,12 +452,14 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
   const int64_t nfc = (int64_t)m->cstore.size();
   std::vector<Tucker> ftuck(nfc);
   int64_t evals_far = 0;
-#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) reduction(+ : evals_far)
+  // Chebyshev nodes of the two boxes of each stored class's first far block (P x d each)
+  std::vector<double> cnodes((size_t)nfc * 2 * P * d);
   for (int64_t ci = 0; ci < nfc; ++ci) {
     const int32_t c = m->cstore[ci].cls;
     const int32_t b = t.class_first_block[c];
     const int32_t s = t.far[2 * b], u = t.far[2 * b + 1];
-    std::vector<double> ns((size_t)P * d), nt((size_t)P * d);
+    double* ns = cnodes.data() + (size_t)ci * 2 * P * d;
+    double* nt = ns + (size_t)P * d;
     for (int k = 0; k < d; ++k) {
       double bs[16], bt[16];
       cheb_nodes(t.box_lo[s * d + k], t.box_hi[s * d + k], ps, bs);
@@ -490,12 +471,30 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
         nt[(size_t)i * d + k] = bt[(i / stride) % ps];
       }
     }
+  }
+  // kernel tensors on the GPU (kernel-tensor generation of the offline stage), else per class
+  // on the host inside the compression loop
+  std::unique_ptr<GpuTensorGen> gen;
+  std::vector<double> Mall;
+  if (gpu) {
+    gen.reset(new GpuTensorGen(t, o.kernel, grid.data(), q));
+    Mall.resize((size_t)nfc * P * q * P);
+    gen->far(cnodes, (int)nfc, P, Mall.data());
+  }
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) reduction(+ : evals_far)
+  for (int64_t ci = 0; ci < nfc; ++ci) {
+    const double* ns = cnodes.data() + (size_t)ci * 2 * P * d;
+    const double* nt = ns + (size_t)P * d;
     std::vector<double> M((size_t)P * q * P);
-    for (int j = 0; j < P; ++j)
-      for (int kk = 0; kk < q; ++kk)
-        for (int i = 0; i < P; ++i)
-          M[(size_t)i + P * (kk + (size_t)q * j)] =
-              kernel_value(o.kernel, d, &ns[(size_t)i * d], &nt[(size_t)j * d], &grid[2 * kk]);
+    if (gpu) {
+      std::memcpy(M.data(), Mall.data() + (size_t)ci * P * q * P, M.size() * sizeof(double));
+    } else {
+      for (int j = 0; j < P; ++j)
+        for (int kk = 0; kk < q; ++kk)
+          for (int i = 0; i < P; ++i)
+            M[(size_t)i + P * (kk + (size_t)q * j)] =
+                kernel_value(o.kernel, d, &ns[(size_t)i * d], &nt[(size_t)j * d], &grid[2 * kk]);
+    }
     evals_far += (int64_t)P * q * P;
     std::vector<int64_t> dims{P};
     if (dth == 1) dims.push_back(pt);
@@ -587,23 +586,99 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
   const int64_t nst = (int64_t)m->nstore.size();
   std::vector<Tucker> ntuck(nst);
   int64_t evals_near = 0;
-#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) reduction(+ : evals_near)
-  for (int64_t bi = 0; bi < nst; ++bi) {
+  // near tensor of stored block bi from src (GPU-generated) or evaluated here, then compressed
+  auto near_one = [&](int64_t bi, const double* src) {
     const NearStored& b = m->nstore[bi];
     const int64_t Ne = (int64_t)b.ns * b.nt;
     std::vector<double> A((size_t)Ne * q);
-    for (int kk = 0; kk < q; ++kk)
-      for (int32_t j = 0; j < b.nt; ++j) {
-        const double* y = &t.pts_t[(size_t)(b.t_begin + j) * d];
-        double* col = A.data() + (size_t)kk * Ne + (size_t)j * b.ns;
-        for (int32_t i = 0; i < b.ns; ++i)
-          col[i] = kernel_value(o.kernel, d, &t.pts_t[(size_t)(b.s_begin + i) * d], y, &grid[2 * kk]);
-      }
-    evals_near += Ne * q;
+    if (src) {
+      std::memcpy(A.data(), src, A.size() * sizeof(double));
+    } else {
+      for (int kk = 0; kk < q; ++kk)
+        for (int32_t j = 0; j < b.nt; ++j) {
+          const double* y = &t.pts_t[(size_t)(b.t_begin + j) * d];
+          double* col = A.data() + (size_t)kk * Ne + (size_t)j * b.ns;
+          for (int32_t i = 0; i < b.ns; ++i)
+            col[i] = kernel_value(o.kernel, d, &t.pts_t[(size_t)(b.s_begin + i) * d], y, &grid[2 * kk]);
+        }
+    }
     std::vector<int64_t> dims{Ne};
     if (dth == 1) dims.push_back(pt);
     else { dims.push_back(pt); dims.push_back(pt); }
     ntuck[bi] = thosvd(A, dims, o.tol);
+  };
+  for (int64_t bi = 0; bi < nst; ++bi) evals_near += (int64_t)m->nstore[bi].ns * m->nstore[bi].nt * q;
+  if (!gpu) {
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
+    for (int64_t bi = 0; bi < nst; ++bi) near_one(bi, nullptr);
+  } else {
+    // batches of at most 64 M tensor entries (512 MB) generated on the GPU, then compressed
+    constexpr int64_t BATCH = (int64_t)1 << 26;
+    for (int64_t b0 = 0; b0 < nst;) {
+      std::vector<NearJob> jobs;
+      int64_t tot = 0, b1 = b0;
+      while (b1 < nst) {
+        const NearStored& b = m->nstore[b1];
+        const int64_t e = (int64_t)b.ns * b.nt * q;
+        if (tot > 0 && tot + e > BATCH) break;
+        jobs.push_back(NearJob{b.s_begin, b.t_begin, tot, b.ns, b.nt});
+        tot += e;
+        ++b1;
+      }
+      const int64_t nj = b1 - b0;
+      if (dth == 1 && q <= 16) {
+        // one parameter: the tensor A (Ne x q) is compressed on the GPU.  R of A = QR comes
+        // back; its SVD R = U_R S V^T gives the singular values and right singular vectors of
+        // A, the rank r follows the rule of the host HOSVD (both modes share the singular
+        // values), and the factors are U_e = A V_r S_r^-1 (formed on the GPU), Theta = V_r,
+        // core = S_r: the blocks U_e S_r Theta^T v(theta) = A V_r V_r^T v(theta).
+        std::vector<double> R((size_t)nj * q * q);
+        gen->near_qr(jobs, q, tot, R.data());
+        std::vector<std::vector<double>> sv(nj), vr(nj);
+        std::vector<int> sweeps(nj, 0);
+        std::vector<int32_t> rk(nj, 0);
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 4)
+        for (int64_t jb = 0; jb < nj; ++jb) {
+          std::vector<double> W(R.begin() + jb * q * q, R.begin() + (jb + 1) * q * q), U((size_t)q * q), V((size_t)q * q);
+          sv[jb].assign(q, 0.0);
+          sweeps[jb] = jacobi_svd(W.data(), q, sv[jb].data(), U.data(), V.data());
+          double normsq = 0;
+          for (double v : sv[jb]) normsq += v * v;
+          rk[jb] = normsq == 0.0 ? 0 : truncation_rank(sv[jb].data(), q, (o.tol * o.tol / 2) * normsq);
+          vr[jb] = V;
+        }
+        std::vector<double> Wm;
+        std::vector<int64_t> woff(nj), uoff(nj);
+        int64_t utot = 0;
+        for (int64_t jb = 0; jb < nj; ++jb) {
+          woff[jb] = (int64_t)Wm.size();
+          for (int k = 0; k < rk[jb]; ++k)
+            for (int c = 0; c < q; ++c) Wm.push_back(vr[jb][(size_t)k * q + c] / sv[jb][k]);
+          uoff[jb] = utot;
+          utot += (int64_t)m->nstore[b0 + jb].ns * m->nstore[b0 + jb].nt * rk[jb];
+        }
+        std::vector<double> Ubuf((size_t)utot);
+        gen->near_factors(jobs, q, Wm, woff, rk, uoff, utot, Ubuf.data());
+        for (int64_t jb = 0; jb < nj; ++jb) {
+          const int64_t Ne = (int64_t)m->nstore[b0 + jb].ns * m->nstore[b0 + jb].nt;
+          const int r = rk[jb];
+          Tucker& tk = ntuck[b0 + jb];
+          tk.ranks = {r, r};
+          tk.sweeps = sweeps[jb];
+          tk.factors.clear();
+          tk.factors.emplace_back(Ubuf.begin() + uoff[jb], Ubuf.begin() + uoff[jb] + Ne * r);
+          tk.factors.emplace_back(vr[jb].begin(), vr[jb].begin() + (size_t)q * r);
+          tk.core.assign((size_t)r * r, 0.0);
+          for (int k = 0; k < r; ++k) tk.core[(size_t)k * r + k] = sv[jb][k];
+        }
+      } else {
+        std::vector<double> buf((size_t)tot);
+        gen->near(jobs, q, buf.data(), tot);
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
+        for (int64_t bi = b0; bi < b1; ++bi) near_one(bi, buf.data() + jobs[bi - b0].off);
+      }
+      b0 = b1;
+    }
   }
   for (const Tucker& tk : ntuck) m->svd_sweeps_max = std::max(m->svd_sweeps_max, tk.sweeps);
   if (m->svd_sweeps_max > JACOBI_MAX_SWEEPS)

@@ -731,6 +731,15 @@ int ph_offline_compress(const ph_tree* t, const ph_offline_opts* opts, void* str
   });
 }
 
+int ph_offline_compress_gpu(const ph_tree* t, const ph_offline_opts* opts, void* stream, ph_model** out) {
+  return guarded([&] {
+    need(t && t->p && opts && out, "NULL argument");
+    auto hm = ph::offline_host(*t->p, *opts, true);
+    auto dm = ph::upload_model(t->p, *hm, (hipStream_t)stream);
+    *out = new ph_model{dm};
+  });
+}
+
 int ph_offline_compress_h(const ph_tree* t, const ph_offline_opts* opts, void* stream, ph_model** out) {
   return guarded([&] {
     need(t && t->p && opts && out, "NULL argument");

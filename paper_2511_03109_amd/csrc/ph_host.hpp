@@ -107,7 +107,39 @@ struct HostModel {
   std::vector<double> hS, hT;
 };
 
-std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts& o);
+// gpu: the kernel tensors (near blocks and far classes) are evaluated on the GPU
+// (k_offline.hip) and compressed on the host
+std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts& o, bool gpu = false);
+
+// GPU kernel-tensor generation for the offline stage (k_offline.hip).  A near job is one stored
+// near block: out[off + kk Ne + j ns + i] = kappa(x_{s_begin + i}, x_{t_begin + j}; grid[kk]),
+// Ne = ns nt.  A far job is one stored class: out[off + i + P (kk + q j)] = kappa(a_i, b_j;
+// grid[kk]) with a, b the class's P Chebyshev nodes (P x d each, in nodes[job * 2 P d ...]).
+// The generator keeps the tree points, the theta grid and the Bessel orders on the device.
+struct NearJob {
+  int64_t s_begin, t_begin, off;
+  int32_t ns, nt;
+};
+class GpuTensorGen {
+ public:
+  GpuTensorGen(const TreeData& t, ph_kernel kernel, const double* grid, int q);
+  ~GpuTensorGen();
+  // near tensors of the jobs into host memory out (total entries), synchronous
+  void near(const std::vector<NearJob>& jobs, int q, double* out, int64_t total);
+  // far tensors of n_cls classes (P x q x P each, consecutive) into host memory out
+  void far(const std::vector<double>& nodes, int n_cls, int P, double* out);
+  // near tensors of the jobs generated on the device (kept for near_factors) and the R factor
+  // of a Householder QR of each (q x q column-major, per job) into host memory R; q <= 16
+  void near_qr(const std::vector<NearJob>& jobs, int q, int64_t total, double* R);
+  // U_job = A_job W_job (Ne x rk[job], W q x rk column-major at woff[job]) for the tensors of the
+  // last near_qr, column-major into host memory out at uoff[job] (utotal entries)
+  void near_factors(const std::vector<NearJob>& jobs, int q, const std::vector<double>& W,
+                    const std::vector<int64_t>& woff, const std::vector<int32_t>& rk,
+                    const std::vector<int64_t>& uoff, int64_t utotal, double* out);
+ private:
+  struct Impl;
+  Impl* p_;
+};
 // The far factors of the parametric H-matrix format from the class factors of offline_host
 // (offline_h.cpp); sets m.hformat.
 void hmatrix_far_host(const TreeData& t, HostModel& m, int num_threads);
@@ -115,9 +147,12 @@ void hmatrix_far_host(const TreeData& t, HostModel& m, int num_threads);
 // kernel value kappa(x, y; theta) on the host
 double kernel_value(ph_kernel k, int d, const double* x, const double* y, const double* th);
 int kernel_dtheta(ph_kernel k, int d);
-// e^x K_nu(x) (modified Bessel function of the second kind, nu >= 0, x > 0) and the Matern
-// kernel 2^(1 - nu) / Gamma(nu) z^nu K_nu(z), z = sqrt(2 nu) r / lambda (special.cpp)
+// e^x K_nu(x) (modified Bessel function of the second kind, nu >= 0, x > 0), the Matern
+// kernel 2^(1 - nu) / Gamma(nu) z^nu K_nu(z), z = sqrt(2 nu) r / lambda, and the order
+// constants of K_nu (special.cpp; the evaluation itself is kernel_fn.hpp)
+struct BesselOrder;
 double bessel_k_scaled(double nu, double x);
 double matern_value(double r, double lambda, double nu);
+BesselOrder bessel_order(double nu);
 
 }  // namespace ph

@@ -318,6 +318,47 @@ def test_hmatrix_variant(case):
     assert e.value.code == _lib.PH_EUNSUPPORTED
 
 
+@pytest.mark.parametrize("case", ["gauss2d", "matern32_3d", "matern_nu_2d"])
+def test_gpu_offline_stage(case):
+    """ph_offline_compress_gpu (kernel tensors evaluated on the GPU, compressed on the host):
+    ranks equal to the oracle's, near blocks, couplings and the MVM against the oracle at the FP64
+    tolerance, and the MVM equal to that of the host-built model to 1e-13 (the two evaluate the
+    kernel with the same code and differ by the rounding of exp / log / sqrt)."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    if case == "gauss2d":
+        X, args, th = inputs.points_for(1, 2500), ("gaussian", [0.05], [0.5], 6, 9, 1e-8, 3, (2, 1)), [0.17]
+    elif case == "matern32_3d":
+        X, args, th = inputs.points_for(2, 3000), ("matern32", [0.05], [0.5], 5, 11, 1e-8, 2, (3, 1)), [0.29]
+    else:
+        X, args, th = inputs.points_for(1, 2000), ("matern", [0.25, 0.5], [1.0, 3.0], 6, 7, 1e-8, 3, (2, 1)), [0.33, 2.2]
+    kernel, lo, hi, p_s, p_theta, tol, l_max, eta2 = args
+    lt = api.Tree(X, l_max=l_max, eta2=eta2)
+    lg = api.Model(lt, kernel, lo, hi, p_s=p_s, p_theta=p_theta, tol=tol, offline="gpu")
+    lh = api.Model(lt, kernel, lo, hi, p_s=p_s, p_theta=p_theta, tol=tol)
+    om = hmat.PH2(X, l_max=l_max, eta2=Fraction(*eta2), kernel=kernels.KERNELS[kernel][0], theta_lo=lo,
+                  theta_hi=hi, p_s=p_s, p_theta=p_theta, tol=tol)
+    _check_ranks(lg, om)
+    assert lg.info["kernel_evals"] == lh.info["kernel_evals"]
+    ig, ih = api.Instance(lg, th), api.Instance(lh, th)
+    oi = om.instantiate(th)
+    sizes = [len(om.tree.idx[s_]) for s_ in om.tree.leaves]
+    Dg = np.concatenate([ig.near_block(b).ravel() for b in range(len(om.near))])
+    _close(Dg, np.concatenate([oi["D"][b].ravel() for b in range(len(om.near))]), what="gpu offline near blocks",
+           max_entries=max(sizes) ** 2)
+    Cg = np.stack([ig.coupling(c) for c in range(len(om.classes))])
+    _close(Cg, np.stack([oi["C"][c] for c in range(len(om.classes))]), what="gpu offline couplings")
+    n = X.shape[0]
+    x = inputs.normal_vectors(n, 4, 13)
+    xd = torch.tensor(np.ascontiguousarray(x.T), device="cuda")
+    yg = ig.matvec(xd).cpu().numpy().T
+    yh = ih.matvec(xd).cpu().numpy().T
+    _close(yg, om.matvec(oi, x), what="gpu offline mvm", max_entries=max(sizes) ** 2)
+    err = np.linalg.norm(yg - yh) / np.linalg.norm(yh)
+    print(f"[parity] gpu offline vs host offline mvm: {err:.3e}", flush=True)
+    assert err <= 1e-13
+
+
 def test_multi_theta_slots_and_alpha_beta():
     torch = _torch()
     from paper_2511_03109_amd import api

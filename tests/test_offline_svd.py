@@ -32,7 +32,8 @@ def harness(tmp_path_factory):
     out = str(tmp_path_factory.mktemp("harness") / "offline_harness.so")
     cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
            "-I" + os.path.join(ROOT, "include"), os.path.join(HERE, "host_harness", "offline_harness.cpp"),
-           os.path.join(ROOT, "paper_2511_03109_amd", "csrc", "special.cpp"), "-o", out]
+           os.path.join(ROOT, "paper_2511_03109_amd", "csrc", "special.cpp"),
+           os.path.join(HERE, "host_harness", "gpu_stub.cpp"), "-o", out]
     subprocess.run(cmd, check=True, capture_output=True)
     lib = C.CDLL(out)
     dp = C.POINTER(C.c_double)
