@@ -21,7 +21,10 @@ tree     Cluster tree (Alg. ConstructClusterTree), block cluster tree
          (Alg. ConstructBlockClusterTree, admissibility eq. in Sec. 3.3 with
          the distance/diameter of App. "Additional definitions"), and
          translation classes (Sec. 5.2).
-tucker   Truncated higher-order SVD (the compression used in place of TT-cross).
+tucker   Truncated higher-order SVD (the default compression).
+tt       TT-cross with partially pivoted ACA, TT-rounding, the conversion of the
+         cores into spatial factors and a parameter core, and the core-by-core
+         coupling of Alg. "Modified H^2-Matrix MVM" (Sec. 2.1, App. PTTK review).
 hmat     Offline stage (Alg. "Offline Stage: Parametric H^2"), online stage
          (Alg. "Online Stage"; PTTK online), H^2 MVM (Alg. "H^2-matrix MVM"
          with FastForward / FastBackward), derivative, dense assembly, the
@@ -33,4 +36,4 @@ Parity status: every function is pinned by a ``-m "not gpu"`` test under
 polynomial exactness, node reproduction, the paper's printed NF ratios).
 """
 
-from . import cheb, kernels, tree, tucker, hmat  # noqa: F401
+from . import cheb, kernels, tree, tucker, tt, hmat  # noqa: F401

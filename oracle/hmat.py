@@ -26,7 +26,12 @@ Paper passages followed:
   ``instantiate_h``, ``matvec_h``), sharing the near field and the far tensors.
 
 Compression is the truncated HOSVD of ``oracle.tucker`` (see there for the reading
-of the tolerance).  The nugget of a regularised system is not part of kappa; it
+of the tolerance), or with ``compress="tt"`` TT-cross followed by TT-rounding
+(``oracle.tt``; Sec. 2.1), whose cores are converted exactly into the same form
+(spatial factors L, R, U_e and a parameter core with identity parameter factors).
+TT-cross is not symmetric in the mode order, so in that mode a far class whose
+offset is lexicographically below its negative takes the transposed factors of its
+mirror class, and a near block (s, t) with s > t the transpose of block (t, s).  The nugget of a regularised system is not part of kappa; it
 is added in the MVM as nugget * x.
 """
 
@@ -34,6 +39,7 @@ import numpy as np
 
 from . import cheb
 from . import tree as tr
+from . import tt as ttm
 from . import tucker
 
 
@@ -41,7 +47,7 @@ class PH2:
     """Offline data of a parametric H^2-matrix, with compression done lazily per tensor."""
 
     def __init__(self, X, *, l_max, eta2, kernel, theta_lo, theta_hi, p_s, p_theta, tol,
-                 box=(0.0, 1.0), dedup=True):
+                 box=(0.0, 1.0), dedup=True, compress="tucker"):
         self.X = np.asarray(X, dtype=np.float64)
         self.n, self.d = self.X.shape
         self.kernel = kernel
@@ -53,6 +59,11 @@ class PH2:
         self.P = self.p_s ** self.d
         self.tol = float(tol)
         self.dedup = dedup
+        if compress not in ("tucker", "tt"):
+            raise ValueError("compress must be 'tucker' or 'tt'")
+        self.compress = compress
+        self.tt_evals = 0         # distinct tensor entries evaluated by TT-cross
+        self._far_tt = {}         # raw TT cores per compressed far key
         # offline stage, first line: cluster tree and block cluster tree
         self.tree = tr.build_cluster_tree(self.X, box[0], box[1], l_max)
         self.near, self.far = tr.build_block_tree(self.tree, eta2)
@@ -136,20 +147,76 @@ class PH2:
         return self.block_class[bi] if self.dedup else bi
 
     def far_factors(self, key):
-        """T-HOSVD of the far tensor of a class (dedup) or of a far block: (core, [L, Θ_1.., R])."""
+        """Compressed far tensor of a class (dedup) or of a far block: (core, [L, Θ_1.., R]).
+        T-HOSVD, or TT-cross + TT-rounding converted to the same form (``compress="tt"``)."""
         if key not in self._far:
-            bi = self.class_rep[key] if self.dedup else key
-            core, facs, _ = tucker.thosvd(self.far_tensor_of_block(bi), self.tol)
-            self._far[key] = (core, facs)
+            if self.compress == "tt":
+                mk = self._mirror_key(key)
+                if mk is not None:
+                    core, facs = self.far_factors(mk)
+                    # M_mirror[i, k, j] = M[j, k, i]: swap the spatial factors and core modes
+                    self._far[key] = (np.moveaxis(np.moveaxis(core, 0, -1), -2, 0), [facs[-1]] + facs[1:-1] + [facs[0]])
+                else:
+                    cores = self._tt_far(key)
+                    self._far[key] = ttm.far_factors(cores, self.d, self.d_theta)
+            else:
+                bi = self.class_rep[key] if self.dedup else key
+                core, facs, _ = tucker.thosvd(self.far_tensor_of_block(bi), self.tol)
+                self._far[key] = (core, facs)
         return self._far[key]
 
+    def _mirror_key(self, key):
+        """TT mode: the class whose factors this one transposes (its offset is below its
+        negative and that class exists), else None."""
+        if not self.dedup:
+            return None
+        lev, o = self.classes[key]
+        neg = tuple(-c for c in o)
+        if tuple(o) < neg and (lev, neg) in self._class_index():
+            return self._class_index()[(lev, neg)]
+        return None
+
+    def _class_index(self):
+        if not hasattr(self, "_cidx"):
+            self._cidx = {k: i for i, k in enumerate(self.classes)}
+        return self._cidx
+
+    def _tt_far(self, key):
+        """TT-cross + TT-rounding of the far tensor of ``key`` with modes
+        (i_1..i_d, k_1..k_dθ, j_1..j_d) (Sec. 2.1; App. PTTK review)."""
+        if key not in self._far_tt:
+            bi = self.class_rep[key] if self.dedup else key
+            M = self.far_tensor_of_block(bi)                    # (P, p.., P), nodes little-endian
+            p, d, dth = self.p_s, self.d, self.d_theta
+            Mm = M.reshape((p,) * d + M.shape[1:1 + dth] + (p,) * d, order="F")
+            dims = list(Mm.shape)
+            cores, ev = ttm.tt_compress(lambda idx: Mm[tuple(idx.T)], dims, self.tol)
+            self.tt_evals += ev
+            self._far_tt[key] = cores
+        return self._far_tt[key]
+
+    def far_tt_cores(self, key):
+        """Raw TT cores of a far key that is compressed itself (not a mirror)."""
+        return self._tt_far(key)
+
     def near_factors(self, bi):
-        """T-HOSVD of the near tensor A_b of near block bi: (core, [U_e, Θ_1..])."""
+        """Compressed near tensor A_b of near block bi: (core, [U_e, Θ_1..])."""
         if bi not in self._near:
             s, u = self.near[bi]
-            core, facs, _ = tucker.thosvd(self.near_tensor(s, u), self.tol)
-            self._near[bi] = (core, facs)
+            A = self.near_tensor(s, u)
+            if self.compress == "tt":
+                cores, ev = ttm.tt_compress(lambda idx: A[tuple(idx.T)], list(A.shape), self.tol)
+                self.tt_evals += ev
+                self._near[bi] = ttm.near_factors(cores, self.d_theta)
+            else:
+                core, facs, _ = tucker.thosvd(A, self.tol)
+                self._near[bi] = (core, facs)
         return self._near[bi]
+
+    def _near_index(self):
+        if not hasattr(self, "_nidx"):
+            self._nidx = {tuple(b): i for i, b in enumerate(self.near)}
+        return self._nidx
 
     # ---------------------------------------------------------------- online stage
     def theta_vectors(self, theta, deriv_dim=None):
@@ -169,6 +236,9 @@ class PH2:
 
     def near_block(self, bi, vs):
         """D_b(theta) = reshape(U_e c_b, [n_s, n_t]) column-major, c_b = core x_θ (Θ_i^T v_i) (Sec. 4.3)."""
+        s, u = self.near[bi]
+        if self.compress == "tt" and s > u:
+            return self.near_block(self._near_index()[(u, s)], vs).T
         core, facs = self.near_factors(bi)
         c = core
         for i in range(self.d_theta):
