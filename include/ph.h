@@ -85,8 +85,12 @@ int ph_kernel_eval(ph_kernel kernel, int d, const double* x, const double* y, in
  *                 C_b(theta) = L H(theta) R^T per far block (Def. "Parametric H²-matrix")
  *   PH_FORMAT_H   parametric H-matrix: explicit factors S_b = U_s L_b, T_b = U_t R_b per far
  *                 block and the far core H_b(theta) (Def. "Parametric H-matrix"; App. PTTK
- *                 offline phase 3); MVM by Alg. "H-matrix MVM" with the parametric far field */
-typedef enum { PH_FORMAT_H2 = 0, PH_FORMAT_H = 1 } ph_format;
+ *                 offline phase 3); MVM by Alg. "H-matrix MVM" with the parametric far field
+ *   PH_FORMAT_H2_IMPLICIT  parametric H²-matrix whose couplings stay factored: the online stage
+ *                 forms H_q(theta) per stored class only, and the MVM applies
+ *                 y_hat_s += L_q (H_q(theta) (R_q^T x_hat_t)) per far block (Alg. "Modified
+ *                 H²-Matrix MVM"); from ph_offline_compress_tt with PH_COUPLING_IMPLICIT */
+typedef enum { PH_FORMAT_H2 = 0, PH_FORMAT_H = 1, PH_FORMAT_H2_IMPLICIT = 2 } ph_format;
 
 /* Arithmetic of an instance.  PH_F64: FP64 storage and arithmetic, I/O in double.
  * PH_F32: FP32 storage of the instantiated blocks, FP32 arithmetic (matrix cores with
@@ -223,6 +227,24 @@ int ph_offline_compress_gpu(const ph_tree* t, const ph_offline_opts* opts, void*
  * H_q(theta) per stored class, ph_matvec applies S_b H_b T_b^T per far block.  Errors as
  * ph_offline_compress.  *out is owned by the caller (ph_model_free). */
 int ph_offline_compress_h(const ph_tree* t, const ph_offline_opts* opts, void* stream, ph_model** out);
+
+/* Offline stage with the paper's own compression (Sec. 2.1 "Tensor Train Decomposition";
+ * Sec. 4.2 / App. PTTK review for the far tensors, Sec. 4.3 for the near tensors): every far
+ * tensor M[i_1..i_d, k_1.., j_1..j_d] and near tensor A_b[e, k_1..] is approximated by TT-cross
+ * (partially pivoted ACA on each supercore, started from the middle index of every mode,
+ * alternating sweeps, a max-norm error check on 256 SplitMix64-sampled entries with enrichment
+ * of the index sets) at tol / 10 and then TT-rounded at tol; entries are evaluated on demand,
+ * each at most once (ph_model_info.kernel_evals counts them).  The cores are converted exactly
+ * into the online form: L_q from the target-side spatial cores, R_q from the source-side ones,
+ * the parameter cores as the core of H_q(theta) with identity parameter factors (ranks
+ * reported as (r_d, p_theta [, p_theta], r_{d+d_theta})), and U_e = G_1 for the near field.
+ * Host only (num_threads threads).  coupling:
+ *   PH_COUPLING_MATERIALIZED  format PH_FORMAT_H2: C_q(theta) is formed per class online
+ *   PH_COUPLING_IMPLICIT      format PH_FORMAT_H2_IMPLICIT (PH_F64 instances only)
+ * Errors as ph_offline_compress; PH_EINVAL for another coupling value. */
+typedef enum { PH_COUPLING_MATERIALIZED = 0, PH_COUPLING_IMPLICIT = 1 } ph_coupling;
+int ph_offline_compress_tt(const ph_tree* t, const ph_offline_opts* opts, int coupling, void* stream,
+                           ph_model** out);
 
 /* The hierarchical format of a model (ph_format). */
 int ph_model_format(const ph_model* m, int* format);
@@ -404,7 +426,8 @@ void ph_graph_free(ph_graph* g);
  * slot t (n_s x n_t column-major, as double; for a factored instance the block is formed
  * by a kernel in the arithmetic of the MVM) or the coupling matrix of class c (P x P
  * column-major, as double) to host memory.  Synchronises the device.  A parametric H-matrix
- * instance forms no coupling matrices: ph_inst_coupling returns PH_EUNSUPPORTED for it. */
+ * instance and an implicit-coupling instance form no coupling matrices: ph_inst_coupling
+ * returns PH_EUNSUPPORTED for them. */
 int ph_inst_near_block(const ph_inst* k, int t, int64_t b, double* host_out);
 int ph_inst_coupling(const ph_inst* k, int t, int64_t c, double* host_out);
 

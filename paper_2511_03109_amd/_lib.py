@@ -11,7 +11,8 @@ KERNELS = {"gaussian": 0, "matern32": 1, "matern12": 2, "aniso_gaussian": 3, "po
            "poly2_test": 5, "matern": 6}
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2}
 NEAR_MODES = {"auto": 0, "blocks": 1, "factored": 2}
-FORMATS = {"h2": 0, "h": 1}
+FORMATS = {"h2": 0, "h": 1, "h2_implicit": 2}
+COUPLINGS = {"materialized": 0, "implicit": 1}
 
 
 class TreeOpts(C.Structure):
@@ -77,6 +78,7 @@ SIGNATURES = {
     "ph_offline_compress": ([_P, C.POINTER(OfflineOpts), _P, C.POINTER(_P)], C.c_int),
     "ph_offline_compress_h": ([_P, C.POINTER(OfflineOpts), _P, C.POINTER(_P)], C.c_int),
     "ph_offline_compress_gpu": ([_P, C.POINTER(OfflineOpts), _P, C.POINTER(_P)], C.c_int),
+    "ph_offline_compress_tt": ([_P, C.POINTER(OfflineOpts), C.c_int, _P, C.POINTER(_P)], C.c_int),
     "ph_model_format": ([_P, C.POINTER(C.c_int)], C.c_int),
     "ph_model_info_get": ([_P, C.POINTER(ModelInfo)], C.c_int),
     "ph_model_near_ranks": ([_P, _I32P], C.c_int),

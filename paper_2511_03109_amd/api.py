@@ -83,11 +83,13 @@ class Tree:
 
 class Model:
     """Offline stage output on the device: ph_offline_compress (format "h2", the parametric
-    H^2-matrix), ph_offline_compress_h (format "h", the parametric H-matrix), or
-    ph_offline_compress_gpu (offline="gpu": kernel tensors evaluated on the GPU)."""
+    H^2-matrix), ph_offline_compress_h (format "h", the parametric H-matrix),
+    ph_offline_compress_gpu (offline="gpu": kernel tensors evaluated on the GPU), or
+    ph_offline_compress_tt (compress="tt": TT-cross + TT-rounding; coupling="implicit" gives
+    the format "h2_implicit")."""
 
     def __init__(self, tree, kernel, theta_lo, theta_hi, *, p_s, p_theta, tol, num_threads=0,
-                 stream=None, format="h2", offline="host"):
+                 stream=None, format="h2", offline="host", compress="hosvd", coupling="materialized"):
         lo = np.atleast_1d(np.asarray(theta_lo, dtype=np.float64))
         hi = np.atleast_1d(np.asarray(theta_hi, dtype=np.float64))
         opts = L.OfflineOpts()
@@ -103,7 +105,18 @@ class Model:
         entry = {"h2": "ph_offline_compress", "h": "ph_offline_compress_h"}[format]
         if offline == "gpu":
             entry = "ph_offline_compress_gpu"
-        L.check(getattr(L.lib(), entry)(tree._h, C.byref(opts), _stream(stream), C.byref(h)), entry)
+        if compress not in ("hosvd", "tt") or coupling not in L.COUPLINGS:
+            raise ValueError('compress must be "hosvd" or "tt", coupling "materialized" or "implicit"')
+        if compress == "tt":
+            if format != "h2" or offline != "host":
+                raise ValueError('compress="tt" builds the H^2 format on the host')
+            entry = "ph_offline_compress_tt"
+            L.check(L.lib().ph_offline_compress_tt(tree._h, C.byref(opts), L.COUPLINGS[coupling], _stream(stream),
+                                                   C.byref(h)), entry)
+        elif coupling != "materialized":
+            raise ValueError('coupling="implicit" needs compress="tt"')
+        else:
+            L.check(getattr(L.lib(), entry)(tree._h, C.byref(opts), _stream(stream), C.byref(h)), entry)
         self._h = h
         fmt = C.c_int()
         L.check(L.lib().ph_model_format(h, C.byref(fmt)), "ph_model_format")

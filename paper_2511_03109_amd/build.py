@@ -15,7 +15,7 @@ OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libph.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HOST_SOURCES = ["tree.cpp", "offline.cpp", "special.cpp"]
+HOST_SOURCES = ["tree.cpp", "offline.cpp", "special.cpp", "tt.cpp"]
 HIP_SOURCES = ["ph_api.hip", "k_instantiate.hip", "k_matvec.hip", "k_near_fused.hip", "k_coupling_bf16.hip", "k_hmatrix.hip", "k_offline.hip", "k_solve.hip"]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

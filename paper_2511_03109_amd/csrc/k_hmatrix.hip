@@ -144,7 +144,9 @@ __global__ void __launch_bounds__(NT) k_h_proj(const double* __restrict__ xt, do
 // (leaf, 128-row chunk) item, one RHS tile and the slots t0 .. t0 + HTB - 1.  Thread (g, c) owns
 // rows g, g + 16, ... of the chunk and RHS column c of every slot; HCH columns of S_b (the chunk's
 // rows) and the matching rows of w_b of every slot go through LDS per step, so S_b is read once
-// for all HTB slots.
+// for all HTB slots.  ADD: the sum is added to yt; else it is written (an item with no blocks
+// then writes zeros).
+template <bool ADD>
 __global__ void __launch_bounds__(NT) k_h_apply(double* __restrict__ yt, const double* __restrict__ W,
                                                 const HBlkDev* __restrict__ blks, const double* __restrict__ hS,
                                                 const int32_t* __restrict__ leaf_ptr,
@@ -205,7 +207,10 @@ __global__ void __launch_bounds__(NT) k_h_apply(double* __restrict__ yt, const d
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int r = g + 16 * j;
-      if (r < cn) y[(int64_t)r * Rs] += acc[s][j];
+      if (r < cn) {
+        if (ADD) y[(int64_t)r * Rs] += acc[s][j];
+        else y[(int64_t)r * Rs] = acc[s][j];
+      }
     }
   }
 }
@@ -229,10 +234,31 @@ void h_far_launch(const InstData& in, const double* xt, double* yt, double* W, i
            (const HBlkDev*)m.hblk.p, (const double*)m.hT.p, (const double*)in.C.p, m.h_tot, m.hw_tot, m.n, Rs,
            (int)nrc, in.T);
   else
-    launch(PH_STAGE_LEAF_DOWN, k_h_apply, dim3((unsigned)m.n_mvm_items, (unsigned)nrc, nb), dim3(NT), st, yt,
+    launch(PH_STAGE_LEAF_DOWN, k_h_apply<true>, dim3((unsigned)m.n_mvm_items, (unsigned)nrc, nb), dim3(NT), st, yt,
            (const double*)W, (const HBlkDev*)m.hblk.p, (const double*)m.hS.p, (const int32_t*)m.hl_ptr.p,
            (const int32_t*)m.hl_blk.p, (const int64_t*)m.nbegin.p, (const int64_t*)m.nend.p,
            (const int32_t*)m.mvm_items.p, m.tree->leaves.front(), m.hw_tot, m.n, Rs, (int)nrc, in.T);
+}
+
+// Alg. "Modified H^2-Matrix MVM", multiplication stage with the couplings kept as factors: the
+// far blocks are the H-matrix kernels' blocks over the index space of x_hat (node s, entry i at
+// row s Pp + i): w_b = H_q(theta) R_q^T x_hat_t, then y_hat_s = sum_b L_q w_b per node (written,
+// so nodes of the far levels without far blocks get zeros for the downward pass).
+void implicit_coupling_launch(const InstData& in, const double* xh, double* yh, double* W, int64_t Rs,
+                              int64_t nrc, hipStream_t st) {
+  const DeviceModel& m = *in.m;
+  if (in.T > 65535 || nrc > 65535) fail(PH_EUNSUPPORTED, "ph_matvec: too many parameter slots or RHS tiles");
+  const unsigned nb = (unsigned)((in.T + HTB - 1) / HTB);
+  const int64_t rows = m.n_nodes * m.Pp;
+  if (m.n_hblk > 0)
+    launch(PH_STAGE_COUPLING, k_h_proj, dim3((unsigned)m.n_hblk, (unsigned)nrc, nb), dim3(NT), st, xh, W,
+           (const HBlkDev*)m.hblk.p, (const double*)m.hS.p, (const double*)in.C.p, m.h_tot, m.hw_tot, rows, Rs,
+           (int)nrc, in.T);
+  if (m.n_hx_items > 0)
+    launch(PH_STAGE_COUPLING, k_h_apply<false>, dim3((unsigned)m.n_hx_items, (unsigned)nrc, nb), dim3(NT), st, yh,
+           (const double*)W, (const HBlkDev*)m.hblk.p, (const double*)m.hS.p, (const int32_t*)m.hl_ptr.p,
+           (const int32_t*)m.hl_blk.p, (const int64_t*)m.hx_nbegin.p, (const int64_t*)m.hx_nend.p,
+           (const int32_t*)m.hx_items.p, (int32_t)0, m.hw_tot, rows, Rs, (int)nrc, in.T);
 }
 
 }  // namespace ph

@@ -254,8 +254,9 @@ void instantiate_impl(InstData& in, const double* theta, hipStream_t st) {
          box, in.v.p, in.T, m.d_theta, m.p_theta, in.grad_dim);
   const int64_t Cps = m.n_classes * m.Pp * m.Pp;
   const int nMt = m.Pp / 16;
-  if (m.format == PH_FORMAT_H) {
-    h_core_launch(in, st);   // far cores H_q(theta_t) of the parametric H-matrix format
+  if (m.format != PH_FORMAT_H2) {
+    // far cores H_q(theta_t) of the parametric H-matrix format and of the implicit coupling
+    h_core_launch(in, st);
   } else {
     constexpr int FT = 4;
     launch(PH_STAGE_FAR_INST, k_far_instantiate<S, FT>, dim3((unsigned)((nMt * nMt + FT - 1) / FT),

@@ -906,7 +906,12 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
   const bool hfmt = m.format == PH_FORMAT_H;
   const bool use_far = m.min_far >= 0 && !hfmt;
   const bool use_hfar = hfmt && m.n_hblk > 0;
-  if (hfmt && sizeof(S) != sizeof(double)) fail(PH_EUNSUPPORTED, "ph_matvec: H-matrix models are FP64 only");
+  // implicit coupling (Alg. "Modified H^2-Matrix MVM"): the H^2 chain with L_q H_q R_q^T
+  // applied per far block instead of the formed C
+  const bool imp = m.format == PH_FORMAT_H2_IMPLICIT && use_far;
+  const bool need_w = use_hfar || imp;
+  if (m.format != PH_FORMAT_H2 && sizeof(S) != sizeof(double))
+    fail(PH_EUNSUPPORTED, "ph_matvec: H-matrix and implicit-coupling models are FP64 only");
   // class-list chunks per target box: 8 (one per XCD) unless the lists are too short;
   // PH_COUPLING_CHUNKS overrides (tuning)
   // launch configuration: environment override (tuning sweeps), else ph_autotune's
@@ -929,6 +934,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     const int g = std::atoi(env);
     if (g >= 1 && g <= 64 && (g & (g - 1)) == 0) G = g;
   }
+  if (imp) G = 1;   // the implicit coupling writes y_hat directly
   // PH_SERIAL_MVM=1 runs the near field on the caller's stream (no overlap; profiling)
   bool serial = in.tune_overlap != 1;   // default: one stream (sharing the GPU measured no gain)
   if (const char* env = std::getenv("PH_SERIAL_MVM")) serial = std::atoi(env) != 0;
@@ -959,7 +965,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     if (G > 1) partp = carve((size_t)G * T * m.n_nodes * m.Pp * Rs * sizeof(S));
     if (need_zb) zbp = carve((size_t)T * m.Zt * sizeof(S));
     if (bf16_mc) xbp = carve((size_t)T * coupling_bf16_x_bytes(m, Rs));
-    if (use_hfar) hwp = (double*)carve((size_t)T * nrc * m.hw_tot * sizeof(double));
+    if (need_w) hwp = (double*)carve((size_t)T * nrc * m.hw_tot * sizeof(double));
     if (off > ext->bytes)
       fail(PH_EINVAL, "ph_matvec_noalloc: this MVM needs " + std::to_string(off) + " bytes of scratch, more than the " +
                           std::to_string(ext->bytes) + " the library reserves per GPU");
@@ -994,7 +1000,7 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
     }
     xbp = in.xb.p;
   }
-  if (use_hfar) {
+  if (need_w) {
     const size_t need = (size_t)T * nrc * m.hw_tot * sizeof(double);
     if (in.hw.n < need) {
       if (in.graphs > 0) fail(PH_ESTATE, "ph_matvec: the instance has recorded graphs, its scratch cannot grow");
@@ -1084,7 +1090,9 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
                (const int32_t*)m.ent_tau.p, (const int32_t*)m.chunk_first.p + m.chunk_off[ilog2(G)], m.Pp,
                m.n_nodes, Rs, G, Cps, part_stride, (int)ngr);
     };
-    if (bf16_mc) {
+    if (imp) {
+      implicit_coupling_launch(in, (const double*)xh, (double*)yh, hwp, Rs, nrc, st);
+    } else if (bf16_mc) {
       coupling_bf16_launch(in, (const float*)xh, xbp, (float*)cout, G, Rs, nrc, t.level_start[m.min_far], st);
     } else {
     // 8 waves (4 row groups x 2 target halves) for Pp > 64, else 4 waves over the targets;

@@ -55,6 +55,8 @@ void lagrange_all(const double* nodes, int p, double x, double* out) {
   }
 }
 
+}  // namespace
+
 // ---- dense linear algebra (column-major) ---------------------------------------------
 
 // Householder QR of the m x k matrix A (m >= k, leading dimension m), in place.
@@ -216,13 +218,6 @@ int truncation_rank(const double* s, int k, double thr) {
 
 // Left singular vectors (first r columns) and singular values of the m x q matrix X
 // given by an accessor that fills it column-major.  Chooses the tall orientation.
-struct LeftSV {
-  std::vector<double> U;  // m x kk, column-major, kk = min(m, q)
-  std::vector<double> s;  // kk
-  int64_t m = 0;
-  int kk = 0;
-  int sweeps = 0;   // Jacobi sweeps (JACOBI_MAX_SWEEPS + 1: not converged)
-};
 
 // X column-major m x q (leading dimension m).
 LeftSV left_sv(const double* X, int64_t m, int64_t q) {
@@ -260,6 +255,8 @@ LeftSV left_sv(const double* X, int64_t m, int64_t q) {
   }
   return out;
 }
+
+namespace {
 
 // Mode-m unfolding of a column-major tensor with dims n[0..N-1] (first index fastest),
 // written column-major as n[m] x (prod of the others).
@@ -333,6 +330,168 @@ Tucker thosvd(const std::vector<double>& T, const std::vector<int64_t>& n, doubl
   return out;
 }
 
+// TT of a far tensor (modes i_1..i_d, k_1..k_dth, j_1..j_d, each index little-endian) in the
+// form of the online stage (App. PTTK review): L = G_0 .. G_{d-1} contracted (P x r_d), R from
+// G_{d+dth} .. G_{N-1} (P x r_{d+dth}), identity parameter factors and the parameter cores as
+// core[a, k_1, (k_2,) b], so that H(theta) = core contracted with v_1 (and v_2).
+Tucker tt_far_tucker(const TensorTrain& t, int d, int dth) {
+  const int N = (int)t.cores.size();
+  Tucker out;
+  out.sweeps = t.sweeps;
+  // L: rows (i_1 .. i_k) little-endian
+  std::vector<double> L = t.cores[0];
+  int64_t rows = t.dims[0];
+  int rl = t.ranks[1];
+  for (int k = 1; k < d; ++k) {
+    const int m = t.dims[k], r1 = t.ranks[k + 1];
+    const std::vector<double>& G = t.cores[k];
+    std::vector<double> Ln((size_t)rows * m * r1, 0.0);
+    for (int b = 0; b < r1; ++b)
+      for (int i = 0; i < m; ++i)
+        for (int a = 0; a < rl; ++a) {
+          const double w = G[(size_t)a + (size_t)rl * (i + (size_t)m * b)];
+          const double* src = L.data() + (size_t)rows * a;
+          double* dst = Ln.data() + (size_t)rows * (i + (size_t)m * b);
+          for (int64_t q = 0; q < rows; ++q) dst[q] += src[q] * w;
+        }
+    L.swap(Ln);
+    rows *= m;
+    rl = r1;
+  }
+  // R: Y (r x (j_k .. j_d)) built from the last core backwards, then transposed
+  int rr = t.ranks[N - 1];
+  int64_t cols = t.dims[N - 1];
+  std::vector<double> Y = t.cores[N - 1];   // rr x m
+  for (int k = N - 2; k >= d + dth; --k) {
+    const int r0 = t.ranks[k], m = t.dims[k];
+    const std::vector<double>& G = t.cores[k];   // r0 x m x rr
+    std::vector<double> Yn((size_t)r0 * m * cols, 0.0);   // [a + r0 (j + m rest)]
+    for (int64_t c = 0; c < cols; ++c)
+      for (int q = 0; q < rr; ++q) {
+        const double y = Y[(size_t)q + (size_t)rr * c];
+        if (y == 0.0) continue;
+        for (int j = 0; j < m; ++j)
+          for (int a = 0; a < r0; ++a)
+            Yn[(size_t)a + (size_t)r0 * (j + (size_t)m * c)] += G[(size_t)a + (size_t)r0 * (j + (size_t)m * q)] * y;
+      }
+    Y.swap(Yn);
+    cols *= m;
+    rr = r0;
+  }
+  std::vector<double> R((size_t)cols * rr);
+  for (int b = 0; b < rr; ++b)
+    for (int64_t j = 0; j < cols; ++j) R[(size_t)j + (size_t)cols * b] = Y[(size_t)b + (size_t)rr * j];
+  const int pt = t.dims[d];
+  std::vector<double> core;
+  if (dth == 1) {
+    core = t.cores[d];
+  } else {
+    const int rm = t.ranks[d + 1];
+    const std::vector<double>& G1 = t.cores[d];       // rl x pt x rm
+    const std::vector<double>& G2 = t.cores[d + 1];   // rm x pt x rr
+    core.assign((size_t)rl * pt * pt * rr, 0.0);
+    for (int b = 0; b < rr; ++b)
+      for (int k2 = 0; k2 < pt; ++k2)
+        for (int c = 0; c < rm; ++c) {
+          const double g2 = G2[(size_t)c + (size_t)rm * (k2 + (size_t)pt * b)];
+          for (int k1 = 0; k1 < pt; ++k1)
+            for (int a = 0; a < rl; ++a)
+              core[(size_t)a + (size_t)rl * (k1 + (size_t)pt * (k2 + (size_t)pt * b))] +=
+                  G1[(size_t)a + (size_t)rl * (k1 + (size_t)pt * c)] * g2;
+        }
+  }
+  std::vector<double> I((size_t)pt * pt, 0.0);
+  for (int k = 0; k < pt; ++k) I[(size_t)k * pt + k] = 1.0;
+  out.ranks.push_back(rl);
+  out.factors.push_back(std::move(L));
+  for (int k = 0; k < dth; ++k) {
+    out.ranks.push_back(pt);
+    out.factors.push_back(I);
+  }
+  out.ranks.push_back(rr);
+  out.factors.push_back(std::move(R));
+  out.core = std::move(core);
+  return out;
+}
+
+// TT of a near tensor (modes e, k_1 (, k_2)) in the form of the online stage (Sec. 4.3):
+// U_e = G_0 (N_e x r_1), identity parameter factors, core[a, k_1 (, k_2)] from the parameter cores.
+Tucker tt_near_tucker(const TensorTrain& t, int dth) {
+  Tucker out;
+  out.sweeps = t.sweeps;
+  const int r1 = t.ranks[1], pt = t.dims[1];
+  std::vector<double> core;
+  if (dth == 1) {
+    core = t.cores[1];   // r1 x pt x 1
+  } else {
+    const int r2 = t.ranks[2];
+    const std::vector<double>& G1 = t.cores[1];   // r1 x pt x r2
+    const std::vector<double>& G2 = t.cores[2];   // r2 x pt x 1
+    core.assign((size_t)r1 * pt * pt, 0.0);
+    for (int k2 = 0; k2 < pt; ++k2)
+      for (int c = 0; c < r2; ++c) {
+        const double g2 = G2[(size_t)c + (size_t)r2 * k2];
+        for (int k1 = 0; k1 < pt; ++k1)
+          for (int a = 0; a < r1; ++a)
+            core[(size_t)a + (size_t)r1 * (k1 + (size_t)pt * k2)] += G1[(size_t)a + (size_t)r1 * (k1 + (size_t)pt * c)] * g2;
+      }
+  }
+  std::vector<double> I((size_t)pt * pt, 0.0);
+  for (int k = 0; k < pt; ++k) I[(size_t)k * pt + k] = 1.0;
+  out.ranks.push_back(r1);
+  out.factors.push_back(t.cores[0]);
+  for (int k = 0; k < dth; ++k) {
+    out.ranks.push_back(pt);
+    out.factors.push_back(I);
+  }
+  out.core = std::move(core);
+  return out;
+}
+
+// Entry accessors for the cross: kernel values at the Chebyshev nodes of a class (far) or at
+// the point pairs of a near block, evaluated on demand
+struct FarCtx {
+  ph_kernel kernel;
+  int d, dth, ps, P;
+  const double* ns;     // P x d target nodes
+  const double* nt;     // P x d source nodes
+  const double* grid;   // parameter nodes, 2 per grid point, k_1 fastest
+  int pt;
+};
+void far_entries(const void* c, const int32_t* idx, int64_t count, double* out) {
+  const FarCtx& f = *static_cast<const FarCtx*>(c);
+  const int N = 2 * f.d + f.dth;
+  for (int64_t s = 0; s < count; ++s) {
+    const int32_t* ix = idx + s * N;
+    int i = 0, j = 0, st = 1;
+    for (int k = 0; k < f.d; ++k) {
+      i += st * ix[k];
+      j += st * ix[f.d + f.dth + k];
+      st *= f.ps;
+    }
+    const int kk = ix[f.d] + (f.dth == 2 ? f.pt * ix[f.d + 1] : 0);
+    out[s] = kernel_value(f.kernel, f.d, &f.ns[(size_t)i * f.d], &f.nt[(size_t)j * f.d], &f.grid[2 * kk]);
+  }
+}
+struct NearCtx {
+  ph_kernel kernel;
+  int d, dth, pt;
+  int32_t ns;
+  const double* xs;     // points of the target cluster (tree order), ns x d
+  const double* xt;     // points of the source cluster
+  const double* grid;
+};
+void near_entries(const void* c, const int32_t* idx, int64_t count, double* out) {
+  const NearCtx& f = *static_cast<const NearCtx*>(c);
+  const int N = 1 + f.dth;
+  for (int64_t s = 0; s < count; ++s) {
+    const int32_t* ix = idx + s * N;
+    const int32_t i = ix[0] % f.ns, j = ix[0] / f.ns;
+    const int kk = ix[1] + (f.dth == 2 ? f.pt * ix[2] : 0);
+    out[s] = kernel_value(f.kernel, f.d, &f.xs[(size_t)i * f.d], &f.xt[(size_t)j * f.d], &f.grid[2 * kk]);
+  }
+}
+
 }  // namespace
 
 int kernel_dtheta(ph_kernel k, int d) {
@@ -356,7 +515,9 @@ double kernel_value(ph_kernel k, int d, const double* x, const double* y, const 
   return kernel_eval(k, d, x, y, th, BesselOrder{});
 }
 
-std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts& o, bool gpu) {
+std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts& o, bool gpu, Compress comp) {
+  const bool use_tt = comp == Compress::TT;
+  if (use_tt && gpu) fail(PH_EUNSUPPORTED, "ph_offline_compress: TT-cross runs on the host only");
   const int d = t.d;
   if (o.p_s < 1 || o.p_s > 16 || o.p_theta < 1 || o.p_theta > 16)
     fail(PH_EINVAL, "ph_offline_compress: p_s and p_theta must be in 1..16");
@@ -485,6 +646,16 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
   for (int64_t ci = 0; ci < nfc; ++ci) {
     const double* ns = cnodes.data() + (size_t)ci * 2 * P * d;
     const double* nt = ns + (size_t)P * d;
+    if (use_tt) {
+      FarCtx fc{o.kernel, d, dth, ps, P, ns, nt, grid.data(), pt};
+      std::vector<int> tdims(d, ps);
+      for (int k = 0; k < dth; ++k) tdims.push_back(pt);
+      for (int k = 0; k < d; ++k) tdims.push_back(ps);
+      TensorTrain tt = tt_compress(far_entries, &fc, tdims, o.tol);
+      evals_far += tt.evals;
+      ftuck[ci] = tt_far_tucker(tt, d, dth);
+      continue;
+    }
     std::vector<double> M((size_t)P * q * P);
     if (gpu) {
       std::memcpy(M.data(), Mall.data() + (size_t)ci * P * q * P, M.size() * sizeof(double));
@@ -585,11 +756,22 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
   }
   const int64_t nst = (int64_t)m->nstore.size();
   std::vector<Tucker> ntuck(nst);
+  std::vector<int64_t> near_evals(nst, -1);   // TT-cross: distinct entries evaluated per block
   int64_t evals_near = 0;
   // near tensor of stored block bi from src (GPU-generated) or evaluated here, then compressed
   auto near_one = [&](int64_t bi, const double* src) {
     const NearStored& b = m->nstore[bi];
     const int64_t Ne = (int64_t)b.ns * b.nt;
+    if (use_tt) {
+      NearCtx nc{o.kernel, d, dth, pt, b.ns, &t.pts_t[(size_t)b.s_begin * d], &t.pts_t[(size_t)b.t_begin * d],
+                 grid.data()};
+      std::vector<int> tdims{(int)Ne};
+      for (int k = 0; k < dth; ++k) tdims.push_back(pt);
+      TensorTrain tt = tt_compress(near_entries, &nc, tdims, o.tol);
+      near_evals[bi] = tt.evals;
+      ntuck[bi] = tt_near_tucker(tt, dth);
+      return;
+    }
     std::vector<double> A((size_t)Ne * q);
     if (src) {
       std::memcpy(A.data(), src, A.size() * sizeof(double));
@@ -607,7 +789,6 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
     else { dims.push_back(pt); dims.push_back(pt); }
     ntuck[bi] = thosvd(A, dims, o.tol);
   };
-  for (int64_t bi = 0; bi < nst; ++bi) evals_near += (int64_t)m->nstore[bi].ns * m->nstore[bi].nt * q;
   if (!gpu) {
 #pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
     for (int64_t bi = 0; bi < nst; ++bi) near_one(bi, nullptr);
@@ -680,6 +861,8 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
       b0 = b1;
     }
   }
+  for (int64_t bi = 0; bi < nst; ++bi)
+    evals_near += near_evals[bi] >= 0 ? near_evals[bi] : (int64_t)m->nstore[bi].ns * m->nstore[bi].nt * q;
   for (const Tucker& tk : ntuck) m->svd_sweeps_max = std::max(m->svd_sweeps_max, tk.sweeps);
   if (m->svd_sweeps_max > JACOBI_MAX_SWEEPS)
     fail(PH_EUNSUPPORTED, "ph_offline_compress: a one-sided Jacobi SVD was still rotating after " +

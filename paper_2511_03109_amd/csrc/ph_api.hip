@@ -73,6 +73,84 @@ static void upload_hmatrix(DeviceModel& m, const TreeData& t, const HostModel& h
                               m.hl_ptr.bytes() + m.hl_blk.bytes());
 }
 
+// The implicit coupling (Alg. "Modified H^2-Matrix MVM"): the H-matrix kernels' structures over
+// the index space of the coupling (row s Pp + i is entry i of x_hat_s / y_hat_s).  Far block
+// (s, t) of class c with stored class q: S_b = L_q, T_b = R_q, or (R_q, L_q) with H_q^T when c is
+// the mirror of q; per stored class its core; per node of the far levels its row range, work
+// item and far blocks.
+static void upload_implicit(DeviceModel& m, const TreeData& t, const HostModel& hm, hipStream_t st) {
+  m.format = PH_FORMAT_H2_IMPLICIT;
+  const int P = hm.P;
+  const int64_t Pp = m.Pp;
+  std::vector<HClsDev> hc(hm.cstore.size());
+  int64_t hoff = 0;
+  for (size_t q = 0; q < hm.cstore.size(); ++q) {
+    const ClassStored& c = hm.cstore[q];
+    hc[q] = HClsDev{c.core_off, c.th1_off, c.th2_off, hoff, c.rL, c.r1, c.r2, c.rR};
+    hoff += (int64_t)c.rL * c.rR;
+  }
+  m.h_tot = hoff;
+  const int64_t Roff = (int64_t)hm.ff_L.size();   // R factors follow the L factors in hS
+  std::vector<HBlkDev> hb;
+  int64_t woff = 0;
+  std::vector<std::vector<int32_t>> by_target(t.n_nodes());
+  for (int64_t b = 0; b < t.n_far(); ++b) {
+    const int32_t s = t.far[2 * b], u = t.far[2 * b + 1], c = t.far_class[b];
+    const int32_t q = hm.class_src[c], tr = hm.class_tr[c];
+    const ClassStored& cs = hm.cstore[q];
+    const int64_t Lo = cs.L_off, Ro = Roff + cs.R_off;
+    HBlkDev h{};
+    h.s_begin = (int64_t)s * Pp;
+    h.t_begin = (int64_t)u * Pp;
+    h.S_off = tr ? Ro : Lo;
+    h.T_off = tr ? Lo : Ro;
+    h.h_off = hc[q].h_off;
+    h.w_off = woff;
+    h.ns = P;
+    h.nt = P;
+    h.rs = tr ? cs.rR : cs.rL;
+    h.rt = tr ? cs.rL : cs.rR;
+    h.lds = P;
+    h.ldt = P;
+    h.tr = tr;
+    h.q = q;
+    woff += (int64_t)h.rs * 16;
+    by_target[s].push_back((int32_t)hb.size());
+    hb.push_back(h);
+  }
+  m.hw_tot = woff;
+  const int32_t a0 = t.level_start[t.min_far_level];
+  std::vector<int32_t> lptr{0}, lblk, items;
+  std::vector<int64_t> nb((size_t)t.n_nodes()), ne((size_t)t.n_nodes());
+  for (int32_t s = 0; s < (int32_t)t.n_nodes(); ++s) {
+    lblk.insert(lblk.end(), by_target[s].begin(), by_target[s].end());
+    lptr.push_back((int32_t)lblk.size());
+    nb[s] = (int64_t)s * Pp;
+    ne[s] = (int64_t)s * Pp + P;
+    if (s >= a0) {
+      items.push_back(s);
+      items.push_back(0);
+    }
+  }
+  std::vector<double> LR(hm.ff_L);
+  LR.insert(LR.end(), hm.ff_R.begin(), hm.ff_R.end());
+  m.n_hblk = (int64_t)hb.size();
+  m.n_hcls = (int64_t)hc.size();
+  m.n_hx_items = (int64_t)items.size() / 2;
+  m.hblk.upload(hb.data(), hb.size(), st);
+  m.hcls.upload(hc.data(), hc.size(), st);
+  m.hcore.upload(hm.ff_core.data(), hm.ff_core.size(), st);
+  m.hS.upload(LR.data(), LR.size(), st);
+  m.hl_ptr.upload(lptr.data(), lptr.size(), st);
+  m.hl_blk.upload(lblk.data(), lblk.size(), st);
+  m.hx_nbegin.upload(nb.data(), nb.size(), st);
+  m.hx_nend.upload(ne.data(), ne.size(), st);
+  m.hx_items.upload(items.data(), items.size(), st);
+  PH_HIP(hipStreamSynchronize(st));   // host staging buffers die with this call
+  m.device_bytes += (int64_t)(m.hblk.bytes() + m.hcls.bytes() + m.hcore.bytes() + m.hS.bytes() + m.hl_ptr.bytes() +
+                              m.hl_blk.bytes() + m.hx_nbegin.bytes() + m.hx_nend.bytes() + m.hx_items.bytes());
+}
+
 static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData> tp, HostModel& hm,
                                                  hipStream_t st) {
   const TreeData& t = *tp;
@@ -454,7 +532,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
   m->near_tr.upload(ntr.data(), ntr.size(), st);
   m->near_q.upload(nq.data(), nq.size(), st);
   m->cstore.upload(cd.data(), cd.size(), st);
-  m->ff_chat.upload(chat.data(), chat.size(), st);
+  if (!hm.implicit) m->ff_chat.upload(chat.data(), chat.size(), st);   // implicit: no formed couplings
   m->ff_theta.upload(hm.ff_theta.data(), hm.ff_theta.size(), st);
   m->grp_targets.upload(gt.data(), gt.size(), st);
   m->grp_entry.upload(gptr.data(), gptr.size(), st);
@@ -504,6 +582,7 @@ static std::shared_ptr<DeviceModel> upload_model(std::shared_ptr<const TreeData>
                               m->chunk_first.bytes() + m->mvm_items.bytes() + m->mvm_items64.bytes() + m->near_q.bytes() + m->hgrp_targets.bytes() + m->hent_cls.bytes() +
                               m->hent_tau.bytes() + m->hchunk_first.bytes());
   if (hm.hformat) upload_hmatrix(*m, t, hm, st);
+  if (hm.implicit) upload_implicit(*m, t, hm, st);
   return m;
 }
 
@@ -567,8 +646,8 @@ int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype
     need(dt == PH_F64 || dt == PH_F32 || dt == PH_BF16, "dtype must be PH_F64, PH_F32 or PH_BF16");
     need(near == PH_NEAR_AUTO || near == PH_NEAR_BLOCKS || near == PH_NEAR_FACTORED, "invalid near-field mode");
     const ph::DeviceModel& md = *m->p;
-    if (md.format == PH_FORMAT_H && dt != PH_F64)
-      ph::fail(PH_EUNSUPPORTED, "parametric H-matrix models support PH_F64 instances only");
+    if (md.format != PH_FORMAT_H2 && dt != PH_F64)
+      ph::fail(PH_EUNSUPPORTED, "parametric H-matrix and implicit-coupling models support PH_F64 instances only");
     if (near == PH_NEAR_FACTORED && md.KRp > 64)
       ph::fail(PH_EUNSUPPORTED, "factored near field supports near ranks up to 64");
     // automatic form: factored for one batch of 4..8 slots, where each factor entry read
@@ -610,7 +689,7 @@ int inst_common(const ph_model* m, const double* theta, int T, int dim, ph_dtype
       } else {
         in->D.alloc((size_t)T * md.N_nf_pad * in->d_esize);
       }
-      if (md.format == PH_FORMAT_H) in->C.alloc((size_t)T * md.h_tot * sizeof(double));   // H_q(theta_t)
+      if (md.format != PH_FORMAT_H2) in->C.alloc((size_t)T * md.h_tot * sizeof(double));   // H_q(theta_t)
       else in->C.alloc((size_t)T * md.n_classes * md.Pp * md.Pp * in->esize);
       if (md.format == PH_FORMAT_H2 && dt == PH_BF16 && md.min_far >= 0 && md.n_groups > 0 && ph::coupling_bf16_supported(md, ph::RC))
         in->Cb.alloc((size_t)T * ph::coupling_bf16_c_bytes(md));
@@ -745,6 +824,18 @@ int ph_offline_compress_h(const ph_tree* t, const ph_offline_opts* opts, void* s
     need(t && t->p && opts && out, "NULL argument");
     auto hm = ph::offline_host(*t->p, *opts);
     ph::hmatrix_far_host(*t->p, *hm, opts->num_threads);
+    auto dm = ph::upload_model(t->p, *hm, (hipStream_t)stream);
+    *out = new ph_model{dm};
+  });
+}
+
+int ph_offline_compress_tt(const ph_tree* t, const ph_offline_opts* opts, int coupling, void* stream,
+                           ph_model** out) {
+  return guarded([&] {
+    need(t && t->p && opts && out, "NULL argument");
+    need(coupling == PH_COUPLING_MATERIALIZED || coupling == PH_COUPLING_IMPLICIT, "invalid coupling form");
+    auto hm = ph::offline_host(*t->p, *opts, false, ph::Compress::TT);
+    hm->implicit = coupling == PH_COUPLING_IMPLICIT && t->p->min_far_level >= 0;
     auto dm = ph::upload_model(t->p, *hm, (hipStream_t)stream);
     *out = new ph_model{dm};
   });
@@ -1152,8 +1243,9 @@ int ph_inst_coupling(const ph_inst* k, int t, int64_t c, double* host_out) {
     const ph::DeviceModel& m = *in.m;
     need(t >= 0 && t < in.T, "slot out of range");
     need(c >= 0 && c < m.n_classes, "class index out of range");
-    if (m.format == PH_FORMAT_H)
-      ph::fail(PH_EUNSUPPORTED, "ph_inst_coupling: a parametric H-matrix instance forms no coupling matrices");
+    if (m.format != PH_FORMAT_H2)
+      ph::fail(PH_EUNSUPPORTED, "ph_inst_coupling: the instance forms no coupling matrices (H-matrix format or "
+                                "implicit coupling)");
     const int64_t cnt = (int64_t)m.Pp * m.Pp;
     PH_HIP(hipDeviceSynchronize());
     std::vector<char> buf(cnt * in.esize);

@@ -216,6 +216,13 @@ struct DeviceModel {
   DevArr<HClsDev> hcls;
   DevArr<double> hcore, hS, hT;
   DevArr<int32_t> hl_ptr, hl_blk;
+  // implicit coupling (PH_FORMAT_H2_IMPLICIT, Alg. "Modified H^2-Matrix MVM"): the same block,
+  // class and CSR arrays over the coupling's index space (row s Pp + i of x_hat / y_hat is
+  // entry i of node s): one block per far block with S_b = L_q, T_b = R_q (swapped for a
+  // mirrored class) in hS = [L factors, R factors], per node its row range and work item
+  DevArr<int64_t> hx_nbegin, hx_nend;
+  DevArr<int32_t> hx_items;
+  int64_t n_hx_items = 0;
   // coupling work list: target boxes of NTG nodes of one level (see coupling_groups)
   DevArr<int32_t> grp_targets;            // n_groups x NTG node ids (-1 = absent)
   DevArr<int32_t> grp_entry;              // n_groups + 1
@@ -329,6 +336,10 @@ void coupling_bf16_launch(const InstData& in, const float* xh, void* xb, float* 
 void h_core_launch(const InstData& in, hipStream_t st);
 void h_far_launch(const InstData& in, const double* xt, double* yt, double* W, int64_t Rs, int64_t nrc,
                   hipStream_t st, int phase);
+// Implicit coupling (k_hmatrix.hip): y_hat_s = sum over the far blocks (s, t) of
+// L_q (H_q(theta) (R_q^T x_hat_t)) for every node s of the far levels (written, not added)
+void implicit_coupling_launch(const InstData& in, const double* xh, double* yh, double* W, int64_t Rs,
+                              int64_t nrc, hipStream_t st);
 // CG / iterative refinement for the R right-hand sides [R][n] of y and a (k_solve.hip)
 void cg_solve_impl(InstData& hi, InstData* lo, const double* y, double* a, int64_t R, double nugget, double tol,
                    int max_iter, int inner_max, double inner_tol, ph_cg_stats* stats, hipStream_t st);

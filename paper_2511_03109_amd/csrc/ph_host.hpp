@@ -103,13 +103,54 @@ struct HostModel {
   int svd_sweeps_max = 0;   // most one-sided Jacobi sweeps any SVD of the stage needed
   // parametric H-matrix format (ph_offline_compress_h): explicit far factors per far block
   bool hformat = false;
+  // implicit coupling (ph_offline_compress_tt with PH_COUPLING_IMPLICIT): the online stage forms
+  // H_q(theta) only and the MVM applies L_q H_q R_q^T without forming C
+  bool implicit = false;
   std::vector<HBlock> hblk;
   std::vector<double> hS, hT;
 };
 
+// Compression of the offline stage's tensors: truncated HOSVD, or TT-cross + TT-rounding
+enum class Compress { HOSVD, TT };
+
 // gpu: the kernel tensors (near blocks and far classes) are evaluated on the GPU
-// (k_offline.hip) and compressed on the host
-std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts& o, bool gpu = false);
+// (k_offline.hip) and compressed on the host; comp: the compression (TT: host only, the
+// entries are evaluated on demand by the cross)
+std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts& o, bool gpu = false,
+                                        Compress comp = Compress::HOSVD);
+
+// ---- dense linear algebra of the offline stage (offline.cpp), column-major
+// Householder QR of the m x k matrix A (m >= k) in place: R in the upper triangle, the
+// reflectors below it (unit leading entry implied) with scalars tau
+void householder_qr(double* A, int64_t m, int k, double* tau);
+// Y (m x r) <- Q Y with Q from householder_qr
+void apply_q(const double* A, int64_t m, int k, const double* tau, double* Y, int r);
+// Left singular vectors and singular values (descending) of the m x q matrix X
+struct LeftSV {
+  std::vector<double> U;  // m x kk, kk = min(m, q)
+  std::vector<double> s;  // kk
+  int64_t m = 0;
+  int kk = 0;
+  int sweeps = 0;   // one-sided Jacobi sweeps (more than the cap: not converged)
+};
+LeftSV left_sv(const double* X, int64_t m, int64_t q);
+// smallest r with sum_{j >= r} s_j^2 <= thr, never cutting a cluster of equal values
+int truncation_rank(const double* s, int k, double thr);
+
+// ---- tensor train (tt.cpp; Sec. 2.1): TT-cross with partially pivoted ACA per supercore,
+// a sampled max-norm check with enrichment, then TT-rounding
+struct TensorTrain {
+  std::vector<int> dims;                   // m_0 .. m_{N-1}
+  std::vector<int> ranks;                  // r_0 = 1 .. r_N = 1
+  std::vector<std::vector<double>> cores;  // core k: r_k x m_k x r_{k+1}, column-major
+  int64_t evals = 0;                       // distinct tensor entries evaluated
+  int sweeps = 0;                          // most Jacobi sweeps of the rounding's SVDs
+};
+// Entry accessor: out[s] = X[idx[s * N .. s * N + N - 1]] for s < count (multi-indices
+// row-major, column-major tensor)
+typedef void (*EntryFn)(const void* ctx, const int32_t* idx, int64_t count, double* out);
+// TT-cross at a tenth of tol (the sampled check at tol), then TT-rounding at tol
+TensorTrain tt_compress(EntryFn entry, const void* ctx, const std::vector<int>& dims, double tol);
 
 // GPU kernel-tensor generation for the offline stage (k_offline.hip).  A near job is one stored
 // near block: out[off + kk Ne + j ns + i] = kappa(x_{s_begin + i}, x_{t_begin + j}; grid[kk]),

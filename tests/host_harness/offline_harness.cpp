@@ -1,7 +1,7 @@
-// Host-only test harness: the offline stage's own SVD and truncated HOSVD (offline.cpp,
-// compiled into this translation unit) behind a small C interface, so that a CPU test can
-// compare them with LAPACK's on the same tensors.  Test infrastructure; not part of the
-// library.
+// Host-only test harness: the offline stage's own SVD, truncated HOSVD (offline.cpp, compiled
+// into this translation unit) and TT compression (tt.cpp, linked beside it) behind a small C
+// interface, so that a CPU test can compare them with LAPACK's and with the oracle's on the
+// same tensors.  Test infrastructure; not part of the library.
 #include "../../paper_2511_03109_amd/csrc/offline.cpp"
 
 extern "C" {
@@ -47,6 +47,49 @@ void harness_thosvd(const double* T, const int64_t* dims, int N, double tol, int
     cur[m] = full;
   }
   for (int64_t i = 0; i < total; ++i) recon[i] = Y[(size_t)i];
+}
+
+// TT-cross + TT-rounding (tt_compress) of the column-major tensor T with dims[0..N-1]: the TT
+// ranks into ranks[0..N] and the TT's full tensor into recon; returns the number of distinct
+// entries the cross evaluated.
+static void dense_entries(const void* c, const int32_t* idx, int64_t count, double* out) {
+  const auto* ctx = static_cast<const std::pair<const double*, std::vector<int64_t>>*>(c);
+  const int N = (int)ctx->second.size();
+  for (int64_t s = 0; s < count; ++s) {
+    int64_t l = 0;
+    for (int k = 0; k < N; ++k) l += ctx->second[k] * idx[s * N + k];
+    out[s] = ctx->first[l];
+  }
+}
+
+int64_t harness_tt(const double* T, const int* dims, int N, double tol, int* ranks, double* recon) {
+  std::vector<int> d(dims, dims + N);
+  std::vector<int64_t> stride;
+  int64_t s = 1;
+  for (int m : d) {
+    stride.push_back(s);
+    s *= m;
+  }
+  std::pair<const double*, std::vector<int64_t>> ctx{T, stride};
+  ph::TensorTrain tt = ph::tt_compress(dense_entries, &ctx, d, tol);
+  for (int k = 0; k <= N; ++k) ranks[k] = tt.ranks[k];
+  // full tensor: X (rows x r) grown core by core
+  std::vector<double> X = tt.cores[0];
+  int64_t rows = d[0];
+  for (int k = 1; k < N; ++k) {
+    const int r0 = tt.ranks[k], m = d[k], r1 = tt.ranks[k + 1];
+    std::vector<double> Y((size_t)rows * m * r1, 0.0);
+    for (int b = 0; b < r1; ++b)
+      for (int i = 0; i < m; ++i)
+        for (int a = 0; a < r0; ++a) {
+          const double g = tt.cores[k][(size_t)a + (size_t)r0 * (i + (size_t)m * b)];
+          for (int64_t q = 0; q < rows; ++q) Y[(size_t)q + (size_t)rows * (i + (size_t)m * b)] += X[(size_t)q + (size_t)rows * a] * g;
+        }
+    X.swap(Y);
+    rows *= m;
+  }
+  for (int64_t i = 0; i < rows; ++i) recon[i] = X[(size_t)i];
+  return tt.evals;
 }
 
 }  // extern "C"

@@ -271,6 +271,80 @@ def test_matern_free_nu(case):
         _mvm_case(X, "matern", [0.1, 0.5], [1.0, 3.0], 4, 7, 1e-8, 2, (3, 1), [0.17, 0.71], R=3)
 
 
+# The library's and the oracle's TT-cross take the same pivots, but solve their pivot systems
+# in different rounding: their TT tensors agree to about 5e-12 of the largest entry (measured on
+# the CPU by test_offline_svd.py::test_library_tt_cross_equals_oracle), which bounds the parity
+# of everything downstream of the TT compression.
+TOL_TT = 1e-10
+
+
+@pytest.mark.parametrize("case", ["2d_T3_R17", "3d_R16", "matern_nu"])
+def test_tt_compression_and_implicit_coupling(case):
+    """ph_offline_compress_tt (TT-cross + TT-rounding, Sec. 2.1) with the couplings formed online
+    (format h2) and kept as factors (format h2_implicit, Alg. "Modified H^2-Matrix MVM").  Against
+    the oracle's TT model (compress="tt"): the ranks and the number of kernel evaluations exactly
+    (same pivots), the near blocks and couplings of the formed model and the MVMs of both
+    formats to TOL_TT; the implicit and the formed model share their factors, so their MVMs
+    agree to the FP64 tolerance.  Coupling inspection and non-FP64 instances of the implicit
+    format are rejected with PH_EUNSUPPORTED."""
+    torch = _torch()
+    from paper_2511_03109_amd import _lib, api
+    if case == "2d_T3_R17":
+        n, wl = 1200, 1
+        args = ("gaussian", [0.05], [0.5], 5, 7, 1e-8, 3, (2, 1))
+        T, R = 3, 17
+    elif case == "3d_R16":
+        n, wl = 1500, 2
+        args = ("matern32", [0.05], [0.5], 4, 7, 1e-8, 2, (3, 1))
+        T, R = 1, 16
+    else:
+        n, wl = 1200, 1
+        args = ("matern", [0.25, 0.5], [1.0, 3.0], 5, 5, 1e-8, 3, (2, 1))
+        T, R = 2, 4
+    kernel, lo, hi, p_s, p_theta, tol, l_max, eta2 = args
+    X = inputs.points_for(wl, n)
+    print(f"[tt] case {case}: n {n} kernel {kernel} T {T} R {R}", flush=True)
+    lt = api.Tree(X, l_max=l_max, eta2=eta2)
+    lm = api.Model(lt, kernel, lo, hi, p_s=p_s, p_theta=p_theta, tol=tol, compress="tt")
+    li = api.Model(lt, kernel, lo, hi, p_s=p_s, p_theta=p_theta, tol=tol, compress="tt", coupling="implicit")
+    assert lm.format == "h2" and li.format == "h2_implicit"
+    om = hmat.PH2(X, l_max=l_max, eta2=Fraction(*eta2), kernel=kernels.KERNELS[kernel][0], theta_lo=lo,
+                  theta_hi=hi, p_s=p_s, p_theta=p_theta, tol=tol, compress="tt")
+    _check_ranks(lm, om)
+    assert lm.info["kernel_evals"] == om.tt_evals == li.info["kernel_evals"]
+    thetas = inputs.theta_samples(T, lo, hi, 37)
+    im = api.Instance(lm, thetas)
+    ii = api.Instance(li, thetas)
+    sizes = [len(om.tree.idx[s_]) for s_ in om.tree.leaves]
+    ne_max = max(sizes) ** 2
+    oi = om.instantiate(thetas[0])
+    Dg = np.concatenate([im.near_block(b).ravel() for b in range(len(om.near))])
+    Do = np.concatenate([oi["D"][b].ravel() for b in range(len(om.near))])
+    _close(Dg, Do, tol=TOL_TT, what=f"TT near blocks {case}", max_entries=ne_max)
+    Cg = np.stack([im.coupling(c) for c in range(len(om.classes))])
+    Co = np.stack([oi["C"][c] for c in range(len(om.classes))])
+    _close(Cg, Co, tol=TOL_TT, what=f"TT couplings {case}")
+    x = inputs.normal_vectors(n, T * R, 43).T.reshape(T, R, n)
+    xd = torch.tensor(np.ascontiguousarray(x), device="cuda")
+    ym = im.matvec(xd, nugget=0.2).cpu().numpy()
+    yi = ii.matvec(xd, nugget=0.2).cpu().numpy()
+    for t in range(T):
+        y_o = om.matvec(om.instantiate(thetas[t]), x[t].T, nugget=0.2)
+        _close(ym[t].T, y_o, tol=TOL_TT, what=f"TT mvm (formed couplings) {case} slot {t}", max_entries=ne_max)
+        _close(yi[t].T, y_o, tol=TOL_TT, what=f"TT mvm (implicit coupling) {case} slot {t}", max_entries=ne_max)
+        _close(yi[t].T, ym[t].T, what=f"implicit vs formed couplings {case} slot {t}", max_entries=ne_max)
+    # a second MVM with one right-hand side on the same implicit instance (scratch reuse)
+    y1 = ii.matvec(xd[:, :1, :].contiguous()).cpu().numpy()
+    for t in range(T):
+        _close(y1[t, 0], ym[t, 0] - 0.2 * x[t, 0], what=f"implicit R=1 {case} slot {t}", max_entries=ne_max)
+    with pytest.raises(_lib.PHError) as e:
+        ii.coupling(0)
+    assert e.value.code == _lib.PH_EUNSUPPORTED
+    with pytest.raises(_lib.PHError) as e:
+        api.Instance(li, thetas, dtype="f32")
+    assert e.value.code == _lib.PH_EUNSUPPORTED
+
+
 @pytest.mark.parametrize("case", ["2d_R1", "2d_T3_R17", "3d_R16", "matern_nu"])
 def test_hmatrix_variant(case):
     """The parametric H-matrix format (ph_offline_compress_h): every slot's MVM (with a nugget)

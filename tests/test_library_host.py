@@ -169,6 +169,22 @@ def test_offline_rejects_bad_options(bad, code):
     # NULL stream: the call must fail in the option checks, before anything is uploaded
     assert lib.ph_offline_compress(t._h, C.byref(opts), None, C.byref(out)) == code
     assert lib.ph_last_error() and not out.value
+    # the TT-compressed offline stage validates the same options the same way
+    assert lib.ph_offline_compress_tt(t._h, C.byref(opts), 1, None, C.byref(out)) == code
+    assert not out.value
+
+
+def test_offline_tt_rejects_bad_coupling():
+    import ctypes as C
+    t = api.Tree(np.random.default_rng(1).random((50, 2)), l_max=1)
+    opts = _lib.OfflineOpts()
+    opts.kernel = _lib.KERNELS["gaussian"]
+    opts.d_theta = 1
+    opts.theta_lo[0], opts.theta_hi[0] = 0.1, 0.5
+    opts.p_s, opts.p_theta, opts.tol, opts.num_threads = 4, 5, 1e-8, 1
+    out = C.c_void_p()
+    assert _lib.lib().ph_offline_compress_tt(t._h, C.byref(opts), 2, None, C.byref(out)) == _lib.PH_EINVAL
+    assert not out.value
 
 
 @pytest.mark.parametrize("d", [1, 2, 3])

@@ -33,6 +33,7 @@ def harness(tmp_path_factory):
     cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
            "-I" + os.path.join(ROOT, "include"), os.path.join(HERE, "host_harness", "offline_harness.cpp"),
            os.path.join(ROOT, "paper_2511_03109_amd", "csrc", "special.cpp"),
+           os.path.join(ROOT, "paper_2511_03109_amd", "csrc", "tt.cpp"),
            os.path.join(HERE, "host_harness", "gpu_stub.cpp"), "-o", out]
     subprocess.run(cmd, check=True, capture_output=True)
     lib = C.CDLL(out)
@@ -41,6 +42,8 @@ def harness(tmp_path_factory):
     lib.harness_left_sv.restype = C.c_int
     lib.harness_thosvd.argtypes = [dp, C.POINTER(C.c_int64), C.c_int, C.c_double, C.POINTER(C.c_int), dp]
     lib.harness_thosvd.restype = None
+    lib.harness_tt.argtypes = [dp, C.POINTER(C.c_int), C.c_int, C.c_double, C.POINTER(C.c_int), dp]
+    lib.harness_tt.restype = C.c_int64
     return lib
 
 
@@ -196,3 +199,52 @@ def test_jacobi_converges_on_graded_and_underflowing_unfoldings(harness):
               f"singular values vs LAPACK {np.max(np.abs(s_lib - s_np)) / s_np[0]:.1e}")
         assert sweeps <= 30
         assert np.max(np.abs(s_lib - s_np)) <= 1e-13 * s_np[0]
+
+
+# ---------------------------------------------------------------- TT-cross (tt.cpp vs oracle.tt)
+def _lib_tt(lib, T, tol):
+    T = np.asfortranarray(T, dtype=np.float64)
+    dims = np.array(T.shape, dtype=np.int32)
+    ranks = np.empty(T.ndim + 1, dtype=np.int32)
+    rec = np.empty(T.shape, order="F")
+    ev = lib.harness_tt(_ptr(T), dims.ctypes.data_as(C.POINTER(C.c_int)), T.ndim, tol,
+                        ranks.ctypes.data_as(C.POINTER(C.c_int)), _ptr(rec))
+    return ranks, rec, ev
+
+
+def _tt_cases():
+    """Far tensors (modes i_1..i_d, k, j_1..j_d) of symmetric and asymmetric classes and near
+    tensors (e, k) of a 2-D Gaussian and a 3-D Matern-3/2 model."""
+    out = []
+    for kern, d, n, l, eta2, lo, hi in (("gaussian", 2, 900, 3, 2, 0.05, 0.5), ("matern32", 3, 1500, 2, 3, 0.05, 0.5)):
+        X = np.random.default_rng([5, d]).random((n, d))
+        m = hmat.PH2(X, l_max=l, eta2=eta2, kernel=kernels.KERNELS[kern][0], theta_lo=[lo], theta_hi=[hi],
+                     p_s=4, p_theta=7, tol=1e-8)
+        seen = 0
+        for key, (lev, off) in enumerate(m.classes):
+            if tuple(off) < tuple(-c for c in off) or seen >= 4:
+                continue
+            M = m.far_tensor_of_block(m.class_rep[key])
+            out.append(M.reshape((4,) * d + (7,) + (4,) * d, order="F"))
+            seen += 1
+        for bi in (0, len(m.near) // 2):
+            s, u = m.near[bi]
+            if s <= u:
+                out.append(m.near_tensor(s, u))
+    return out
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-10])
+def test_library_tt_cross_equals_oracle(harness, tol):
+    """The library's TT-cross + TT-rounding (tt.cpp) takes the same pivots as the oracle's on the
+    same tensors: the ranks agree exactly and the two TT tensors agree to rounding (1e-10 of the
+    largest entry; different pivots would differ by about tol).  Both are within tol ||M||_F."""
+    from oracle import tt
+    for M in _tt_cases():
+        ranks, rec, ev = _lib_tt(harness, M, tol)
+        cores, ev_o = tt.tt_compress(lambda idx: M[tuple(idx.T)], list(M.shape), tol)
+        assert list(ranks[1:-1]) == [c.shape[2] for c in cores[:-1]]
+        assert ev == ev_o
+        full = tt.tt_full(cores)
+        assert np.max(np.abs(rec - full)) <= 1e-10 * np.max(np.abs(M))
+        assert np.linalg.norm(rec - M) <= tol * np.linalg.norm(M)
