@@ -500,8 +500,68 @@ def mode_offline(args):
                       "unit": "s", "higher_is_better": False, "n_gpus": 1, "data": "synthetic", "results": out}))
 
 
+def mode_tt(args):
+    """The paper's compression (TT-cross + TT-rounding) against the truncated HOSVD on the same
+    workloads (the benchmark, Matern-3/2 n = 65536, and the E kernel at n = 8^5 with the paper's
+    lambda box): host offline seconds, kernel evaluations, mean ranks and device bytes of each;
+    then 8 theta instantiated and applied to 16 RHS each, timed like the headline, for the HOSVD
+    model (couplings formed), the TT model with couplings formed and the TT model with the
+    implicit coupling of Alg. "Modified H^2-Matrix MVM"; relative differences of the outputs."""
+    import torch
+    from paper_2511_03109_amd import _lib, api, inputs
+    lib = _lib.lib()
+    out = {}
+    for wid in (7, 2):
+        w = inputs.WORKLOADS[wid]
+        n, T, R = w["n"], w["T"], w["R"]
+        X = inputs.points_for(wid)
+        tree = api.Tree(X, leaf_size=w["leaf"], l_max=-1, eta2=tuple(w["eta2"]))
+        thetas = inputs.theta_samples(T, w["theta_lo"], w["theta_hi"], wid)
+        x = torch.tensor(np.ascontiguousarray(inputs.normal_vectors(n, T * R, wid).T.reshape(T, R, n)), device="cuda")
+        res, ys = {}, {}
+        for name, kw in (("hosvd", {}), ("tt", {"compress": "tt"}),
+                         ("tt_implicit", {"compress": "tt", "coupling": "implicit"})):
+            torch.cuda.synchronize()
+            t0 = time.time()
+            model = api.Model(tree, w["kernel"], w["theta_lo"], w["theta_hi"], p_s=w["p_s"], p_theta=w["p_theta"],
+                              tol=w["tol"], **kw)
+            torch.cuda.synchronize()
+            offline_s = time.time() - t0
+            y = torch.empty_like(x)
+            inst = api.Instance(model, thetas)
+            ms = _timed(lambda: (inst.reinstantiate(thetas), inst.matvec(x, y)), args.steps, args.warmup)
+            stats = _lib.TraceStats()
+            lib.ph_trace_read(stats, 1)
+            lib.ph_trace_enable(1)
+            for _ in range(3):
+                inst.reinstantiate(thetas)
+                inst.matvec(x, y)
+            torch.cuda.synchronize()
+            lib.ph_trace_enable(0)
+            _lib.check(lib.ph_trace_read(stats, 1), "ph_trace_read")
+            info = model.info
+            res[name] = {"offline_s": offline_s, "kernel_evals": info["kernel_evals"],
+                         "far_rank_mean": info["far_rank_mean"], "near_rank_mean": info["near_rank_mean"],
+                         "device_bytes": info["device_bytes"], "ms_per_theta": ms / T,
+                         "stage_ms_per_step": {nm: stats.ms[i] / 3 for i, nm in enumerate(_lib.STAGES)
+                                               if stats.count[i]}}
+            ys[name] = y.clone()
+            log(f"[bench] tt {w['name']} {name}: {res[name]}")
+            del inst, model
+            torch.cuda.empty_cache()
+        for name in ("tt", "tt_implicit"):
+            res[name]["rel_diff_vs_hosvd"] = float(torch.linalg.vector_norm(ys[name] - ys["hosvd"]) /
+                                                   torch.linalg.vector_norm(ys["hosvd"]))
+        res["rel_diff_implicit_vs_formed"] = float(torch.linalg.vector_norm(ys["tt_implicit"] - ys["tt"]) /
+                                                   torch.linalg.vector_norm(ys["tt"]))
+        out[w["name"]] = res
+    print(json.dumps({"metric": "TT-cross vs HOSVD compression; formed vs implicit coupling",
+                      "unit": "ms per theta (16 RHS) / s offline", "higher_is_better": False, "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "data": "synthetic", "results": out}))
+
+
 MODES = {"precision": mode_precision, "cg": mode_cg, "grad": mode_grad, "sweep": mode_sweep,
-         "matern": mode_matern, "hmatrix": mode_hmatrix, "offline": mode_offline}
+         "matern": mode_matern, "hmatrix": mode_hmatrix, "offline": mode_offline, "tt": mode_tt}
 
 
 def main():
@@ -514,7 +574,7 @@ def main():
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the comparison legs (per-theta FP64, near blocks in memory, FP32, BF16)")
     ap.add_argument("--mode", default="step", choices=["step", "precision", "cg", "grad", "sweep", "matern", "hmatrix",
-                                                    "offline"],
+                                                    "offline", "tt"],
                     help="step (default): the benchmark step; precision: FP64 / FP32 / BF16 instances of "
                          "the same step; cg: (K + 1e-2 I) a = y at n = 262144 by FP64 CG and by FP64 "
                          "refinement around FP32 / BF16; grad: forward + backward of y = K(l) x at "

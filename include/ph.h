@@ -232,8 +232,8 @@ int ph_offline_compress_h(const ph_tree* t, const ph_offline_opts* opts, void* s
  * Sec. 4.2 / App. PTTK review for the far tensors, Sec. 4.3 for the near tensors): every far
  * tensor M[i_1..i_d, k_1.., j_1..j_d] and near tensor A_b[e, k_1..] is approximated by TT-cross
  * (partially pivoted ACA on each supercore, started from the middle index of every mode,
- * alternating sweeps, a max-norm error check on 256 SplitMix64-sampled entries with enrichment
- * of the index sets) at tol / 10 and then TT-rounded at tol; entries are evaluated on demand,
+ * alternating sweeps, a max-norm error check at 10 tol on 256 SplitMix64-sampled entries with
+ * enrichment of the index sets) at tol / 10 and then TT-rounded at tol; entries are evaluated on demand,
  * each at most once (ph_model_info.kernel_evals counts them).  The cores are converted exactly
  * into the online form: L_q from the target-side spatial cores, R_q from the source-side ones,
  * the parameter cores as the core of H_q(theta) with identity parameter factors (ranks

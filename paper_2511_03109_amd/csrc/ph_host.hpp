@@ -149,7 +149,7 @@ struct TensorTrain {
 // Entry accessor: out[s] = X[idx[s * N .. s * N + N - 1]] for s < count (multi-indices
 // row-major, column-major tensor)
 typedef void (*EntryFn)(const void* ctx, const int32_t* idx, int64_t count, double* out);
-// TT-cross at a tenth of tol (the sampled check at tol), then TT-rounding at tol
+// TT-cross at a tenth of tol (the sampled max-norm check at 10 tol), then TT-rounding at tol
 TensorTrain tt_compress(EntryFn entry, const void* ctx, const std::vector<int>& dims, double tol);
 
 // GPU kernel-tensor generation for the offline stage (k_offline.hip).  A near job is one stored
