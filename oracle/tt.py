@@ -40,7 +40,8 @@ them.  The reading taken here:
   from sweep to sweep as its index sets change, so they are no stopping test.)
 * Cores from the last left-to-right sweep: G_k = A(I_k x m_k, J_{k+1})
   A(I_{k+1}, J_{k+1})^{-1} for k < N-1 and G_{N-1} = A(I_{N-1} x m_{N-1}), the
-  interpolation form of the cross.
+  interpolation form of the cross; G_k is evaluated as Q Q(I_{k+1}, :)^{-1} from the
+  reduced QR of A(I_k x m_k, J_{k+1}) (the same matrix, better conditioned).
 * TT-rounding (Oseledets): right-to-left QR orthogonalisation, then left-to-right
   SVD truncation with delta = tol / sqrt(N-1) ||X||_F per unfolding (at least rank
   1), never cutting a cluster of equal singular values (the rule of
@@ -237,8 +238,10 @@ def tt_cross(entry, dims, tol, start=None, check_tol=None):
         for k in range(N - 1):
             rp, cp, raw_rows, raw_cols = last[k]
             C = np.stack(raw_cols, axis=1)                   # (r_k m_k) x r_{k+1}
-            A = C[rp, :]                                     # pivot submatrix
-            G = np.linalg.solve(A.T, C.T).T
+            # C A^{-1} with A = C[rp] the pivot submatrix, formed as Q Q[rp]^{-1} from C = Q R:
+            # the same matrix, but Q[rp] is far better conditioned than A
+            Q, _ = np.linalg.qr(C)
+            G = np.linalg.solve(Q[rp, :].T, Q.T).T
             cores.append(G.reshape(rl, dims[k], len(rp), order="F"))
             rl = len(rp)
             if k == N - 2:

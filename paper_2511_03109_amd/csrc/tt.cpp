@@ -25,7 +25,9 @@
 //    MAX_SWEEPS sweeps.  (The ranks of an ACA-based cross move by one or two from sweep to sweep
 //    as its index sets change, so they are no stopping test.)
 //  * Cores from the last left-to-right sweep: G_k = A(I_k x m_k, J_{k+1}) A(I_{k+1}, J_{k+1})^-1,
-//    G_{N-1} = A(I_{N-1} x m_{N-1}): the interpolation form of the cross.
+//    G_{N-1} = A(I_{N-1} x m_{N-1}): the interpolation form of the cross, with G_k evaluated as
+//    Q Q(I_{k+1}, :)^-1 from the reduced QR of A(I_k x m_k, J_{k+1}) (same matrix, better
+//    conditioned).
 //  * TT-rounding (Oseledets): right-to-left QR orthogonalisation, then left-to-right truncated
 //    SVD with delta = tol / sqrt(N-1) |X|_F per unfolding (rank >= 1), with the cluster rule of
 //    truncation_rank.
@@ -348,6 +350,9 @@ TensorTrain zero_tt(const std::vector<int>& dims) {
   return t;
 }
 
+void qr_reduced(const std::vector<double>& A, int64_t m, int k, std::vector<double>& Q, std::vector<double>& R,
+                int& q);
+
 TensorTrain tt_cross(Tensor& X, double tol, double check_tol) {
   const int N = X.N();
   const std::vector<int>& dims = X.dims;
@@ -376,9 +381,14 @@ TensorTrain tt_cross(Tensor& X, double tol, double check_tol) {
       std::vector<double> C((size_t)mr * r), A((size_t)r * r);
       for (int l = 0; l < r; ++l)
         for (int64_t q = 0; q < mr; ++q) C[(size_t)q + (size_t)mr * l] = a.raw_cols[l][q];
+      // C A^-1 with A = C(pivot rows) is formed as Q Q(pivot rows)^-1 from C = Q R: the same
+      // matrix, but Q(pivot rows) is far better conditioned than A
+      std::vector<double> Q, Rq;
+      int q;
+      qr_reduced(C, mr, r, Q, Rq, q);
       for (int l = 0; l < r; ++l)
-        for (int p = 0; p < r; ++p) A[(size_t)p + (size_t)r * l] = C[(size_t)a.rows[p] + (size_t)mr * l];
-      t.cores.push_back(right_solve(C, mr, A, r));
+        for (int p = 0; p < r; ++p) A[(size_t)p + (size_t)r * l] = Q[(size_t)a.rows[p] + (size_t)mr * l];
+      t.cores.push_back(right_solve(Q, mr, A, r));
       t.ranks[k + 1] = r;
       rl = r;
       if (k == N - 2) {
