@@ -31,6 +31,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 
 #include "kernel_fn.hpp"
@@ -492,6 +493,36 @@ void near_entries(const void* c, const int32_t* idx, int64_t count, double* out)
   }
 }
 
+// A failure inside an OpenMP loop is recorded (the first one) and raised after the loop: an
+// exception must not leave a parallel region.
+struct LoopError {
+  std::mutex mu;
+  int code = 0;
+  std::string msg;
+  void record(int c, const std::string& m) {
+    std::lock_guard<std::mutex> g(mu);
+    if (code == 0) {
+      code = c;
+      msg = m;
+    }
+  }
+  template <typename F>
+  void guard(F&& f) {
+    try {
+      f();
+    } catch (const Failure& e) {
+      record(e.code, e.what());
+    } catch (const std::bad_alloc&) {
+      record(PH_ENOMEM, "ph_offline_compress: out of host memory");
+    } catch (const std::exception& e) {
+      record(PH_EINVAL, e.what());   // as the C ABI maps other exceptions
+    }
+  }
+  void raise() {
+    if (code != 0) fail(code, msg);
+  }
+};
+
 }  // namespace
 
 int kernel_dtheta(ph_kernel k, int d) {
@@ -613,6 +644,7 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
   const int64_t nfc = (int64_t)m->cstore.size();
   std::vector<Tucker> ftuck(nfc);
   int64_t evals_far = 0;
+  LoopError lerr;   // failures of the TT compression inside the parallel loops
   // Chebyshev nodes of the two boxes of each stored class's first far block (P x d each)
   std::vector<double> cnodes((size_t)nfc * 2 * P * d);
   for (int64_t ci = 0; ci < nfc; ++ci) {
@@ -651,9 +683,11 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
       std::vector<int> tdims(d, ps);
       for (int k = 0; k < dth; ++k) tdims.push_back(pt);
       for (int k = 0; k < d; ++k) tdims.push_back(ps);
-      TensorTrain tt = tt_compress(far_entries, &fc, tdims, o.tol);
-      evals_far += tt.evals;
-      ftuck[ci] = tt_far_tucker(tt, d, dth);
+      lerr.guard([&] {
+        TensorTrain tt = tt_compress(far_entries, &fc, tdims, o.tol);
+        evals_far += tt.evals;
+        ftuck[ci] = tt_far_tucker(tt, d, dth);
+      });
       continue;
     }
     std::vector<double> M((size_t)P * q * P);
@@ -673,6 +707,7 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
     dims.push_back(P);
     ftuck[ci] = thosvd(M, dims, o.tol);
   }
+  lerr.raise();
   for (const Tucker& tk : ftuck) m->svd_sweeps_max = std::max(m->svd_sweeps_max, tk.sweeps);
   for (int64_t ci = 0; ci < nfc; ++ci) {
     ClassStored& cs = m->cstore[ci];
@@ -767,9 +802,11 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
                  grid.data()};
       std::vector<int> tdims{(int)Ne};
       for (int k = 0; k < dth; ++k) tdims.push_back(pt);
-      TensorTrain tt = tt_compress(near_entries, &nc, tdims, o.tol);
-      near_evals[bi] = tt.evals;
-      ntuck[bi] = tt_near_tucker(tt, dth);
+      lerr.guard([&] {
+        TensorTrain tt = tt_compress(near_entries, &nc, tdims, o.tol);
+        near_evals[bi] = tt.evals;
+        ntuck[bi] = tt_near_tucker(tt, dth);
+      });
       return;
     }
     std::vector<double> A((size_t)Ne * q);
@@ -861,6 +898,7 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
       b0 = b1;
     }
   }
+  lerr.raise();
   for (int64_t bi = 0; bi < nst; ++bi)
     evals_near += near_evals[bi] >= 0 ? near_evals[bi] : (int64_t)m->nstore[bi].ns * m->nstore[bi].nt * q;
   for (const Tucker& tk : ntuck) m->svd_sweeps_max = std::max(m->svd_sweeps_max, tk.sweeps);
