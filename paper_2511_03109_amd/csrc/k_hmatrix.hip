@@ -45,117 +45,133 @@ __global__ void __launch_bounds__(NT) k_h_core(const HClsDev* __restrict__ cls, 
 }
 
 constexpr int HTB = 8;    // parameter slots per workgroup (S_b and T_b read once for them)
-constexpr int HCH = 16;   // rows of T_b / ranks of S_b staged per step
+
+// Offset of entry (m, k), m < 128, k < 16, in a 128 x 16 operand panel staged in LDS in the
+// operand order of the FP64 matrix cores (the in-panel part of frag_index): row tile m / 16,
+// then (k, m % 4, (m % 16) / 4), so the four rows a lane feeds to one instruction are adjacent.
+__device__ __forceinline__ int panel_index(int m, int k) {
+  return (m >> 4) * 256 + k * 16 + (m & 3) * 4 + ((m & 15) >> 2);
+}
 
 // w_b = H_b(theta_t) (T_b^T x_t) for far block b, one 16-column RHS tile and the slots
-// t0 .. t0 + HTB - 1; W[(t nrc + tile) hw_tot + w_off + a 16 + c].  T_b is theta-independent, so
-// z_t = T_b^T x_t for all HTB slots comes from one pass over T_b: thread (g, c) = (tid / 16,
-// tid % 16) owns ranks g, g + 16, ... and RHS column c of every slot.  Rows of T_b and of the
-// slots' x go through LDS in chunks of HCH.  Then, slot by slot, z_t goes through LDS and
-// w_t = H' z_t, H' = H_q (or H_q^T for a mirrored class) read from the instance.
-__global__ void __launch_bounds__(NT) k_h_proj(const double* __restrict__ xt, double* __restrict__ W,
+// t0 .. t0 + HTB - 1; W[(t nrc + tile) hw_tot + w_off + a 16 + c].  On the FP64 matrix cores:
+// T_b is theta-independent, so z_t = T_b^T x_t for all HTB slots comes from one pass over T_b,
+// with the ranks as 8 row tiles of 16 and the slots as 8 column tiles of 16 right-hand sides
+// (wave w owns rank tiles w and w + 4 of every slot); per step 16 rows of T_b (transposed into
+// the operand order) and of every slot's x go through LDS.  Then, slot by slot, z_t goes
+// through LDS as the B operand and w_t = H' z_t, H' = H_q (or H_q^T for a mirrored class) read
+// from the instance 16 columns per step, on the matrix cores again.
+__global__ void __launch_bounds__(NT, 2) k_h_proj(const double* __restrict__ xt, double* __restrict__ W,
                                                const HBlkDev* __restrict__ blks, const double* __restrict__ hT,
                                                const double* __restrict__ Hc, int64_t h_tot, int64_t hw_tot,
                                                int64_t n, int64_t Rs, int nrc, int T) {
-  // phase 1 (z = T_b^T x for all slots) uses Ts and xs, phase 2 (w = H' z per slot) zs and Hs
-  constexpr int P1 = HCH * 129 + HTB * HCH * 16, P2 = 128 * 17 + 128 * (HCH + 1);
-  __shared__ double smem[P1 > P2 ? P1 : P2];
-  double(*Ts)[129] = reinterpret_cast<double(*)[129]>(smem);
-  double(*xs)[HCH][16] = reinterpret_cast<double(*)[HCH][16]>(smem + HCH * 129);
-  double(*zs)[17] = reinterpret_cast<double(*)[17]>(smem);
-  double(*Hs)[HCH + 1] = reinterpret_cast<double(*)[HCH + 1]>(smem + 128 * 17);
+  typedef Tile16<double> MF;
+  __shared__ __attribute__((aligned(16))) double As[8 * 256];   // A panel: 128 x 16, operand order
+  __shared__ __attribute__((aligned(16))) double Bs[HTB][256];  // B: 16 x 16 per slot; phase 2: z (128 x 16)
+  double* Bz = &Bs[0][0];
   const HBlkDev b = blks[blockIdx.x];
   const int tile = blockIdx.y;
   const int t0 = blockIdx.z * HTB;
   const int tn = min(HTB, T - t0);
   const int r0 = tile * RC;
   const int rc = (int)min<int64_t>(RC, Rs - r0);
-  const int c = threadIdx.x % 16, g = threadIdx.x / 16;
+  const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
   const double* T_ = hT + b.T_off;
-  double acc[HTB][8];
+  MF::acc_t acc[HTB][2];
 #pragma unroll
   for (int s = 0; s < HTB; ++s)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[s][j] = 0;
-  for (int64_t i0 = 0; i0 < b.nt; i0 += HCH) {
-    const int cn = (int)min<int64_t>(HCH, b.nt - i0);
+    for (int j = 0; j < 2; ++j) acc[s][j] = (MF::acc_t){0, 0, 0, 0};
+  // phase 1: z_t = T_b^T x_t, 16 rows of T_b per step
+  for (int64_t i0 = 0; i0 < b.nt; i0 += 16) {
     __syncthreads();
-    for (int e = threadIdx.x; e < HTB * HCH * 16; e += NT) {
-      const int ts = e / (HCH * 16), ii = (e / 16) % HCH, cc = e % 16;
-      xs[ts][ii][cc] = (ts < tn && ii < cn && cc < rc)
-                           ? xt[((int64_t)(t0 + ts) * n + b.t_begin + i0 + ii) * Rs + r0 + cc] : 0.0;
+    for (int q = threadIdx.x; q < 128 * 16; q += NT) {
+      const int kk = q % 16, a = q / 16;
+      As[panel_index(a, kk)] = (a < b.rt && i0 + kk < b.nt) ? T_[i0 + kk + (int64_t)b.ldt * a] : 0.0;
     }
-    for (int e = threadIdx.x; e < HCH * b.rt; e += NT) {
-      const int ii = e % HCH, a = e / HCH;
-      Ts[ii][a] = ii < cn ? T_[i0 + ii + (int64_t)b.ldt * a] : 0.0;
+    for (int q = threadIdx.x; q < HTB * 256; q += NT) {
+      const int ts = q / 256, kk = (q / 16) % 16, cc = q % 16;
+      Bs[ts][kk * 16 + cc] = (ts < tn && i0 + kk < b.nt && cc < rc)
+                                 ? xt[((int64_t)(t0 + ts) * n + b.t_begin + i0 + kk) * Rs + r0 + cc] : 0.0;
     }
     __syncthreads();
-    for (int ii = 0; ii < cn; ++ii) {
-      double tv[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) tv[j] = Ts[ii][min(g + 16 * j, 127)];
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int k = kk + (lane >> 4);
+      MF::a_t av[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) av[j] = MF::load_tiled(&As[(wave + 4 * j) * 256 + k * 16], lane);
 #pragma unroll
       for (int s = 0; s < HTB; ++s) {
-        const double xv = xs[s][ii][c];
+        const double bv = Bs[s][k * 16 + (lane & 15)];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[s][j] += tv[j] * xv;
+        for (int j = 0; j < 2; ++j) acc[s][j] = MF::mac(av[j], bv, acc[s][j]);
       }
     }
   }
-  for (int s = 0; s < tn; ++s) {
+  // phase 2, slot by slot: w_t = H' z_t (rows of H' beyond rs and columns beyond rt are zero)
+#pragma unroll
+  for (int s = 0; s < HTB; ++s) {
+    if (s >= tn) break;
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int a = g + 16 * j;
-      if (a < b.rt) zs[a][c] = acc[s][j];
-    }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Bz[((wave + 4 * j) * 16 + MF::row(lane, q)) * 16 + (lane & 15)] = acc[s][j][q];
     const int64_t slot = t0 + s;
     const double* H = Hc + slot * h_tot + b.h_off;
-    double wacc[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) wacc[j] = 0;
-    // H' in column chunks of HCH through LDS (coalesced reads of H_q or of H_q^T's rows)
-    for (int a0 = 0; a0 < b.rt; a0 += HCH) {
-      const int an = min(HCH, b.rt - a0);
+    MF::acc_t w2[2] = {(MF::acc_t){0, 0, 0, 0}, (MF::acc_t){0, 0, 0, 0}};
+    for (int a0 = 0; a0 < b.rt; a0 += 16) {
       __syncthreads();
-      for (int e = threadIdx.x; e < b.rs * HCH; e += NT) {
-        int ap, aa;
-        if (b.tr) { aa = e % HCH; ap = e / HCH; }
-        else { ap = e % b.rs; aa = e / b.rs; }
-        Hs[ap][aa] = aa < an ? (b.tr ? H[a0 + aa + (int64_t)b.rt * ap] : H[ap + (int64_t)b.rs * (a0 + aa)]) : 0.0;
+      for (int q = threadIdx.x; q < 128 * 16; q += NT) {
+        int ap, kk;
+        if (b.tr) { kk = q % 16; ap = q / 16; }   // H' = H^T: H[a + rt ap], a contiguous
+        else { ap = q % 128; kk = q / 128; }       // H' = H: H[ap + rs a], ap contiguous
+        const int a = a0 + kk;
+        As[panel_index(ap, kk)] =
+            (ap < b.rs && a < b.rt) ? (b.tr ? H[a + (int64_t)b.rt * ap] : H[ap + (int64_t)b.rs * a]) : 0.0;
       }
       __syncthreads();
-      for (int aa = 0; aa < an; ++aa) {
-        const double zv = zs[a0 + aa][c];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) wacc[j] += Hs[min(g + 16 * j, 127)][aa] * zv;
+      for (int kk = 0; kk < 16; kk += 4) {
+        const int k = kk + (lane >> 4);
+        const double bv = Bz[(a0 + k) * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const MF::a_t av = MF::load_tiled(&As[(wave + 4 * j) * 256 + k * 16], lane);
+          w2[j] = MF::mac(av, bv, w2[j]);
+        }
       }
     }
     double* w = W + (slot * nrc + tile) * hw_tot + b.w_off;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int ap = g + 16 * j;
-      if (ap < b.rs) w[ap * 16 + c] = wacc[j];
-    }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ap = (wave + 4 * j) * 16 + MF::row(lane, q);
+        if (ap < b.rs) w[ap * 16 + (lane & 15)] = w2[j][q];
+      }
   }
 }
 
-// yt[rows] += sum over the far blocks b whose target contains the rows of S_b[rows] w_b, for one
-// (leaf, 128-row chunk) item, one RHS tile and the slots t0 .. t0 + HTB - 1.  Thread (g, c) owns
-// rows g, g + 16, ... of the chunk and RHS column c of every slot; HCH columns of S_b (the chunk's
-// rows) and the matching rows of w_b of every slot go through LDS per step, so S_b is read once
-// for all HTB slots.  ADD: the sum is added to yt; else it is written (an item with no blocks
-// then writes zeros).
+// yt[rows] (+)= sum over the far blocks b whose target contains the rows of S_b[rows] w_b, for
+// one (leaf, 128-row chunk) item, one RHS tile and the slots t0 .. t0 + HTB - 1, on the FP64
+// matrix cores: the chunk's rows are 8 row tiles of 16 and the slots 8 column tiles of 16
+// right-hand sides (wave w owns row tiles w and w + 4 of every slot).  Per step 16 columns of
+// S_b (the chunk's rows, in the operand order) and the matching 16 rows of w_b of every slot go
+// through LDS, so S_b is read once for all HTB slots.  ADD: the sum is added to yt; else it is
+// written (an item with no blocks then writes zeros).
 template <bool ADD>
-__global__ void __launch_bounds__(NT) k_h_apply(double* __restrict__ yt, const double* __restrict__ W,
+__global__ void __launch_bounds__(NT, 2) k_h_apply(double* __restrict__ yt, const double* __restrict__ W,
                                                 const HBlkDev* __restrict__ blks, const double* __restrict__ hS,
                                                 const int32_t* __restrict__ leaf_ptr,
                                                 const int32_t* __restrict__ leaf_blk, const int64_t* __restrict__ nbegin,
                                                 const int64_t* __restrict__ nend, const int32_t* __restrict__ items,
                                                 int32_t leaf0, int64_t hw_tot, int64_t n, int64_t Rs, int nrc, int T) {
+  typedef Tile16<double> MF;
   constexpr int CH = 128;
-  __shared__ double Ss[HCH][CH + 1];
-  __shared__ double ws[HTB][HCH][16];
+  __shared__ __attribute__((aligned(16))) double As[8 * 256];   // 128 rows x 16 columns of S_b
+  __shared__ __attribute__((aligned(16))) double Bs[HTB][256];  // 16 rows of w_b per slot
   const int li = items[2 * blockIdx.x], cstart = items[2 * blockIdx.x + 1];
   const int32_t leaf = leaf0 + li;
   const int tile = blockIdx.y;
@@ -163,55 +179,62 @@ __global__ void __launch_bounds__(NT) k_h_apply(double* __restrict__ yt, const d
   const int tn = min(HTB, T - t0);
   const int r0 = tile * RC;
   const int rc = (int)min<int64_t>(RC, Rs - r0);
-  const int c = threadIdx.x % 16, g = threadIdx.x / 16;
+  const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
   const int64_t lb = nbegin[leaf], ln = nend[leaf] - lb;
   const int cn = (int)min<int64_t>(CH, ln - cstart);
-  double acc[HTB][8];
+  MF::acc_t acc[HTB][2];
 #pragma unroll
   for (int s = 0; s < HTB; ++s)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[s][j] = 0;
+    for (int j = 0; j < 2; ++j) acc[s][j] = (MF::acc_t){0, 0, 0, 0};
   for (int e = leaf_ptr[li]; e < leaf_ptr[li + 1]; ++e) {
     const HBlkDev b = blks[leaf_blk[e]];
     // rows of the chunk relative to the block's target cluster
     const double* S = hS + b.S_off + (lb + cstart - b.s_begin);
-    for (int a0 = 0; a0 < b.rs; a0 += HCH) {
-      const int an = min(HCH, b.rs - a0);
+    for (int a0 = 0; a0 < b.rs; a0 += 16) {
       __syncthreads();
-      for (int q = threadIdx.x; q < HCH * CH; q += NT) {
-        const int aa = q / CH, r = q % CH;
-        Ss[aa][r] = (aa < an && r < cn) ? S[r + (int64_t)b.lds * (a0 + aa)] : 0.0;
+      for (int q = threadIdx.x; q < CH * 16; q += NT) {
+        const int r = q % CH, kk = q / CH;
+        As[panel_index(r, kk)] = (r < cn && a0 + kk < b.rs) ? S[r + (int64_t)b.lds * (a0 + kk)] : 0.0;
       }
-      for (int q = threadIdx.x; q < HTB * HCH * 16; q += NT) {
-        const int ts = q / (HCH * 16), aa = (q / 16) % HCH, cc = q % 16;
-        ws[ts][aa][cc] = (ts < tn && aa < an) ? W[((int64_t)(t0 + ts) * nrc + tile) * hw_tot + b.w_off + (a0 + aa) * 16 + cc]
-                                              : 0.0;
+      for (int q = threadIdx.x; q < HTB * 256; q += NT) {
+        const int ts = q / 256, kk = (q / 16) % 16, cc = q % 16;
+        Bs[ts][kk * 16 + cc] = (ts < tn && a0 + kk < b.rs)
+                                   ? W[((int64_t)(t0 + ts) * nrc + tile) * hw_tot + b.w_off + (a0 + kk) * 16 + cc]
+                                   : 0.0;
       }
       __syncthreads();
-      for (int aa = 0; aa < an; ++aa) {
-        double sv[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) sv[j] = Ss[aa][g + 16 * j];
+      for (int kk = 0; kk < 16; kk += 4) {
+        const int k = kk + (lane >> 4);
+        MF::a_t av[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) av[j] = MF::load_tiled(&As[(wave + 4 * j) * 256 + k * 16], lane);
 #pragma unroll
         for (int s = 0; s < HTB; ++s) {
-          const double wv = ws[s][aa][c];
+          const double bv = Bs[s][k * 16 + (lane & 15)];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) acc[s][j] += sv[j] * wv;
+          for (int j = 0; j < 2; ++j) acc[s][j] = MF::mac(av[j], bv, acc[s][j]);
         }
       }
     }
   }
+  const int c = lane & 15;
   if (c >= rc) return;
-  for (int s = 0; s < tn; ++s) {
+#pragma unroll
+  for (int s = 0; s < HTB; ++s) {
+    if (s >= tn) break;
     double* y = yt + ((int64_t)(t0 + s) * n + lb + cstart) * Rs + r0 + c;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int r = g + 16 * j;
-      if (r < cn) {
-        if (ADD) y[(int64_t)r * Rs] += acc[s][j];
-        else y[(int64_t)r * Rs] = acc[s][j];
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = (wave + 4 * j) * 16 + MF::row(lane, q);
+        if (r < cn) {
+          if (ADD) y[(int64_t)r * Rs] += acc[s][j][q];
+          else y[(int64_t)r * Rs] = acc[s][j][q];
+        }
       }
-    }
   }
 }
 
