@@ -444,6 +444,7 @@ __global__ void __launch_bounds__(NW * 64, HB) k_coupling(
     bool use[NTW];
 #pragma unroll
     for (int s = 0; s < NTW; ++s) use[s] = PACK || ent_tau[e * NTG + toff + wt * NTW + s] >= 0;
+    __builtin_amdgcn_s_setprio(1);   // matrix-core phase first when the other workgroup stages
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       const int k = kk + (lane >> 4);
@@ -464,6 +465,7 @@ __global__ void __launch_bounds__(NW * 64, HB) k_coupling(
           if (FULL || wr + WR * j < nMt) acc[s][j] = MF::mac(a[j], bv[s], acc[s][j]);
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     if (PD == 1) stash(decltype(RS)::value, buf ^ 1);
     __syncthreads();
   };
