@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(NT) k_transfer_down(S* __restrict__ yh, const 
 // B[k][c] = x_hat of target c's source for the entry's class (zero if c does not use it),
 // so a stage multiplies one C panel by one 16-column tile instead of 16 tiles of which 15
 // columns would be padding.  Requires the unpadded single-RHS layout (Rs = 1, r0 = 0).
-template <typename S, int NW, int WR, int TPW, int PD, bool FULL, bool PACK = false, int HB = 1>
+template <typename S, int NW, int WR, int TPW, int PD, bool FULL, bool PACK = false, int HB = 1, int KG = 1>
 __global__ void __launch_bounds__(NW * 64, HB) k_coupling(
     const S* __restrict__ xh, S* __restrict__ out, const S* __restrict__ C,
     const int32_t* __restrict__ grp_targets, const int32_t* __restrict__ grp_entry,
@@ -445,24 +445,31 @@ __global__ void __launch_bounds__(NW * 64, HB) k_coupling(
 #pragma unroll
     for (int s = 0; s < NTW; ++s) use[s] = PACK || ent_tau[e * NTG + toff + wt * NTW + s] >= 0;
     __builtin_amdgcn_s_setprio(1);   // matrix-core phase first when the other workgroup stages
+    // KG K-steps of 4 per group: the fragments of a group are read from LDS together, so the
+    // wait before the first target's products is paid once per group rather than per K-step
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
-      const int k = kk + (lane >> 4);
-      typename MF::a_t a[TPW];
-      S bv[NTW];
+    for (int kk = 0; kk < KC; kk += 4 * KG) {
+      typename MF::a_t a[KG][TPW];
+      S bv[KG][NTW];
 #pragma unroll
-      for (int j = 0; j < TPW; ++j) {
-        const int mt = wr + WR * j;
-        if (FULL || mt < nMt) a[j] = MF::load_tiled(&As[buf][mt * 256 + k * 16], lane);
+      for (int g = 0; g < KG; ++g) {
+        const int k = kk + 4 * g + (lane >> 4);
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) {
+          const int mt = wr + WR * j;
+          if (FULL || mt < nMt) a[g][j] = MF::load_tiled(&As[buf][mt * 256 + k * 16], lane);
+        }
+#pragma unroll
+        for (int s = 0; s < NTW; ++s) bv[g][s] = Bs[buf][wt * NTW + s][k * 16 + (lane & 15)];
       }
-#pragma unroll
-      for (int s = 0; s < NTW; ++s) bv[s] = Bs[buf][wt * NTW + s][k * 16 + (lane & 15)];
 #pragma unroll
       for (int s = 0; s < NTW; ++s) {
         if (!use[s]) continue;
 #pragma unroll
-        for (int j = 0; j < TPW; ++j)
-          if (FULL || wr + WR * j < nMt) acc[s][j] = MF::mac(a[j], bv[s], acc[s][j]);
+        for (int g = 0; g < KG; ++g)
+#pragma unroll
+          for (int j = 0; j < TPW; ++j)
+            if (FULL || wr + WR * j < nMt) acc[s][j] = MF::mac(a[g][j], bv[g][s], acc[s][j]);
       }
     }
     __builtin_amdgcn_s_setprio(0);
@@ -1116,8 +1123,10 @@ void matvec_impl(InstData& in, const S* x, S* y, int64_t R, double alpha, double
         run(k_coupling<S, 4, 4, 1, 1, false, true>, 4);
       }
     } else if (nMt == 8 && hb == 2) {
+      // fragments of two K-steps read per group (KG = 2): 4.75 vs 4.97 ms per launch on the
+      // benchmark in a same-box A/B; KG = 4 spills
       if (pd == 2) run(k_coupling<S, 4, 4, 2, 2, true, false, 2>, 4);
-      else run(k_coupling<S, 4, 4, 2, 1, true, false, 2>, 4);
+      else run(k_coupling<S, 4, 4, 2, 1, true, false, 2, 2>, 4);
     } else if (nMt == 8) {
       if (pd == 2) run(k_coupling<S, 8, 4, 2, 2, true>, 8);
       else run(k_coupling<S, 8, 4, 2, 1, true>, 8);
