@@ -44,7 +44,7 @@ def kernel_text(text, kernel):
     """The definition of `kernel` in a source text: from its template line to the first
     closing brace in column 0."""
     import re
-    m = re.search(r"^template <[^\n]*>\n__global__[^\n]*\b" + kernel + r"\(", text, re.M)
+    m = re.search(r"^template <[^>]*>\n__global__[^\n]*\b" + kernel + r"\(", text, re.M)
     if m is None:
         raise KeyError(kernel)
     end = text.index("\n}\n", m.start())
