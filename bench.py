@@ -560,8 +560,58 @@ def mode_tt(args):
                       "steps": args.steps, "warmup": args.warmup, "data": "synthetic", "results": out}))
 
 
+def mode_ttrank(args):
+    """The TT compression at the paper's parametric H^2 configuration (Matern (lambda, nu) in
+    [0.25, 1] x [0.5, 3], n = 8^4 and 8^5 uniform in [0,1]^3, l_max 2 and 3, eta = sqrt(3),
+    p_s = 8, p_theta = 27, tol 1e-5): the TT ranks of every translation class's far tensor
+    (ph_tt_far_ranks, host only; P = 512 is beyond the online kernels, so no model is built),
+    then the paper's Rank (mean over far blocks of max(r_d, r_{d+d_theta})) and Coupling Ratio
+    (entries of the TT-stored couplings of all far blocks over n^2), next to the values the paper
+    prints for its own TT-cross.  The printed Coupling Ratio formula lists the spatial cores
+    1..3 and, on the source side, only the last two; the plain ratios count all 2 d spatial cores
+    (p_s r_{i-1} r_i each) plus r_d r_{d+d_theta}, the `_as_printed` ones the printed terms.  The
+    formula sums over far blocks, but the printed values match one coupling per translation
+    class; both counts are reported."""
+    from paper_2511_03109_amd import api
+    paper = {4: 0.14734703302383423, 5: 0.004155942238867283}   # Table "ph_h2_induced", MN
+    out = {}
+    d, dth, ps = 3, 2, 8
+    N = 2 * d + dth
+    for e, l_max in ((4, 2), (5, 3)):
+        n = 8 ** e
+        X = np.random.default_rng([17, e]).random((n, d))
+        tree = api.Tree(X, l_max=l_max, eta2=(3, 1))
+        t0 = time.time()
+        ranks, ev = api.tt_far_ranks(tree, "matern", [0.25, 0.5], [1.0, 3.0], p_s=ps, p_theta=27, tol=1e-5)
+        secs = time.time() - t0
+        _, _, fcls = tree.blocks()
+        nb = np.bincount(fcls, minlength=ranks.shape[0]).astype(np.float64)
+        r = ranks.astype(np.float64)
+        rank = float(np.sum(nb * np.maximum(r[:, d], r[:, d + dth])) / np.sum(nb))
+        spatial = sum(r[:, i - 1] * r[:, i] for i in range(1, d + 1)) + \
+            sum(r[:, i - 1] * r[:, i] for i in range(d + dth + 1, N + 1))
+        printed = sum(r[:, i - 1] * r[:, i] for i in range(1, d + 1)) + \
+            sum(r[:, i] * r[:, i + 1] for i in range(d + dth + 1, N))
+        mid = r[:, d] * r[:, d + dth]
+        cr = float(np.sum(nb * (ps * spatial + mid)) / n ** 2)
+        cr_p = float(np.sum(nb * (ps * printed + mid)) / n ** 2)
+        # one stored coupling per translation class (Sec. 5.2): the paper's printed values match
+        # this count, not one per far block
+        cr_c = float(np.sum(ps * spatial + mid) / n ** 2)
+        cr_cp = float(np.sum(ps * printed + mid) / n ** 2)
+        out[f"n=8^{e}"] = {"classes": int(ranks.shape[0]), "far_blocks": int(nb.sum()), "rank": rank,
+                           "coupling_ratio_per_class": cr_c, "coupling_ratio_per_class_as_printed": cr_cp,
+                           "coupling_ratio_per_block": cr, "coupling_ratio_per_block_as_printed": cr_p,
+                           "paper_coupling_ratio": paper[e], "tt_ranks_mean": [float(v) for v in r.mean(axis=0)],
+                           "kernel_evals": int(ev), "seconds": secs}
+        log(f"[bench] ttrank n=8^{e}: {out[f'n=8^{e}']}")
+    print(json.dumps({"metric": "TT ranks and coupling ratio at the paper's parametric H^2 configuration (MN)",
+                      "unit": "ratio", "data": "synthetic", "results": out}))
+
+
 MODES = {"precision": mode_precision, "cg": mode_cg, "grad": mode_grad, "sweep": mode_sweep,
-         "matern": mode_matern, "hmatrix": mode_hmatrix, "offline": mode_offline, "tt": mode_tt}
+         "matern": mode_matern, "hmatrix": mode_hmatrix, "offline": mode_offline, "tt": mode_tt,
+         "ttrank": mode_ttrank}
 
 
 def main():
@@ -574,7 +624,7 @@ def main():
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the comparison legs (per-theta FP64, near blocks in memory, FP32, BF16)")
     ap.add_argument("--mode", default="step", choices=["step", "precision", "cg", "grad", "sweep", "matern", "hmatrix",
-                                                    "offline", "tt"],
+                                                    "offline", "tt", "ttrank"],
                     help="step (default): the benchmark step; precision: FP64 / FP32 / BF16 instances of "
                          "the same step; cg: (K + 1e-2 I) a = y at n = 262144 by FP64 CG and by FP64 "
                          "refinement around FP32 / BF16; grad: forward + backward of y = K(l) x at "

@@ -246,6 +246,16 @@ typedef enum { PH_COUPLING_MATERIALIZED = 0, PH_COUPLING_IMPLICIT = 1 } ph_coupl
 int ph_offline_compress_tt(const ph_tree* t, const ph_offline_opts* opts, int coupling, void* stream,
                            ph_model** out);
 
+/* The compression of ph_offline_compress_tt on its own (Sec. 2.1; the paper's Rank and
+ * Coupling Ratio are functions of these ranks): the TT ranks r_0 .. r_N, N = 2 d + d_theta, of
+ * the far tensor of every translation class after TT-cross and TT-rounding, host only, no model
+ * built and nothing uploaded, so p_s^d up to 4096 and p_theta up to 64 are accepted (the model
+ * entry points stop at 128 and 16).  ranks: host, n_classes x (N + 1) row-major in class order
+ * (ph_tree_classes); a class whose offset is lexicographically below its negative reports the
+ * ranks of its mirror in reverse order.  kernel_evals (may be NULL): distinct kernel values
+ * evaluated.  Errors as ph_offline_compress. */
+int ph_tt_far_ranks(const ph_tree* t, const ph_offline_opts* opts, int32_t* ranks, int64_t* kernel_evals);
+
 /* The hierarchical format of a model (ph_format). */
 int ph_model_format(const ph_model* m, int* format);
 

@@ -79,6 +79,7 @@ SIGNATURES = {
     "ph_offline_compress_h": ([_P, C.POINTER(OfflineOpts), _P, C.POINTER(_P)], C.c_int),
     "ph_offline_compress_gpu": ([_P, C.POINTER(OfflineOpts), _P, C.POINTER(_P)], C.c_int),
     "ph_offline_compress_tt": ([_P, C.POINTER(OfflineOpts), C.c_int, _P, C.POINTER(_P)], C.c_int),
+    "ph_tt_far_ranks": ([_P, C.POINTER(OfflineOpts), C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int),
     "ph_model_format": ([_P, C.POINTER(C.c_int)], C.c_int),
     "ph_model_info_get": ([_P, C.POINTER(ModelInfo)], C.c_int),
     "ph_model_near_ranks": ([_P, _I32P], C.c_int),

@@ -322,6 +322,26 @@ def kernel_eval(kernel, x, y, theta):
     return out
 
 
+def tt_far_ranks(tree, kernel, theta_lo, theta_hi, *, p_s, p_theta, tol, num_threads=0):
+    """TT ranks of every translation class's far tensor after TT-cross + TT-rounding
+    (ph_tt_far_ranks; host only, no model): an int32 array of shape (n_classes, 2 d + d_theta + 1)
+    and the number of distinct kernel values evaluated."""
+    lo = np.atleast_1d(np.asarray(theta_lo, dtype=np.float64))
+    hi = np.atleast_1d(np.asarray(theta_hi, dtype=np.float64))
+    opts = L.OfflineOpts()
+    opts.kernel = L.KERNELS[kernel]
+    opts.d_theta = lo.shape[0]
+    for k in range(lo.shape[0]):
+        opts.theta_lo[k] = lo[k]
+        opts.theta_hi[k] = hi[k]
+    opts.p_s, opts.p_theta, opts.tol, opts.num_threads = p_s, p_theta, tol, num_threads
+    out = np.empty((tree.info["n_classes"], 2 * tree.d + lo.shape[0] + 1), np.int32)
+    ev = C.c_int64()
+    L.check(L.lib().ph_tt_far_ranks(tree._h, C.byref(opts), out.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(ev)),
+            "ph_tt_far_ranks")
+    return out, ev.value
+
+
 def cg_solve(inst64, y, *, nugget, tol=1e-6, lo=None, max_iter=100000, inner_max=1000, inner_tol=1e-4,
              stream=None):
     """Solve (K~ + nugget I) a = y (ph_cg_solve, or ph_cg_solve_batch for several right-hand

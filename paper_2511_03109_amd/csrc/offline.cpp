@@ -950,6 +950,96 @@ std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts
   return m;
 }
 
+// TT ranks of the far tensor of every translation class after TT-cross + TT-rounding (Sec. 2.1),
+// for comparisons of the compression itself; no model is built, so P = p_s^d (up to 4096) and
+// p_theta (up to 64) are not limited by the online stage's kernels.  ranks: n_classes x (N + 1),
+// N = 2 d + d_theta; a mirrored class reports its stored class's ranks in reverse order.
+std::vector<int32_t> tt_far_ranks(const TreeData& t, const ph_offline_opts& o, int64_t* evals_out) {
+  const int d = t.d;
+  if (o.p_s < 1 || o.p_s > 16 || o.p_theta < 1 || o.p_theta > 64)
+    fail(PH_EINVAL, "ph_tt_far_ranks: p_s must be in 1..16 and p_theta in 1..64");
+  if (!(o.tol >= 0.0)) fail(PH_EINVAL, "ph_tt_far_ranks: tol must be >= 0");
+  const int dth = kernel_dtheta(o.kernel, d);
+  if (dth < 0) fail(PH_EUNSUPPORTED, "ph_tt_far_ranks: unknown kernel");
+  if (o.kernel == PH_KERNEL_ANISO_GAUSSIAN && d > 2)
+    fail(PH_EUNSUPPORTED, "ph_tt_far_ranks: anisotropic Gaussian supports d <= 2");
+  if (o.d_theta != dth) fail(PH_EUNSUPPORTED, "ph_tt_far_ranks: d_theta does not match the kernel");
+  for (int k = 0; k < dth; ++k)
+    if (!(o.theta_lo[k] < o.theta_hi[k])) fail(PH_EINVAL, "ph_tt_far_ranks: need theta_lo < theta_hi");
+  if (o.kernel == PH_KERNEL_MATERN && !(o.theta_lo[0] > 0 && o.theta_lo[1] > 0))
+    fail(PH_EINVAL, "ph_tt_far_ranks: the Matern kernel needs lambda > 0 and nu > 0 on all of Theta");
+  const int ps = o.p_s, pt = o.p_theta;
+  int P = 1;
+  for (int k = 0; k < d; ++k) P *= ps;
+  const int N = 2 * d + dth;
+  const int q = dth == 1 ? pt : pt * pt;
+  std::vector<double> thn((size_t)2 * pt), grid((size_t)q * 2, 0.0);
+  for (int k = 0; k < dth; ++k) cheb_nodes(o.theta_lo[k], o.theta_hi[k], pt, thn.data() + (size_t)pt * k);
+  for (int kk = 0; kk < q; ++kk) {
+    grid[2 * kk] = thn[kk % pt];
+    if (dth == 2) grid[2 * kk + 1] = thn[(size_t)pt + kk / pt];
+  }
+  const int64_t ncls = t.n_classes();
+  std::map<std::vector<int32_t>, int32_t> bykey;
+  for (int64_t c = 0; c < ncls; ++c) {
+    std::vector<int32_t> kk{t.class_level[c]};
+    for (int k = 0; k < d; ++k) kk.push_back(t.class_off[c * d + k]);
+    bykey[kk] = (int32_t)c;
+  }
+  // stored classes (offset >= its negative) and, for the others, the stored class they mirror
+  std::vector<int32_t> src(ncls, -1), canon;
+  for (int64_t c = 0; c < ncls; ++c) {
+    std::vector<int32_t> off(t.class_off.begin() + c * d, t.class_off.begin() + (c + 1) * d), neg(d);
+    for (int k = 0; k < d; ++k) neg[k] = -off[k];
+    if (off >= neg) {
+      canon.push_back((int32_t)c);
+    } else {
+      std::vector<int32_t> mk{t.class_level[c]};
+      mk.insert(mk.end(), neg.begin(), neg.end());
+      auto it = bykey.find(mk);
+      if (it == bykey.end()) fail(PH_ESTATE, "far class list is not symmetric");
+      src[c] = it->second;
+    }
+  }
+  std::vector<int32_t> ranks((size_t)ncls * (N + 1), 0);
+  int64_t evals = 0;
+  LoopError lerr;
+  const int nthreads = o.num_threads > 0 ? o.num_threads : omp_get_max_threads();
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) reduction(+ : evals)
+  for (int64_t ci = 0; ci < (int64_t)canon.size(); ++ci) {
+    lerr.guard([&] {
+      const int32_t c = canon[ci];
+      const int32_t b = t.class_first_block[c];
+      const int32_t s = t.far[2 * b], u = t.far[2 * b + 1];
+      std::vector<double> ns((size_t)P * d), nt((size_t)P * d);
+      for (int k = 0; k < d; ++k) {
+        double bs[16], bt[16];
+        cheb_nodes(t.box_lo[s * d + k], t.box_hi[s * d + k], ps, bs);
+        cheb_nodes(t.box_lo[u * d + k], t.box_hi[u * d + k], ps, bt);
+        int stride = 1;
+        for (int kk = 0; kk < k; ++kk) stride *= ps;
+        for (int i = 0; i < P; ++i) {
+          ns[(size_t)i * d + k] = bs[(i / stride) % ps];
+          nt[(size_t)i * d + k] = bt[(i / stride) % ps];
+        }
+      }
+      FarCtx fc{o.kernel, d, dth, ps, P, ns.data(), nt.data(), grid.data(), pt};
+      std::vector<int> tdims(d, ps);
+      for (int k = 0; k < dth; ++k) tdims.push_back(pt);
+      for (int k = 0; k < d; ++k) tdims.push_back(ps);
+      TensorTrain tt = tt_compress(far_entries, &fc, tdims, o.tol);
+      evals += tt.evals;
+      for (int k = 0; k <= N; ++k) ranks[(size_t)c * (N + 1) + k] = tt.ranks[k];
+    });
+  }
+  lerr.raise();
+  for (int64_t c = 0; c < ncls; ++c)
+    if (src[c] >= 0)
+      for (int k = 0; k <= N; ++k) ranks[(size_t)c * (N + 1) + k] = ranks[(size_t)src[c] * (N + 1) + (N - k)];
+  if (evals_out) *evals_out = evals;
+  return ranks;
+}
+
 // Parametric H-matrix far field (Def. "Parametric H-matrix"; App. PTTK, offline phase 3).
 // For far block b = (s, t) of class c with stored class q: S_b = U_s A and T_b = U_t B, where
 // (A, B) = (L_q, R_q), or (R_q, L_q) when c is the mirror of q (its far tensor is the transpose),

@@ -841,6 +841,16 @@ int ph_offline_compress_tt(const ph_tree* t, const ph_offline_opts* opts, int co
   });
 }
 
+int ph_tt_far_ranks(const ph_tree* t, const ph_offline_opts* opts, int32_t* ranks, int64_t* kernel_evals) {
+  return guarded([&] {
+    need(t && t->p && opts && ranks, "NULL argument");
+    int64_t ev = 0;
+    const std::vector<int32_t> r = ph::tt_far_ranks(*t->p, *opts, &ev);
+    std::copy(r.begin(), r.end(), ranks);
+    if (kernel_evals) *kernel_evals = ev;
+  });
+}
+
 int ph_model_format(const ph_model* m, int* format) {
   return guarded([&] {
     need(m && m->p && format, "NULL argument");

@@ -119,6 +119,11 @@ enum class Compress { HOSVD, TT };
 std::shared_ptr<HostModel> offline_host(const TreeData& t, const ph_offline_opts& o, bool gpu = false,
                                         Compress comp = Compress::HOSVD);
 
+// TT ranks r_0 .. r_N of every translation class's far tensor after TT-cross + TT-rounding
+// (n_classes x (N + 1), N = 2 d + d_theta; mirrored classes in reverse order), without building
+// a model; P up to 4096 and p_theta up to 64.  evals_out: distinct kernel values evaluated.
+std::vector<int32_t> tt_far_ranks(const TreeData& t, const ph_offline_opts& o, int64_t* evals_out);
+
 // ---- dense linear algebra of the offline stage (offline.cpp), column-major
 // Householder QR of the m x k matrix A (m >= k) in place: R in the upper triangle, the
 // reflectors below it (unit leading entry implied) with scalars tau

@@ -40,6 +40,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <unordered_map>
 
 #include "ph_host.hpp"
 
@@ -83,14 +84,18 @@ double dot(const std::vector<double>& a, const std::vector<double>& b) {
   return s;
 }
 
-// The tensor seen through its accessor, every entry evaluated at most once.
+// The tensor seen through its accessor, every entry evaluated at most once: a dense cache for
+// tensors up to DENSE_MAX entries, a hash map beyond (the cross touches a small part of those).
+constexpr int64_t DENSE_MAX = (int64_t)1 << 24;
 struct Tensor {
   EntryFn fn;
   const void* ctx;
   std::vector<int> dims;
   std::vector<int64_t> stride;
+  bool dense;
   std::vector<double> val;
   std::vector<char> have;
+  std::unordered_map<int64_t, double> sparse;
   int64_t evals = 0;
   Tensor(EntryFn f, const void* c, const std::vector<int>& d) : fn(f), ctx(c), dims(d) {
     int64_t s = 1;
@@ -98,8 +103,11 @@ struct Tensor {
       stride.push_back(s);
       s *= m;
     }
-    val.assign((size_t)s, 0.0);
-    have.assign((size_t)s, 0);
+    dense = s <= DENSE_MAX;
+    if (dense) {
+      val.assign((size_t)s, 0.0);
+      have.assign((size_t)s, 0);
+    }
   }
   int N() const { return (int)dims.size(); }
   // out[s] = X[idx row s], idx count x N row-major
@@ -109,12 +117,15 @@ struct Tensor {
     std::vector<int64_t> lin((size_t)count);
     std::vector<int32_t> miss;
     std::vector<int64_t> miss_lin;
+    std::unordered_map<int64_t, int> queued;   // sparse mode: entries queued in this call
     for (int64_t s = 0; s < count; ++s) {
       int64_t l = 0;
       for (int k = 0; k < n; ++k) l += stride[k] * idx[(size_t)s * n + k];
       lin[s] = l;
-      if (!have[l]) {
-        have[l] = 2;   // queued
+      const bool known = dense ? have[l] != 0 : (sparse.count(l) != 0 || queued.count(l) != 0);
+      if (!known) {
+        if (dense) have[l] = 2;   // queued
+        else queued.emplace(l, 0);
         miss.insert(miss.end(), idx.begin() + s * n, idx.begin() + (s + 1) * n);
         miss_lin.push_back(l);
       }
@@ -123,12 +134,16 @@ struct Tensor {
       std::vector<double> v(miss_lin.size());
       fn(ctx, miss.data(), (int64_t)miss_lin.size(), v.data());
       for (size_t q = 0; q < miss_lin.size(); ++q) {
-        val[miss_lin[q]] = v[q];
-        have[miss_lin[q]] = 1;
+        if (dense) {
+          val[miss_lin[q]] = v[q];
+          have[miss_lin[q]] = 1;
+        } else {
+          sparse.emplace(miss_lin[q], v[q]);
+        }
       }
       evals += (int64_t)miss_lin.size();
     }
-    for (int64_t s = 0; s < count; ++s) out[s] = val[lin[s]];
+    for (int64_t s = 0; s < count; ++s) out[s] = dense ? val[lin[s]] : sparse.find(lin[s])->second;
   }
 };
 

@@ -264,3 +264,31 @@ def test_bench_refuses_more_than_one_gpu():
     assert res.returncode != 0
     msg = json.loads(res.stdout.strip().splitlines()[-1])["error"]
     assert "single GPU" in msg
+
+
+@pytest.mark.parametrize("kernel,d,lo,hi,p_s,p_theta,tol", [
+    ("gaussian", 2, [0.05], [0.5], 5, 7, 1e-8),
+    ("matern32", 3, [0.1], [0.6], 4, 5, 1e-6),
+    ("matern", 2, [0.25, 0.5], [1.0, 3.0], 4, 5, 1e-6),
+])
+def test_tt_far_ranks_match_oracle(kernel, d, lo, hi, p_s, p_theta, tol):
+    """ph_tt_far_ranks (host only, no GPU): the TT ranks of every translation class's far tensor
+    and the number of kernel values evaluated equal those of the oracle's TT-cross on the same
+    tensors (same pivots; mirrored classes reversed)."""
+    from fractions import Fraction
+    from oracle import hmat, kernels
+    n, l_max, eta2 = (900, 3, (2, 1)) if d == 2 else (1200, 2, (3, 1))
+    X = np.random.default_rng([21, d]).random((n, d))
+    t = api.Tree(X, l_max=l_max, eta2=eta2)
+    ranks, ev = api.tt_far_ranks(t, kernel, lo, hi, p_s=p_s, p_theta=p_theta, tol=tol)
+    om = hmat.PH2(X, l_max=l_max, eta2=Fraction(*eta2), kernel=kernels.KERNELS[kernel][0], theta_lo=lo,
+                  theta_hi=hi, p_s=p_s, p_theta=p_theta, tol=tol, compress="tt")
+    assert ranks.shape == (len(om.classes), 2 * d + len(lo) + 1)
+    for key in range(len(om.classes)):
+        mk = om._mirror_key(key)
+        cores = om.far_tt_cores(mk if mk is not None else key)
+        r = [c.shape[0] for c in cores] + [1]
+        if mk is not None:
+            r = r[::-1]
+        assert list(ranks[key]) == r, f"class {key} {om.classes[key]}"
+    assert ev == om.tt_evals
