@@ -185,6 +185,25 @@ def test_polynomial_kernel_against_dense_product():
         _close(y.cpu().numpy().T, K @ x, 1e-11)
 
 
+@pytest.mark.parametrize("coupling", ["materialized", "implicit"])
+def test_tt_polynomial_kernel_against_dense_product(coupling):
+    """TT-compressed models of an exactly interpolated kernel (degree 2 in x, y and theta, so every
+    tensor has exact low TT ranks): the GPU MVM with formed and with implicit couplings equals the
+    textbook dense K(theta) x (independent of which pivots the cross takes), three slots."""
+    torch = _torch()
+    from paper_2511_03109_amd import api
+    X = inputs.points_for(1, 1200)
+    lt = api.Tree(X, l_max=3, eta2=(2, 1))
+    lm = api.Model(lt, "poly_test", [0.1], [0.9], p_s=3, p_theta=3, tol=1e-12, compress="tt", coupling=coupling)
+    assert lm.format == ("h2_implicit" if coupling == "implicit" else "h2")
+    thetas = [0.1, 0.45, 0.9]
+    x = inputs.normal_vectors(1200, 3 * 2, 3).T.reshape(3, 2, 1200)
+    y = api.Instance(lm, thetas).matvec(torch.tensor(np.ascontiguousarray(x), device="cuda")).cpu().numpy()
+    for t, th in enumerate(thetas):
+        K = kernels.poly_test(X[:, None, :], X[None, :, :], [th])
+        _close(y[t].T, K @ x[t].T, 1e-11, what=f"TT {coupling} polynomial kernel theta {th}")
+
+
 @pytest.mark.parametrize("p_theta", [7, 11])
 def test_untruncated_benchmark_geometry(p_theta):
     """tol = 0 (nothing truncated): the kernels against the oracle independently of how well
