@@ -75,8 +75,12 @@ __global__ void __launch_bounds__(NT, 2) k_h_proj(const double* __restrict__ xt,
   const int tn = min(HTB, T - t0);
   const int r0 = tile * RC;
   const int rc = (int)min<int64_t>(RC, Rs - r0);
-  const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+  const int lane = threadIdx.x % WAVE, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const double* T_ = hT + b.T_off;
+  // row tiles that hold a row below the rank (rows beyond it stay zero): with ranks up to 64
+  // every wave keeps one tile and skips the other
+  const bool zt[2] = {wave * 16 < b.rt, (wave + 4) * 16 < b.rt};
+  const bool wt[2] = {wave * 16 < b.rs, (wave + 4) * 16 < b.rs};
   MF::acc_t acc[HTB][2];
 #pragma unroll
   for (int s = 0; s < HTB; ++s)
@@ -100,12 +104,14 @@ __global__ void __launch_bounds__(NT, 2) k_h_proj(const double* __restrict__ xt,
       const int k = kk + (lane >> 4);
       MF::a_t av[2];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) av[j] = MF::load_tiled(&As[(wave + 4 * j) * 256 + k * 16], lane);
+      for (int j = 0; j < 2; ++j)
+        if (zt[j]) av[j] = MF::load_tiled(&As[(wave + 4 * j) * 256 + k * 16], lane);
 #pragma unroll
       for (int s = 0; s < HTB; ++s) {
         const double bv = Bs[s][k * 16 + (lane & 15)];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[s][j] = MF::mac(av[j], bv, acc[s][j]);
+        for (int j = 0; j < 2; ++j)
+          if (zt[j]) acc[s][j] = MF::mac(av[j], bv, acc[s][j]);
       }
     }
   }
@@ -138,6 +144,7 @@ __global__ void __launch_bounds__(NT, 2) k_h_proj(const double* __restrict__ xt,
         const double bv = Bz[(a0 + k) * 16 + (lane & 15)];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
+          if (!wt[j]) continue;   // rows of w beyond rs are not stored
           const MF::a_t av = MF::load_tiled(&As[(wave + 4 * j) * 256 + k * 16], lane);
           w2[j] = MF::mac(av, bv, w2[j]);
         }
@@ -179,9 +186,11 @@ __global__ void __launch_bounds__(NT, 2) k_h_apply(double* __restrict__ yt, cons
   const int tn = min(HTB, T - t0);
   const int r0 = tile * RC;
   const int rc = (int)min<int64_t>(RC, Rs - r0);
-  const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+  const int lane = threadIdx.x % WAVE, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int64_t lb = nbegin[leaf], ln = nend[leaf] - lb;
   const int cn = (int)min<int64_t>(CH, ln - cstart);
+  // row tiles that hold a row of the chunk (with chunks of up to 64 rows every wave keeps one)
+  const bool rt_[2] = {wave * 16 < cn, (wave + 4) * 16 < cn};
   MF::acc_t acc[HTB][2];
 #pragma unroll
   for (int s = 0; s < HTB; ++s)
@@ -209,12 +218,14 @@ __global__ void __launch_bounds__(NT, 2) k_h_apply(double* __restrict__ yt, cons
         const int k = kk + (lane >> 4);
         MF::a_t av[2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) av[j] = MF::load_tiled(&As[(wave + 4 * j) * 256 + k * 16], lane);
+        for (int j = 0; j < 2; ++j)
+          if (rt_[j]) av[j] = MF::load_tiled(&As[(wave + 4 * j) * 256 + k * 16], lane);
 #pragma unroll
         for (int s = 0; s < HTB; ++s) {
           const double bv = Bs[s][k * 16 + (lane & 15)];
 #pragma unroll
-          for (int j = 0; j < 2; ++j) acc[s][j] = MF::mac(av[j], bv, acc[s][j]);
+          for (int j = 0; j < 2; ++j)
+            if (rt_[j]) acc[s][j] = MF::mac(av[j], bv, acc[s][j]);
         }
       }
     }
