@@ -86,19 +86,43 @@ __global__ void __launch_bounds__(NT, 2) k_h_proj(const double* __restrict__ xt,
   for (int s = 0; s < HTB; ++s)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[s][j] = (MF::acc_t){0, 0, 0, 0};
-  // phase 1: z_t = T_b^T x_t, 16 rows of T_b per step
+  // phase 1: z_t = T_b^T x_t, 16 rows of T_b per step.  The next step's T_b and x values are
+  // loaded into registers while the current step is multiplied.  Every load is unconditional
+  // (T_b: raw buffer loads, zeros at an out-of-range offset; x: clamped addresses), so the
+  // wait for them falls at the next step's LDS stores.  Thread tid holds T_b entry (row i0 + tid % 16, rank
+  // tid / 16 + 16 p) and x entry (point i0 + tid / 16, column tid % 16) of slot t0 + p.
+  // T_b is read through a raw buffer view (below 2 GiB, checked on the host).
+  static_assert(NT == 256 && HTB == 8, "staging map: 8 values of T_b and of x per thread");
+  const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)T_, (short)0, (int)((int64_t)b.ldt * b.rt * (int64_t)sizeof(double)), BUF_WORD3);
+  const int kT = threadIdx.x % 16, aT = threadIdx.x / 16;   // T_b: row in the step, rank mod 16
+  const int kX = threadIdx.x / 16, cX = threadIdx.x % 16;   // x: point in the step, column
+  double pa[8], pb[HTB];
+  auto stage_load = [&](int64_t i0) {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int a = aT + 16 * p;
+      const bool ok = a < b.rt && i0 + kT < b.nt;
+      pa[p] = bload1<double>(trs, ok ? (int)((i0 + kT + (int64_t)b.ldt * a) * (int64_t)sizeof(double)) : BUF_OOB);
+    }
+    // x: a plain load from a clamped, valid address; entries outside the block, the tile or
+    // the slots are zeroed when stored (xok below), so the load itself is unconditional
+#pragma unroll
+    for (int p = 0; p < HTB; ++p) {
+      const int64_t tp = t0 + min(p, tn - 1), ip = min<int64_t>(i0 + kX, b.nt - 1);
+      pb[p] = xt[(tp * n + b.t_begin + ip) * Rs + r0 + min(cX, rc - 1)];
+    }
+  };
+  auto xok = [&](int64_t i0, int p) { return p < tn && i0 + kX < b.nt && cX < rc; };
+  if (b.nt > 0) stage_load(0);   // (an empty source cluster has no step and no load)
   for (int64_t i0 = 0; i0 < b.nt; i0 += 16) {
     __syncthreads();
-    for (int q = threadIdx.x; q < 128 * 16; q += NT) {
-      const int kk = q % 16, a = q / 16;
-      As[panel_index(a, kk)] = (a < b.rt && i0 + kk < b.nt) ? T_[i0 + kk + (int64_t)b.ldt * a] : 0.0;
-    }
-    for (int q = threadIdx.x; q < HTB * 256; q += NT) {
-      const int ts = q / 256, kk = (q / 16) % 16, cc = q % 16;
-      Bs[ts][kk * 16 + cc] = (ts < tn && i0 + kk < b.nt && cc < rc)
-                                 ? xt[((int64_t)(t0 + ts) * n + b.t_begin + i0 + kk) * Rs + r0 + cc] : 0.0;
-    }
+#pragma unroll
+    for (int p = 0; p < 8; ++p) As[panel_index(aT + 16 * p, kT)] = pa[p];
+#pragma unroll
+    for (int p = 0; p < HTB; ++p) Bs[p][threadIdx.x] = xok(i0, p) ? pb[p] : 0.0;
     __syncthreads();
+    stage_load(i0 + 16);   // past the last step: T_b offsets out of range, x clamped (unused)
 #pragma unroll
     for (int kk = 0; kk < 16; kk += 4) {
       const int k = kk + (lane >> 4);
@@ -257,12 +281,18 @@ void h_core_launch(const InstData& in, hipStream_t st) {
          (double*)in.C.p, m.h_tot, m.p_theta, m.d_theta);
 }
 
+// The projection reads T_b through a raw buffer view of 32-bit range.
+static void h_buffer_check(const DeviceModel& m) {
+  if (m.h_tbytes_max > BUF_MAX_BYTES) fail(PH_EUNSUPPORTED, "ph_matvec: a far block's T_b exceeds 2 GiB");
+}
+
 void h_far_launch(const InstData& in, const double* xt, double* yt, double* W, int64_t Rs, int64_t nrc,
                   hipStream_t st, int phase) {
   const DeviceModel& m = *in.m;
   if (m.n_hblk == 0) return;
   if (in.T > 65535 || nrc > 65535) fail(PH_EUNSUPPORTED, "ph_matvec: too many parameter slots or RHS tiles");
   const unsigned nb = (unsigned)((in.T + HTB - 1) / HTB);
+  h_buffer_check(m);
   if (phase == 0)
     launch(PH_STAGE_COUPLING, k_h_proj, dim3((unsigned)m.n_hblk, (unsigned)nrc, nb), dim3(NT), st, xt, W,
            (const HBlkDev*)m.hblk.p, (const double*)m.hT.p, (const double*)in.C.p, m.h_tot, m.hw_tot, m.n, Rs,
@@ -283,6 +313,7 @@ void implicit_coupling_launch(const InstData& in, const double* xh, double* yh, 
   const DeviceModel& m = *in.m;
   if (in.T > 65535 || nrc > 65535) fail(PH_EUNSUPPORTED, "ph_matvec: too many parameter slots or RHS tiles");
   const unsigned nb = (unsigned)((in.T + HTB - 1) / HTB);
+  h_buffer_check(m);
   const int64_t rows = m.n_nodes * m.Pp;
   if (m.n_hblk > 0)
     launch(PH_STAGE_COUPLING, k_h_proj, dim3((unsigned)m.n_hblk, (unsigned)nrc, nb), dim3(NT), st, xh, W,

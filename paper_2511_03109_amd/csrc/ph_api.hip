@@ -50,6 +50,7 @@ static void upload_hmatrix(DeviceModel& m, const TreeData& t, const HostModel& h
     hb[b] = HBlkDev{h.s_begin, h.t_begin, h.S_off, h.T_off, hc[h.q].h_off, woff,
                     (int32_t)h.ns, (int32_t)h.nt, h.rs, h.rt, h.lds, h.ldt, h.tr, h.q};
     woff += (int64_t)h.rs * 16;
+    m.h_tbytes_max = std::max(m.h_tbytes_max, (int64_t)h.ldt * h.rt * (int64_t)sizeof(double));
     by_target[h.s].push_back((int32_t)b);
   }
   m.hw_tot = woff;
@@ -115,6 +116,7 @@ static void upload_implicit(DeviceModel& m, const TreeData& t, const HostModel& 
     h.tr = tr;
     h.q = q;
     woff += (int64_t)h.rs * 16;
+    m.h_tbytes_max = std::max(m.h_tbytes_max, (int64_t)h.ldt * h.rt * (int64_t)sizeof(double));
     by_target[s].push_back((int32_t)hb.size());
     hb.push_back(h);
   }

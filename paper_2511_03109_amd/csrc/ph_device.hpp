@@ -212,6 +212,7 @@ struct DeviceModel {
   // holds w_b = H_b T_b^T x_t (hw_tot entries per slot and 16-column RHS tile)
   int format = PH_FORMAT_H2;
   int64_t n_hblk = 0, n_hcls = 0, h_tot = 0, hw_tot = 0;
+  int64_t h_tbytes_max = 0;   // bytes of the largest T_b of a far block
   DevArr<HBlkDev> hblk;
   DevArr<HClsDev> hcls;
   DevArr<double> hcore, hS, hT;
