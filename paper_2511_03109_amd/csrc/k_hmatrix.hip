@@ -220,23 +220,54 @@ __global__ void __launch_bounds__(NT, 2) k_h_apply(double* __restrict__ yt, cons
   for (int s = 0; s < HTB; ++s)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[s][j] = (MF::acc_t){0, 0, 0, 0};
-  for (int e = leaf_ptr[li]; e < leaf_ptr[li + 1]; ++e) {
-    const HBlkDev b = blks[leaf_blk[e]];
+  // The steps (block e of the chunk's list, 16 columns a0 of S_b) run as one sequence, and the
+  // next step's S_b and w values are loaded into registers while the current one is
+  // multiplied.  Thread tid holds S_b entry (chunk row tid % 128, column a0 + tid / 128 + 2 p)
+  // and w entry (row a0 + tid / 16, column tid % 16) of slot t0 + p.  The loads use clamped,
+  // valid addresses and are masked when stored, so they are unconditional and the wait for
+  // them falls at the next step's LDS stores; blocks of rank 0 have no step.
+  static_assert(NT == 256 && HTB == 8 && CH == 128, "staging map: 8 values of S_b and of w per thread");
+  const int rS = threadIdx.x % CH, kS = threadIdx.x / CH;   // S_b: chunk row, column mod 2
+  const int kW = threadIdx.x / 16, cW = threadIdx.x % 16;   // w: row in the step, column
+  const int e1 = leaf_ptr[li + 1];
+  auto seek = [&](int e, HBlkDev& bb) {   // first block at or after e with a step
+    for (; e < e1; ++e) {
+      bb = blks[leaf_blk[e]];
+      if (bb.rs > 0) break;
+    }
+    return e;
+  };
+  double pa[8], pb[HTB];
+  auto stage_load = [&](const HBlkDev& bb, int a0) {
     // rows of the chunk relative to the block's target cluster
-    const double* S = hS + b.S_off + (lb + cstart - b.s_begin);
-    for (int a0 = 0; a0 < b.rs; a0 += 16) {
+    const double* S = hS + bb.S_off + (lb + cstart - bb.s_begin) + min(rS, cn - 1);
+#pragma unroll
+    for (int p = 0; p < 8; ++p) pa[p] = S[(int64_t)bb.lds * min(a0 + kS + 2 * p, bb.rs - 1)];
+#pragma unroll
+    for (int p = 0; p < HTB; ++p)
+      pb[p] = W[((int64_t)(t0 + min(p, tn - 1)) * nrc + tile) * hw_tot + bb.w_off + min(a0 + kW, bb.rs - 1) * 16 + cW];
+  };
+  HBlkDev b{};
+  int e = cn > 0 ? seek(leaf_ptr[li], b) : e1, a0 = 0;
+  if (e < e1) stage_load(b, 0);
+  while (e < e1) {
+    // the step after (e, a0); past the last one the current step's addresses are re-read
+    HBlkDev bn = b;
+    int en = e, an = a0 + 16;
+    if (an >= b.rs) {
+      an = 0;
+      en = seek(e + 1, bn);
+    }
+    {
       __syncthreads();
-      for (int q = threadIdx.x; q < CH * 16; q += NT) {
-        const int r = q % CH, kk = q / CH;
-        As[panel_index(r, kk)] = (r < cn && a0 + kk < b.rs) ? S[r + (int64_t)b.lds * (a0 + kk)] : 0.0;
-      }
-      for (int q = threadIdx.x; q < HTB * 256; q += NT) {
-        const int ts = q / 256, kk = (q / 16) % 16, cc = q % 16;
-        Bs[ts][kk * 16 + cc] = (ts < tn && a0 + kk < b.rs)
-                                   ? W[((int64_t)(t0 + ts) * nrc + tile) * hw_tot + b.w_off + (a0 + kk) * 16 + cc]
-                                   : 0.0;
-      }
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+        As[panel_index(rS, kS + 2 * p)] = rS < cn && a0 + kS + 2 * p < b.rs ? pa[p] : 0.0;
+#pragma unroll
+      for (int p = 0; p < HTB; ++p) Bs[p][threadIdx.x] = p < tn && a0 + kW < b.rs ? pb[p] : 0.0;
       __syncthreads();
+      if (en < e1) stage_load(bn, an);
+      else stage_load(b, a0);
 #pragma unroll
       for (int kk = 0; kk < 16; kk += 4) {
         const int k = kk + (lane >> 4);
@@ -253,6 +284,9 @@ __global__ void __launch_bounds__(NT, 2) k_h_apply(double* __restrict__ yt, cons
         }
       }
     }
+    e = en;
+    a0 = an;
+    b = bn;
   }
   const int c = lane & 15;
   if (c >= rc) return;
