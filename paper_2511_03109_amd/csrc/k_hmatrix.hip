@@ -139,7 +139,26 @@ __global__ void __launch_bounds__(NT, 2) k_h_proj(const double* __restrict__ xt,
       }
     }
   }
-  // phase 2, slot by slot: w_t = H' z_t (rows of H' beyond rs and columns beyond rt are zero)
+  // phase 2, slot by slot: w_t = H' z_t (rows of H' beyond rs and columns beyond rt are zero).
+  // The steps (slot, 16 columns a0 of H') run as one sequence with the next step's H' values
+  // prefetched into registers as in phase 1 (clamped addresses, masked when stored).  Thread
+  // tid holds entry (row ap, column a0 + kk) of H' for p < 8: H' = H^T (tr), H[a + rt ap]
+  // with a contiguous: kk = tid % 16, ap = tid / 16 + 16 p; H' = H, H[ap + rs a] with ap
+  // contiguous: ap = tid % 128, kk = tid / 128 + 2 p.  A block of rank 0 on either side has
+  // no step (its w is zero).
+  const bool hsteps = b.rs > 0 && b.rt > 0;
+  auto h_ap = [&](int p) { return b.tr ? (int)threadIdx.x / 16 + 16 * p : (int)threadIdx.x % 128; };
+  auto h_kk = [&](int p) { return b.tr ? (int)threadIdx.x % 16 : (int)threadIdx.x / 128 + 2 * p; };
+  double ph[8];
+  auto h_load = [&](int s, int a0) {
+    const double* H = Hc + (int64_t)(t0 + s) * h_tot + b.h_off;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int ap = min(h_ap(p), b.rs - 1), a = min(a0 + h_kk(p), b.rt - 1);
+      ph[p] = b.tr ? H[a + (int64_t)b.rt * ap] : H[ap + (int64_t)b.rs * a];
+    }
+  };
+  if (hsteps) h_load(0, 0);
 #pragma unroll
   for (int s = 0; s < HTB; ++s) {
     if (s >= tn) break;
@@ -149,19 +168,23 @@ __global__ void __launch_bounds__(NT, 2) k_h_proj(const double* __restrict__ xt,
 #pragma unroll
       for (int q = 0; q < 4; ++q) Bz[((wave + 4 * j) * 16 + MF::row(lane, q)) * 16 + (lane & 15)] = acc[s][j][q];
     const int64_t slot = t0 + s;
-    const double* H = Hc + slot * h_tot + b.h_off;
     MF::acc_t w2[2] = {(MF::acc_t){0, 0, 0, 0}, (MF::acc_t){0, 0, 0, 0}};
-    for (int a0 = 0; a0 < b.rt; a0 += 16) {
-      __syncthreads();
-      for (int q = threadIdx.x; q < 128 * 16; q += NT) {
-        int ap, kk;
-        if (b.tr) { kk = q % 16; ap = q / 16; }   // H' = H^T: H[a + rt ap], a contiguous
-        else { ap = q % 128; kk = q / 128; }       // H' = H: H[ap + rs a], ap contiguous
-        const int a = a0 + kk;
-        As[panel_index(ap, kk)] =
-            (ap < b.rs && a < b.rt) ? (b.tr ? H[a + (int64_t)b.rt * ap] : H[ap + (int64_t)b.rs * a]) : 0.0;
+    for (int a0 = 0; hsteps && a0 < b.rt; a0 += 16) {
+      // the step after (s, a0); past the last one the current step's addresses are re-read
+      int sn = s, an = a0 + 16;
+      if (an >= b.rt) {
+        an = 0;
+        sn = s + 1;
       }
       __syncthreads();
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const int ap = h_ap(p), kk = h_kk(p);
+        As[panel_index(ap, kk)] = ap < b.rs && a0 + kk < b.rt ? ph[p] : 0.0;
+      }
+      __syncthreads();
+      if (sn < tn) h_load(sn, an);
+      else h_load(s, a0);
 #pragma unroll
       for (int kk = 0; kk < 16; kk += 4) {
         const int k = kk + (lane >> 4);
