@@ -174,7 +174,8 @@ def _timed(fn, steps, warmup):
 def step_legs(model, thetas, x_host, T, R, y64, args):
     """The same work in other forms, each timed like the headline (events around K steps
     after W warm-up steps): FP64 one theta at a time (T = 1 instances, near blocks in
-    memory), FP64 batched with the near blocks in memory, FP32 and BF16 batched.  Each
+    memory), FP64 batched with the near blocks in memory, FP64 batched after ph_autotune (which
+    may run the near field concurrently with the far field), FP32 and BF16 batched.  Each
     low-precision result's relative error is taken against the FP64 headline output y64
     (which matches the oracle to 1e-12)."""
     import torch
@@ -213,6 +214,16 @@ def step_legs(model, thetas, x_host, T, R, y64, args):
     legs["fp64_batched_blocks_in_memory"] = {"ms_per_theta": ms / T, "T": T,
                                              "rel_error_vs_headline": float((yb - y64).norm() / y64.norm())}
     del ib, yb
+    torch.cuda.empty_cache()
+    # the headline step after ph_autotune on the same instance shape: coupling chunks, prefetch
+    # depth, near field on the instance's second stream or not, near-field launch shape
+    ia = api.Instance(model, thetas)
+    ya = torch.empty_like(x64)
+    cfg = ia.autotune(x64, ya)
+    ms = timed(lambda: (ia.reinstantiate(thetas), ia.matvec(x64, ya)))
+    legs["fp64_autotuned"] = {"ms_per_theta": ms / T, "T": T, "config": cfg,
+                              "rel_error_vs_headline": float((ya - y64).norm() / y64.norm())}
+    del ia, ya
     torch.cuda.empty_cache()
     x32 = x64.float()
     for dt in ("f32", "bf16"):
